@@ -1,0 +1,165 @@
+/*
+ * vie.h -- C ABI of the MI355X voxel J-VIE solver.
+ *
+ * The library solves the discrete J-VIE of the paper (Section III, boxed J-VIE;
+ * discrete form in Section III-A and again in Section V-D):
+ *
+ *     (I - M_eps N) w = b,       b = M_eps e_inc  (the constant c_e is dropped)
+ *
+ * on a uniform grid of n1 x n2 x n3 cubic voxels of edge h.  N is the Galerkin
+ * matrix of curl curl S for normalised voxel indicators (Section III-A); it is
+ * block Toeplitz with six unique symmetric tensor components, and its product
+ * with a vector is done by circulant embedding and FFTs (Section III-A, last
+ * paragraph; Section V-D).  M_eps is diagonal with (eps_r - 1)/eps_r per voxel,
+ * eps_r = eps/eps_b (Section III; background scaled to one as in Section II).
+ * Absorbers (Section IV) enter only through eps.
+ *
+ * Conventions
+ *   - Time dependence exp(-i omega t): the kernel is e^{+i k_b R}/(4 pi R) with
+ *     k_b = k0 sqrt(eps_b), and passive media have Im eps >= 0.  This is the
+ *     complex conjugate of the paper's exp(+j omega t) system; all real
+ *     observables agree.
+ *   - Vectors are complex, interleaved (re, im), component-major
+ *     [3][n1][n2][n3] in C order (n3 fastest), i.e. a contiguous tensor of
+ *     shape (3, n1, n2, n3).  Per-voxel arrays are [n1][n2][n3].
+ *   - "device" pointers are HIP device memory on the plan's device; the caller
+ *     owns every buffer it passes, the library never keeps caller pointers.
+ *   - Every call is ordered on the plan's HIP stream.  vie_matvec* and
+ *     vie_set_contrast return without synchronising; vie_solve* synchronise.
+ *   - Errors: every int-returning call returns VIE_OK or a negative code; no
+ *     exception or abort crosses the ABI.  vie_last_error() gives the message.
+ *
+ * Size limits of this version: n1, n2 <= 32 and n3 <= 2048 (circulant lengths
+ * up to 64, 64 and 4096); each circulant length is the power of two
+ * >= 2 n_d - 1.
+ */
+#ifndef VIE_H
+#define VIE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vie_plan_s* vie_plan_t;            /* opaque; owned by the library until vie_destroy */
+typedef struct { double re, im; } vie_c128;       /* interleaved FP64 complex */
+typedef struct { float re, im; } vie_c64;         /* interleaved FP32 complex */
+
+enum {
+  VIE_OK = 0,
+  VIE_EINVAL = -1,    /* bad argument: size, pointer, non-finite value */
+  VIE_ENOMEM = -2,    /* device or host allocation failed */
+  VIE_EDEVICE = -3,   /* HIP runtime error */
+  VIE_ENOCONV = -4,   /* solver stopped before reaching tol; x holds the best iterate */
+  VIE_ENUMERIC = -5,  /* non-finite value met during a solve */
+  VIE_ESTATE = -6,    /* call out of order (e.g. matvec before set_contrast) */
+  VIE_ENOTIMPL = -7
+};
+
+/* plan flags */
+enum {
+  VIE_FP64 = 0,        /* FP64 spectrum only */
+  VIE_WITH_FP32 = 1    /* also keep FP32 copies of spectrum and contrast (mixed tier) */
+};
+
+/*
+ * vie_green_table -- host-only, FP64.  Galerkin entries N^{ab}(m) of curl curl S
+ * for normalised voxel indicators (Section III-A), for all non-negative offsets
+ * 0 <= m_d < grid[d], dimensionless with voxel edge 1 and kappa = k_b h.
+ * out: host array of 6*grid[0]*grid[1]*grid[2] vie_c128, layout
+ *      [6][n1][n2][n3], components in the order xx, xy, xz, yy, yz, zz.
+ * Entries for negative offsets follow by parity: negating m_d multiplies
+ * N^{ab} by -1 exactly when one of a, b equals d.
+ * nthreads <= 0 picks the hardware concurrency.
+ */
+int vie_green_table(const int grid[3], double kappa, vie_c128* out, int nthreads);
+
+/*
+ * vie_plan -- build the operator for a grid (Section III-A): the Toeplitz table
+ * on the host (FP64, threaded), its circulant embedding and 3-D spectrum on the
+ * device.  h and k0 in one consistent length unit; eps_b > 0 the background
+ * relative permittivity.  hip_stream: a hipStream_t (NULL = default stream).
+ * Returns VIE_EINVAL for sizes outside the limits above or non-positive h, k0, eps_b.
+ */
+int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps_b,
+             unsigned flags, void* hip_stream);
+
+/*
+ * vie_set_contrast -- M_eps from the relative permittivity per voxel
+ * (Section III: multiplier (eps_r - 1)/eps_r; Section III-A: constant per voxel).
+ * eps: device pointer, N = n1 n2 n3 values [n1][n2][n3], copied.  A voxel equal
+ * to eps_b has zero contrast.  Non-finite or zero eps gives VIE_EINVAL.
+ */
+int vie_set_contrast(vie_plan_t plan, const vie_c128* eps);
+
+/*
+ * vie_rhs -- b = h^{3/2} M_eps e_inc: the Galerkin projection of an incident field
+ * sampled at voxel centres, times the contrast (Section III-A right-hand side).
+ * e_inc, b: device, 3N values each; may alias.
+ */
+int vie_rhs(vie_plan_t plan, const vie_c128* e_inc, vie_c128* b);
+
+/*
+ * vie_matvec -- y = (I - M_eps N) x in FP64 (Section V-D matrix-vector product).
+ * x, y: device, 3N values, must not overlap.  Asynchronous on the plan's stream.
+ */
+int vie_matvec(vie_plan_t plan, const vie_c128* x, vie_c128* y);
+
+/*
+ * vie_matvec_c64 -- the same product with FP32 spectrum, contrast and FFTs
+ * (plan built with VIE_WITH_FP32).  x, y: device, 3N vie_c64, no overlap.
+ */
+int vie_matvec_c64(vie_plan_t plan, const vie_c64* x, vie_c64* y);
+
+/*
+ * vie_residual -- r = b - (I - M_eps N) x in FP64.  x, b, r device, 3N values;
+ * r may alias b but not x.
+ */
+int vie_residual(vie_plan_t plan, const vie_c128* x, const vie_c128* b, vie_c128* r);
+
+typedef struct {
+  int restart;        /* Krylov dimension m of GMRES(m) / outer FGMRES(m); <= 0 -> 50 */
+  int maxit;          /* total outer iterations; <= 0 -> 10000 */
+  int use_x0;         /* 1: x holds the initial guess; 0: start from zero */
+  int precision;      /* 0: FP64 GMRES; 1: mixed (FP32 inner GMRES, FP64 outer FGMRES) */
+  int inner_restart;  /* mixed tier: inner GMRES dimension; <= 0 -> 20 */
+  double inner_tol;   /* mixed tier: inner relative tolerance; <= 0 -> 1e-4 */
+} vie_solve_opts;
+
+typedef struct {
+  int iters;          /* outer Arnoldi steps */
+  int inner_iters;    /* FP32 matvecs spent in inner solves (mixed tier) */
+  int restarts;
+  int matvecs;        /* FP64 matvecs (incl. residual checks) */
+  int status;         /* same code as returned */
+  double rel_res_true;   /* ||b - A x|| / ||b|| with the FP64 matvec */
+  double rel_res_est;    /* last Hessenberg estimate */
+  double seconds;        /* wall time of the call */
+} vie_solve_info;
+
+/*
+ * vie_solve -- GMRES(m) with classical Gram-Schmidt applied twice (Section V-D
+ * solves with GMRES to 1e-8).  Stops when the relative residual estimate and then
+ * the true FP64 relative residual ||b - A x||/||b|| are <= tol.
+ * b, x: device, 3N values (x in/out).  opts, info: host, may be NULL (defaults /
+ * no report).  Returns VIE_OK, or VIE_ENOCONV with the best iterate in x.
+ * The Krylov basis (restart + 1 vectors of 3N FP64 complex) is allocated per call.
+ */
+int vie_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol,
+              const vie_solve_opts* opts, vie_solve_info* info);
+
+/* Message for the last failing call on this plan (plan = NULL: on this thread). */
+const char* vie_last_error(vie_plan_t plan);
+
+/* Release every device and host resource of the plan.  NULL is a no-op. */
+void vie_destroy(vie_plan_t plan);
+
+/* Library version string. */
+const char* vie_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIE_H */

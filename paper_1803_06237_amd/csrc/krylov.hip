@@ -1,0 +1,359 @@
+// GMRES(m) and flexible GMRES(m) on the device (Section V-D: the discrete J-VIE
+// is solved by GMRES with matrix-vector products only).
+//
+// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): two sweeps of a fused
+// multi-dot h = V^H w over all basis vectors followed by a multi-axpy
+// w -= V h.  The Hessenberg matrix is kept in upper-triangular form with complex
+// Givens rotations by one device thread; the host reads only the residual
+// estimate |g_{j+1}| / ||b|| after each step.  Reductions are two-stage and in
+// a fixed order, so results are bitwise reproducible run to run.  All
+// reductions and Hessenberg data are FP64; basis vectors are FP64 (cx<double>)
+// or FP32 (cx<float>, the inner solve of the mixed tier).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "fft_device.hpp"
+#include "krylov.hpp"
+
+namespace vie {
+
+constexpr int kThreads = 256;
+constexpr int kEPT = 8;                     // elements per thread held in registers
+constexpr int kChunk = kThreads * kEPT;     // elements per block
+constexpr int kGroup = 4;                   // basis vectors reduced together
+
+__device__ __forceinline__ double2 to_d(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d(float2 v) { return double2{(double)v.x, (double)v.y}; }
+template <typename V> __device__ __forceinline__ V from_d(double2 v);
+template <> __device__ __forceinline__ double2 from_d<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 from_d<float2>(double2 v) { return float2{(float)v.x, (float)v.y}; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of NV double values per thread; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NV; ++i) {
+      double s = 0;
+      for (int w = 0; w < kThreads / 64; ++w) s += lds[w * NV + i];
+      v[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// partial[i * nblk + blk] = sum over the block's chunk of conj(V_i) w   (i < nv)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_mdot(const cx<T>* __restrict__ V, long ldv, int nv,
+                                                    const cx<T>* __restrict__ w, long n,
+                                                    double2* __restrict__ partial) {
+  __shared__ double lds[(kThreads / 64) * 2 * kGroup];
+  const long e0 = (long)blockIdx.x * kChunk + threadIdx.x;
+  double2 wv[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const long e = e0 + (long)k * kThreads;
+    wv[k] = e < n ? to_d(w[e]) : double2{0.0, 0.0};
+  }
+  for (int i0 = 0; i0 < nv; i0 += kGroup) {
+    double acc[2 * kGroup];
+#pragma unroll
+    for (int q = 0; q < 2 * kGroup; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+      if (i0 + q < nv) {
+        const cx<T>* Vi = V + (long)(i0 + q) * ldv;
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+          const long e = e0 + (long)k * kThreads;
+          if (e < n) {
+            const double2 a = to_d(Vi[e]);
+            acc[2 * q] += a.x * wv[k].x + a.y * wv[k].y;
+            acc[2 * q + 1] += a.x * wv[k].y - a.y * wv[k].x;
+          }
+        }
+      }
+    }
+    block_sum<2 * kGroup>(acc, lds);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < kGroup; ++q)
+        if (i0 + q < nv) partial[(long)(i0 + q) * gridDim.x + blockIdx.x] = double2{acc[2 * q], acc[2 * q + 1]};
+  }
+}
+
+// out[i] (+)= sum_b partial[i * nblk + b], one workgroup per i, fixed order
+__global__ __launch_bounds__(kThreads) void k_reduce(const double2* __restrict__ partial, int nblk,
+                                                      double2* __restrict__ out, int accumulate) {
+  __shared__ double lds[(kThreads / 64) * 2];
+  const int i = blockIdx.x;
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    const double2 p = partial[(long)i * nblk + b];
+    v[0] += p.x;
+    v[1] += p.y;
+  }
+  block_sum<2>(v, lds);
+  if (threadIdx.x == 0) {
+    if (accumulate) out[i] = double2{out[i].x + v[0], out[i].y + v[1]};
+    else out[i] = double2{v[0], v[1]};
+  }
+}
+
+// w += sign * sum_i coef[i] V_i
+template <typename T, typename TW>
+__global__ __launch_bounds__(kThreads) void k_maxpy(const cx<T>* __restrict__ V, long ldv, int nv,
+                                                     const double2* __restrict__ coef, double sign,
+                                                     cx<TW>* __restrict__ w, long n) {
+  __shared__ double2 c[512];
+  for (int i = threadIdx.x; i < nv && i < 512; i += kThreads) c[i] = double2{sign * coef[i].x, sign * coef[i].y};
+  __syncthreads();
+  const long e0 = (long)blockIdx.x * kChunk + threadIdx.x;
+  double2 acc[kEPT];
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const long e = e0 + (long)k * kThreads;
+    acc[k] = e < n ? to_d(w[e]) : double2{0.0, 0.0};
+  }
+  for (int i = 0; i < nv; ++i) {
+    const double2 ci = c[i];
+    const cx<T>* Vi = V + (long)i * ldv;
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+      const long e = e0 + (long)k * kThreads;
+      if (e < n) {
+        const double2 a = to_d(Vi[e]);
+        acc[k].x += ci.x * a.x - ci.y * a.y;
+        acc[k].y += ci.x * a.y + ci.y * a.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const long e = e0 + (long)k * kThreads;
+    if (e < n) w[e] = from_d<cx<TW>>(acc[k]);
+  }
+}
+
+// partial[blk] = sum |w|^2 over the block's chunk
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_nrm2_partial(const cx<T>* __restrict__ w, long n,
+                                                            double2* __restrict__ partial) {
+  __shared__ double lds[(kThreads / 64) * 2];
+  const long e0 = (long)blockIdx.x * kChunk + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < kEPT; ++k) {
+    const long e = e0 + (long)k * kThreads;
+    if (e < n) {
+      const double2 a = to_d(w[e]);
+      v[0] += a.x * a.x + a.y * a.y;
+    }
+  }
+  block_sum<2>(v, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = double2{v[0], 0.0};
+}
+
+// dst = src * (1/norm) where norm = sqrt(sumsq->x); dst may alias src
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scale(const cx<T>* src, cx<T>* dst, long n,
+                                                     const double2* __restrict__ sumsq) {
+  const double nr = sqrt(sumsq->x);
+  const double s = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < n; e += (long)gridDim.x * kThreads) {
+    const double2 a = to_d(src[e]);
+    dst[e] = from_d<cx<T>>(double2{a.x * s, a.y * s});
+  }
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(kThreads) void k_copy(const cx<TS>* __restrict__ src, cx<TD>* __restrict__ dst,
+                                                    long n) {
+  for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < n; e += (long)gridDim.x * kThreads)
+    dst[e] = from_d<cx<TD>>(to_d(src[e]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zero(cx<T>* __restrict__ dst, long n) {
+  for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < n; e += (long)gridDim.x * kThreads)
+    dst[e] = cx<T>{(T)0, (T)0};
+}
+
+// One Arnoldi step's Hessenberg bookkeeping (single thread).
+// h1[0..j] + h2[0..j] = projections of the two Gram-Schmidt sweeps,
+// sumsq->x = ||w||^2 after orthogonalisation.
+// H is column-major with leading dimension m+1.  state[0] = residual estimate
+// |g_{j+1}| / bnorm, state[1] = ||w|| (breakdown when 0), state[2] = 1 if any
+// value is non-finite.
+__global__ void k_arnoldi_update(const double2* __restrict__ h1, const double2* __restrict__ h2,
+                                 const double2* __restrict__ sumsq,
+                                 double2* __restrict__ H, int ldh, double* __restrict__ cs,
+                                 double2* __restrict__ sn, double2* __restrict__ gvec, int j, double bnorm,
+                                 double* __restrict__ state) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double2* h = H + (long)j * ldh;
+  for (int i = 0; i <= j; ++i) h[i] = double2{h1[i].x + h2[i].x, h1[i].y + h2[i].y};
+  const double hn = sqrt(sumsq->x);
+  h[j + 1] = double2{hn, 0.0};
+  // previous rotations: [c s; -conj(s) c]
+  for (int i = 0; i < j; ++i) {
+    const double2 a = h[i], b = h[i + 1];
+    const double c = cs[i];
+    const double2 s = sn[i];
+    h[i] = double2{c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x)};
+    h[i + 1] = double2{-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y};
+  }
+  // new rotation zeroing h[j+1]
+  const double2 a = h[j], b = h[j + 1];
+  const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+  double c;
+  double2 s, r;
+  if (nb == 0.0) {
+    c = 1.0;
+    s = double2{0.0, 0.0};
+    r = a;
+  } else if (na == 0.0) {
+    c = 0.0;
+    s = double2{1.0, 0.0};
+    r = b;
+  } else {
+    const double t = hypot(na, nb);
+    const double2 ph = double2{a.x / na, a.y / na};
+    c = na / t;
+    // s = ph * conj(b) / t
+    s = double2{(ph.x * b.x + ph.y * b.y) / t, (ph.y * b.x - ph.x * b.y) / t};
+    r = double2{ph.x * t, ph.y * t};
+  }
+  cs[j] = c;
+  sn[j] = s;
+  h[j] = r;
+  h[j + 1] = double2{0.0, 0.0};
+  const double2 gj = gvec[j];
+  // g_{j+1} = -conj(s) g_j ; g_j = c g_j
+  gvec[j + 1] = double2{-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x)};
+  gvec[j] = double2{c * gj.x, c * gj.y};
+  const double est = hypot(gvec[j + 1].x, gvec[j + 1].y) / bnorm;
+  state[0] = est;
+  state[1] = hn;
+  state[2] = (isfinite(est) && isfinite(hn) && isfinite(r.x) && isfinite(r.y)) ? 0.0 : 1.0;
+}
+
+// y = R^{-1} g for the leading k x k upper triangle of H (single thread)
+__global__ void k_trisolve(const double2* __restrict__ H, int ldh, const double2* __restrict__ gvec, int k,
+                           double2* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double2 s = gvec[i];
+    for (int l = i + 1; l < k; ++l) {
+      const double2 hil = H[(long)l * ldh + i], yl = y[l];
+      s.x -= hil.x * yl.x - hil.y * yl.y;
+      s.y -= hil.x * yl.y + hil.y * yl.x;
+    }
+    const double2 d = H[(long)i * ldh + i];
+    const double dd = d.x * d.x + d.y * d.y;
+    y[i] = double2{(s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd};
+  }
+}
+
+__global__ void k_set_g(double2* gvec, int m, const double2* sumsq) {
+  for (int i = threadIdx.x; i <= m; i += blockDim.x) gvec[i] = double2{0.0, 0.0};
+  if (threadIdx.x == 0) gvec[0] = double2{sqrt(sumsq->x), 0.0};
+}
+
+// ------------------------------------------------------------------ host-side helpers
+
+static inline int nblocks(long n) { return (int)((n + kChunk - 1) / kChunk); }
+
+template <typename T>
+hipError_t KrylovOps<T>::nrm2sq(const cx<T>* w, long n, double2* partial, double2* out, hipStream_t s) {
+  const int nb = nblocks(n);
+  hipLaunchKernelGGL((k_nrm2_partial<T>), dim3(nb), dim3(kThreads), 0, s, w, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, partial, nb, out, 0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::mdot(const cx<T>* V, long ldv, int nv, const cx<T>* w, long n, double2* partial,
+                              double2* out, int accumulate, hipStream_t s) {
+  const int nb = nblocks(n);
+  hipLaunchKernelGGL((k_mdot<T>), dim3(nb), dim3(kThreads), 0, s, V, ldv, nv, w, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kThreads), 0, s, partial, nb, out, accumulate);
+  return hipGetLastError();
+}
+
+template <typename T>
+template <typename TW>
+hipError_t KrylovOps<T>::maxpy(const cx<T>* V, long ldv, int nv, const double2* coef, double sign, cx<TW>* w,
+                               long n, hipStream_t s) {
+  for (int i0 = 0; i0 < nv; i0 += 512) {
+    const int cnt = nv - i0 < 512 ? nv - i0 : 512;
+    hipLaunchKernelGGL((k_maxpy<T, TW>), dim3(nblocks(n)), dim3(kThreads), 0, s, V + (long)i0 * ldv, ldv, cnt,
+                       coef + i0, sign, w, n);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::scale(const cx<T>* src, cx<T>* dst, long n, const double2* sumsq, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale<T>), dim3(2048), dim3(kThreads), 0, s, src, dst, n, sumsq);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::zero(cx<T>* dst, long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero<T>), dim3(2048), dim3(kThreads), 0, s, dst, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::arnoldi_update(const double2* h1, const double2* h2, const double2* sumsq, double2* H,
+                                        int ldh, double* cs, double2* sn, double2* g, int j, double bnorm,
+                                        double* state, hipStream_t s) {
+  hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(64), 0, s, h1, h2, sumsq, H, ldh, cs, sn, g, j, bnorm, state);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::trisolve(const double2* H, int ldh, const double2* g, int k, double2* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, s, H, ldh, g, k, y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::set_g(double2* g, int m, const double2* sumsq, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_g, dim3(1), dim3(256), 0, s, g, m, sumsq);
+  return hipGetLastError();
+}
+
+template <typename TS, typename TD>
+hipError_t convert(const cx<TS>* src, cx<TD>* dst, long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy<TS, TD>), dim3(2048), dim3(kThreads), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+template struct KrylovOps<double>;
+template struct KrylovOps<float>;
+template hipError_t KrylovOps<double>::maxpy<double>(const cx<double>*, long, int, const double2*, double,
+                                                     cx<double>*, long, hipStream_t);
+template hipError_t KrylovOps<float>::maxpy<float>(const cx<float>*, long, int, const double2*, double,
+                                                   cx<float>*, long, hipStream_t);
+template hipError_t convert<double, float>(const cx<double>*, cx<float>*, long, hipStream_t);
+template hipError_t convert<float, double>(const cx<float>*, cx<double>*, long, hipStream_t);
+template hipError_t convert<double, double>(const cx<double>*, cx<double>*, long, hipStream_t);
+
+int partial_blocks(long n) { return nblocks(n); }
+
+}  // namespace vie

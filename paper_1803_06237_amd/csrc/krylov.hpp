@@ -1,0 +1,34 @@
+// Krylov building blocks launched on a stream (implementations in krylov.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft_device.hpp"
+
+namespace vie {
+
+template <typename T>
+struct KrylovOps {
+  // out[0].x = ||w||^2 (FP64 accumulation); partial needs partial_blocks(n) entries
+  static hipError_t nrm2sq(const cx<T>* w, long n, double2* partial, double2* out, hipStream_t s);
+  // out[i] (+)= V_i^H w for i < nv; partial needs nv * partial_blocks(n) entries
+  static hipError_t mdot(const cx<T>* V, long ldv, int nv, const cx<T>* w, long n, double2* partial,
+                         double2* out, int accumulate, hipStream_t s);
+  // w += sign * sum_i coef[i] V_i
+  template <typename TW>
+  static hipError_t maxpy(const cx<T>* V, long ldv, int nv, const double2* coef, double sign, cx<TW>* w, long n,
+                          hipStream_t s);
+  // dst = src / sqrt(sumsq->x)
+  static hipError_t scale(const cx<T>* src, cx<T>* dst, long n, const double2* sumsq, hipStream_t s);
+  static hipError_t zero(cx<T>* dst, long n, hipStream_t s);
+  static hipError_t arnoldi_update(const double2* h1, const double2* h2, const double2* sumsq, double2* H, int ldh, double* cs,
+                                   double2* sn, double2* g, int j, double bnorm, double* state, hipStream_t s);
+  static hipError_t trisolve(const double2* H, int ldh, const double2* g, int k, double2* y, hipStream_t s);
+  static hipError_t set_g(double2* g, int m, const double2* sumsq, hipStream_t s);
+};
+
+template <typename TS, typename TD>
+hipError_t convert(const cx<TS>* src, cx<TD>* dst, long n, hipStream_t s);
+
+int partial_blocks(long n);
+
+}  // namespace vie

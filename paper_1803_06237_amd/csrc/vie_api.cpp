@@ -1,0 +1,553 @@
+// C ABI of the voxel J-VIE solver: plan lifetime, contrast, matvec and the
+// GMRES / flexible-GMRES drivers.  See include/vie.h for the contract.
+#include "../../include/vie.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "krylov.hpp"
+#include "vie_internal.hpp"
+
+namespace vie {
+template <typename T>
+hipError_t allow_lds(size_t bytes);
+}
+
+using namespace vie;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+template <typename T>
+struct GmresWs {
+  long n = 0;
+  int m = 0;
+  bool flex = false;
+  cx<T>* V = nullptr;
+  cx<T>* Z = nullptr;
+  double2* partial = nullptr;
+  double2* h1 = nullptr;
+  double2* h2 = nullptr;
+  double2* sumsq = nullptr;
+  double2* H = nullptr;
+  double2* sn = nullptr;
+  double2* g = nullptr;
+  double2* y = nullptr;
+  double* cs = nullptr;
+  double* state = nullptr;
+  double* state_h = nullptr;
+
+  void release() {
+    for (void* p : {(void*)V, (void*)Z, (void*)partial, (void*)h1, (void*)h2, (void*)sumsq, (void*)H, (void*)sn,
+                    (void*)g, (void*)y, (void*)cs, (void*)state})
+      if (p) (void)hipFree(p);
+    if (state_h) (void)hipHostFree(state_h);
+    *this = GmresWs();
+  }
+  hipError_t ensure(long n_, int m_, bool flex_) {
+    if (n_ == n && m_ == m && flex_ == flex && V) return hipSuccess;
+    release();
+    n = n_;
+    m = m_;
+    flex = flex_;
+    const long nb = partial_blocks(n);
+    hipError_t e;
+    if ((e = hipMalloc(&V, sizeof(cx<T>) * (size_t)n * (m + 1)))) return e;
+    if (flex && (e = hipMalloc(&Z, sizeof(cx<T>) * (size_t)n * m))) return e;
+    if ((e = hipMalloc(&partial, sizeof(double2) * (size_t)nb * (m + 1)))) return e;
+    if ((e = hipMalloc(&h1, sizeof(double2) * (m + 2)))) return e;
+    if ((e = hipMalloc(&h2, sizeof(double2) * (m + 2)))) return e;
+    if ((e = hipMalloc(&sumsq, sizeof(double2) * 2))) return e;
+    if ((e = hipMalloc(&H, sizeof(double2) * (size_t)(m + 1) * m))) return e;
+    if ((e = hipMalloc(&sn, sizeof(double2) * (m + 1)))) return e;
+    if ((e = hipMalloc(&g, sizeof(double2) * (m + 1)))) return e;
+    if ((e = hipMalloc(&y, sizeof(double2) * (m + 1)))) return e;
+    if ((e = hipMalloc(&cs, sizeof(double) * (m + 1)))) return e;
+    if ((e = hipMalloc(&state, sizeof(double) * 4))) return e;
+    if ((e = hipHostMalloc(&state_h, sizeof(double) * 4, hipHostMallocDefault))) return e;
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+
+struct vie_plan_s {
+  Geom g{};
+  double h = 0, k0 = 0, eps_b = 0, kappa = 0;
+  unsigned flags = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Tune t64{}, t32{};
+  double2* goct64 = nullptr;
+  float2* goct32 = nullptr;
+  double2* chi64 = nullptr;
+  float2* chi32 = nullptr;
+  double2* U64 = nullptr;
+  float2* U32 = nullptr;
+  double2* tw64[3] = {nullptr, nullptr, nullptr};
+  float2* tw32[3] = {nullptr, nullptr, nullptr};
+  double2* rvec = nullptr;     // FP64 scratch vector (residuals)
+  float2* v32a = nullptr;      // FP32 scratch vectors (mixed tier)
+  float2* v32b = nullptr;
+  int* flag = nullptr;
+  bool has_contrast = false;
+  GmresWs<double> ws64;
+  GmresWs<float> ws32;
+  std::string err;
+};
+
+namespace {
+
+int fail(vie_plan_s* p, int code, const std::string& msg) {
+  if (p) p->err = msg;
+  else g_thread_error = msg;
+  return code;
+}
+
+int hipfail(vie_plan_s* p, hipError_t e, const char* where) {
+  return fail(p, VIE_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPTRY(p, expr)                                     \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return hipfail((p), _e, #expr);   \
+  } while (0)
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+template <typename T>
+bool pick_tune(const Geom& g, size_t budget, size_t zbudget, Tune* t) {
+  const size_t cs = sizeof(cx<T>);
+  int tp = 16;
+  const int n1p = 1 << ilog2(g.n1);
+  if (tp > n1p) tp = n1p;
+  while (tp > 1 && (size_t)tp * (g.M3 + 1) * cs > zbudget) tp >>= 1;
+  if ((size_t)tp * (g.M3 + 1) * cs > budget) return false;
+  t->tp = tp;
+  int zt = (tp * g.M3 + 15) / 16;
+  zt = ((zt + 63) / 64) * 64;
+  if (zt < 64) zt = 64;
+  if (zt > 1024) return false;
+  t->zthreads = zt < 256 ? (tp * g.M3 >= 256 ? 256 : zt) : zt;
+  int cc = g.M1 < 16 ? g.M1 : 16;
+  while (cc > 1 && ((size_t)3 * g.n2 * g.M1 + (size_t)3 * g.M2 * cc) * cs > budget) cc >>= 1;
+  if (((size_t)3 * g.n2 * g.M1 + (size_t)3 * g.M2 * cc) * cs > budget) return false;
+  t->cc = cc;
+  int need = 3 * g.n2 * g.M1;
+  if (3 * g.M2 * cc > need) need = 3 * g.M2 * cc;
+  int xt = (need + 15) / 16;
+  xt = ((xt + 63) / 64) * 64;
+  if (xt < 256) xt = need >= 256 ? 256 : 64;
+  if (xt > 1024) return false;
+  t->xythreads = xt;
+  return true;
+}
+
+template <typename T>
+hipError_t make_twiddles(int M, cx<T>** out) {
+  std::vector<cx<T>> h(M);
+  for (int k = 0; k < M; ++k) {
+    long double a = -2.0L * 3.14159265358979323846264338327950288L * k / M;
+    h[k] = cx<T>{(T)std::cos(a), (T)std::sin(a)};
+  }
+  hipError_t e = hipMalloc(out, sizeof(cx<T>) * M);
+  if (e) return e;
+  return hipMemcpy(*out, h.data(), sizeof(cx<T>) * M, hipMemcpyHostToDevice);
+}
+
+// ---- operator wrappers used by the solvers ---------------------------------
+struct Op64 {
+  vie_plan_s* p;
+  hipError_t apply(const double2* x, double2* y) {
+    const void* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+    return launch_matvec<double>(p->g, p->t64, x, y, nullptr, 0, p->U64, p->goct64, p->chi64, tw, p->stream);
+  }
+  hipError_t residual(const double2* x, const double2* b, double2* r) {
+    const void* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+    return launch_matvec<double>(p->g, p->t64, x, r, b, 1, p->U64, p->goct64, p->chi64, tw, p->stream);
+  }
+};
+struct Op32 {
+  vie_plan_s* p;
+  hipError_t apply(const float2* x, float2* y) {
+    const void* tw[3] = {p->tw32[0], p->tw32[1], p->tw32[2]};
+    return launch_matvec<float>(p->g, p->t32, x, y, nullptr, 0, p->U32, p->goct32, p->chi32, tw, p->stream);
+  }
+  hipError_t residual(const float2* x, const float2* b, float2* r) {
+    const void* tw[3] = {p->tw32[0], p->tw32[1], p->tw32[2]};
+    return launch_matvec<float>(p->g, p->t32, x, r, b, 1, p->U32, p->goct32, p->chi32, tw, p->stream);
+  }
+};
+
+struct Stats {
+  int iters = 0, restarts = 0, matvecs = 0, inner = 0;
+  double est = 0, rel_true = INFINITY;
+};
+
+struct NoPrecond {
+  hipError_t operator()(const void*, void*, Stats&) { return hipSuccess; }
+};
+
+hipError_t read_scalar(const double2* d, double* out, double* pinned, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(pinned, d, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e) return e;
+  if ((e = hipStreamSynchronize(s))) return e;
+  *out = pinned[0];
+  return hipSuccess;
+}
+
+// GMRES(m) (flexible when a preconditioner is given) on basis type T.
+// check_true: confirm convergence with the true residual and restart until then.
+template <typename T, typename OP, typename PC>
+int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, const cx<T>* b, cx<T>* x, double tol, int m,
+               int maxit, bool use_x0, bool check_true, Stats& st) {
+  using K = KrylovOps<T>;
+  hipStream_t s = p->stream;
+  const long n = 3 * p->g.N;
+  HIPTRY(p, W.ensure(n, m, M != nullptr));
+  double bsq = 0;
+  HIPTRY(p, K::nrm2sq(b, n, W.partial, W.sumsq, s));
+  HIPTRY(p, read_scalar(W.sumsq, &bsq, W.state_h, s));
+  if (!std::isfinite(bsq)) return fail(p, VIE_EINVAL, "right-hand side is not finite");
+  const double bnorm = std::sqrt(bsq);
+  if (bnorm == 0.0) {
+    HIPTRY(p, K::zero(x, n, s));
+    st.rel_true = 0;
+    return VIE_OK;
+  }
+  cx<T>* V0 = W.V;
+  if (use_x0) {
+    HIPTRY(p, A.residual(x, b, V0));
+    st.matvecs++;
+  } else {
+    HIPTRY(p, K::zero(x, n, s));
+    HIPTRY(p, hipMemcpyAsync(V0, b, sizeof(cx<T>) * n, hipMemcpyDeviceToDevice, s));
+  }
+  double beta2 = 0;
+  HIPTRY(p, K::nrm2sq(V0, n, W.partial, W.sumsq, s));
+  HIPTRY(p, read_scalar(W.sumsq, &beta2, W.state_h, s));
+  double rel = std::sqrt(beta2) / bnorm;
+  st.est = rel;
+  int status = VIE_ENOCONV;
+  const int ldh = m + 1;
+  while (true) {
+    if (!std::isfinite(rel)) return fail(p, VIE_ENUMERIC, "non-finite residual");
+    if (rel <= tol) {
+      status = VIE_OK;
+      break;
+    }
+    if (st.iters >= maxit) break;
+    HIPTRY(p, K::set_g(W.g, m, W.sumsq, s));
+    HIPTRY(p, K::scale(V0, V0, n, W.sumsq, s));
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      cx<T>* Vj = W.V + (long)j * n;
+      cx<T>* w = W.V + (long)(j + 1) * n;
+      const cx<T>* z = Vj;
+      if (M) {
+        cx<T>* Zj = W.Z + (long)j * n;
+        HIPTRY(p, (*M)(Vj, Zj, st));
+        z = Zj;
+      }
+      HIPTRY(p, A.apply(z, w));
+      st.matvecs++;
+      HIPTRY(p, K::mdot(W.V, n, j + 1, w, n, W.partial, W.h1, 0, s));
+      HIPTRY(p, K::template maxpy<T>(W.V, n, j + 1, W.h1, -1.0, w, n, s));
+      HIPTRY(p, K::mdot(W.V, n, j + 1, w, n, W.partial, W.h2, 0, s));
+      HIPTRY(p, K::template maxpy<T>(W.V, n, j + 1, W.h2, -1.0, w, n, s));
+      HIPTRY(p, K::nrm2sq(w, n, W.partial, W.sumsq, s));
+      HIPTRY(p, K::scale(w, w, n, W.sumsq, s));
+      HIPTRY(p, K::arnoldi_update(W.h1, W.h2, W.sumsq, W.H, ldh, W.cs, W.sn, W.g, j, bnorm, W.state, s));
+      HIPTRY(p, hipMemcpyAsync(W.state_h, W.state, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPTRY(p, hipStreamSynchronize(s));
+      st.iters++;
+      k = j + 1;
+      st.est = W.state_h[0];
+      if (W.state_h[2] != 0.0) return fail(p, VIE_ENUMERIC, "non-finite value in Arnoldi step");
+      if (W.state_h[0] <= tol || W.state_h[1] == 0.0 || st.iters >= maxit) break;
+    }
+    HIPTRY(p, K::trisolve(W.H, ldh, W.g, k, W.y, s));
+    HIPTRY(p, K::template maxpy<T>(M ? W.Z : W.V, n, k, W.y, 1.0, x, n, s));
+    st.restarts++;
+    if (!check_true) {
+      status = st.est <= tol ? VIE_OK : VIE_ENOCONV;
+      HIPTRY(p, hipStreamSynchronize(s));
+      break;
+    }
+    HIPTRY(p, A.residual(x, b, V0));
+    st.matvecs++;
+    HIPTRY(p, K::nrm2sq(V0, n, W.partial, W.sumsq, s));
+    HIPTRY(p, read_scalar(W.sumsq, &beta2, W.state_h, s));
+    rel = std::sqrt(beta2) / bnorm;
+    st.rel_true = rel;
+  }
+  if (check_true) st.rel_true = rel;
+  return status;
+}
+
+}  // namespace
+
+size_t vie::lds_budget(int device) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
+    v = 65536;
+  return (size_t)v;
+}
+
+extern "C" {
+
+const char* vie_version(void) { return "vie-mi355x 0.1 (gfx950)"; }
+
+const char* vie_last_error(vie_plan_t plan) { return plan ? plan->err.c_str() : g_thread_error.c_str(); }
+
+int vie_green_table(const int grid[3], double kappa, vie_c128* out, int nthreads) {
+  if (!grid || !out) return fail(nullptr, VIE_EINVAL, "null argument");
+  for (int d = 0; d < 3; ++d)
+    if (grid[d] < 1 || grid[d] > 4096) return fail(nullptr, VIE_EINVAL, "grid size out of range");
+  if (!std::isfinite(kappa)) return fail(nullptr, VIE_EINVAL, "kappa not finite");
+  vie::green_table(grid, kappa, reinterpret_cast<std::complex<double>*>(out), nthreads);
+  return VIE_OK;
+}
+
+int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps_b, unsigned flags,
+             void* hip_stream) {
+  if (!out || !grid) return fail(nullptr, VIE_EINVAL, "null argument");
+  *out = nullptr;
+  if (!(h > 0) || !(k0 > 0) || !(eps_b > 0) || !std::isfinite(h) || !std::isfinite(k0) || !std::isfinite(eps_b))
+    return fail(nullptr, VIE_EINVAL, "h, k0 and eps_b must be positive and finite");
+  const int lim[3] = {32, 32, 2048};
+  for (int d = 0; d < 3; ++d)
+    if (grid[d] < 1 || grid[d] > lim[d]) return fail(nullptr, VIE_EINVAL, "grid outside n1,n2 <= 32, n3 <= 2048");
+  auto* p = new vie_plan_s();
+  p->h = h;
+  p->k0 = k0;
+  p->eps_b = eps_b;
+  p->kappa = k0 * std::sqrt(eps_b) * h;
+  p->flags = flags;
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  Geom& g = p->g;
+  g.n1 = grid[0];
+  g.n2 = grid[1];
+  g.n3 = grid[2];
+  int Ms[3];
+  for (int d = 0; d < 3; ++d) {
+    int M = 1;
+    while (M < 2 * grid[d] - 1) M <<= 1;
+    Ms[d] = M;
+  }
+  g.M1 = Ms[0];
+  g.M2 = Ms[1];
+  g.M3 = Ms[2];
+  g.L1 = ilog2(g.M1);
+  g.L2 = ilog2(g.M2);
+  g.L3 = ilog2(g.M3);
+  g.H1 = g.M1 / 2 + 1;
+  g.H2 = g.M2 / 2 + 1;
+  g.H3 = g.M3 / 2 + 1;
+  g.N = (long)g.n1 * g.n2 * g.n3;
+  auto bail = [&](int code) {
+    vie_destroy(p);
+    return code;
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&p->device))) return bail(hipfail(nullptr, e, "hipGetDevice"));
+  const size_t budget = lds_budget(p->device);
+  const size_t zbudget = budget < 65536 ? budget : 65536;
+  if (!pick_tune<double>(g, budget, zbudget, &p->t64) || !pick_tune<float>(g, budget, zbudget, &p->t32))
+    return bail(fail(nullptr, VIE_EINVAL, "grid does not fit the LDS budget"));
+  if ((e = allow_lds<double>(budget)) || (e = allow_lds<float>(budget)))
+    return bail(hipfail(nullptr, e, "hipFuncSetAttribute"));
+  // host table
+  std::vector<std::complex<double>> table((size_t)6 * g.N);
+  vie::green_table(grid, p->kappa, table.data(), 0);
+  const bool f32 = (flags & VIE_WITH_FP32) != 0;
+  const long H = (long)g.H1 * g.H2 * g.H3;
+  const long P = (long)g.M1 * g.M2 * g.M3;
+  double2* table_dev = nullptr;
+  double2* full = nullptr;
+  auto cleanup_tmp = [&]() {
+    if (table_dev) (void)hipFree(table_dev);
+    if (full) (void)hipFree(full);
+  };
+#define PLANTRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) {                             \
+      cleanup_tmp();                                    \
+      return bail(hipfail(nullptr, _e, #expr));         \
+    }                                                   \
+  } while (0)
+  for (int d = 0; d < 3; ++d) {
+    PLANTRY(make_twiddles<double>(Ms[d], &p->tw64[d]));
+    PLANTRY(make_twiddles<float>(Ms[d], &p->tw32[d]));
+  }
+  PLANTRY(hipMalloc(&p->goct64, sizeof(double2) * 6 * H));
+  if (f32) PLANTRY(hipMalloc(&p->goct32, sizeof(float2) * 6 * H));
+  PLANTRY(hipMalloc(&p->chi64, sizeof(double2) * g.N));
+  PLANTRY(hipMalloc(&p->chi32, sizeof(float2) * g.N));
+  PLANTRY(hipMalloc(&p->U64, sizeof(double2) * 3 * (size_t)g.n1 * g.n2 * g.M3));
+  if (f32) PLANTRY(hipMalloc(&p->U32, sizeof(float2) * 3 * (size_t)g.n1 * g.n2 * g.M3));
+  PLANTRY(hipMalloc(&p->rvec, sizeof(double2) * 3 * g.N));
+  PLANTRY(hipMalloc(&p->flag, sizeof(int)));
+  PLANTRY(hipMalloc(&table_dev, sizeof(double2) * 6 * g.N));
+  PLANTRY(hipMalloc(&full, sizeof(double2) * P));
+  PLANTRY(hipMemcpyAsync(table_dev, table.data(), sizeof(double2) * 6 * g.N, hipMemcpyHostToDevice, p->stream));
+  {
+    const double2* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+    PLANTRY(launch_spectrum(g, table_dev, full, p->goct64, p->goct32, tw, p->stream));
+  }
+  PLANTRY(hipStreamSynchronize(p->stream));
+  cleanup_tmp();
+#undef PLANTRY
+  *out = p;
+  return VIE_OK;
+}
+
+int vie_set_contrast(vie_plan_t p, const vie_c128* eps) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!eps) return fail(p, VIE_EINVAL, "null eps");
+  HIPTRY(p, hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
+  HIPTRY(p, launch_contrast(p->g.N, reinterpret_cast<const double2*>(eps), p->eps_b, p->chi64, p->chi32, p->flag,
+                            p->stream));
+  int bad = 0;
+  HIPTRY(p, hipMemcpyAsync(&bad, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIPTRY(p, hipStreamSynchronize(p->stream));
+  if (bad) {
+    p->has_contrast = false;
+    return fail(p, VIE_EINVAL, "eps has a non-finite or zero value");
+  }
+  p->has_contrast = true;
+  return VIE_OK;
+}
+
+int vie_rhs(vie_plan_t p, const vie_c128* e_inc, vie_c128* b) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!e_inc || !b) return fail(p, VIE_EINVAL, "null vector");
+  if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
+  HIPTRY(p, launch_rhs(p->g.N, std::pow(p->h, 1.5), p->chi64, reinterpret_cast<const double2*>(e_inc),
+                       reinterpret_cast<double2*>(b), p->stream));
+  return VIE_OK;
+}
+
+int vie_matvec(vie_plan_t p, const vie_c128* x, vie_c128* y) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!x || !y || (const void*)x == (const void*)y) return fail(p, VIE_EINVAL, "x, y null or aliased");
+  if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
+  Op64 A{p};
+  HIPTRY(p, A.apply(reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y)));
+  return VIE_OK;
+}
+
+int vie_matvec_c64(vie_plan_t p, const vie_c64* x, vie_c64* y) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!x || !y || (const void*)x == (const void*)y) return fail(p, VIE_EINVAL, "x, y null or aliased");
+  if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
+  if (!p->goct32) return fail(p, VIE_ESTATE, "plan built without VIE_WITH_FP32");
+  Op32 A{p};
+  HIPTRY(p, A.apply(reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(y)));
+  return VIE_OK;
+}
+
+int vie_residual(vie_plan_t p, const vie_c128* x, const vie_c128* b, vie_c128* r) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!x || !b || !r || (const void*)x == (const void*)r) return fail(p, VIE_EINVAL, "bad vectors");
+  if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
+  Op64 A{p};
+  HIPTRY(p, A.residual(reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(b),
+                       reinterpret_cast<double2*>(r)));
+  return VIE_OK;
+}
+
+int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts* opts,
+              vie_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!b || !x || (const void*)b == (const void*)x) return fail(p, VIE_EINVAL, "b, x null or aliased");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(p, VIE_EINVAL, "tol must be positive");
+  if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
+  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4};
+  if (opts) o = *opts;
+  if (o.restart <= 0) o.restart = 50;
+  if (o.maxit <= 0) o.maxit = 10000;
+  if (o.inner_restart <= 0) o.inner_restart = 20;
+  if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
+  if (o.restart > 4096 || o.inner_restart > 4096) return fail(p, VIE_EINVAL, "restart too large");
+  const long n = 3 * p->g.N;
+  Stats st;
+  int status;
+  Op64 A{p};
+  if (o.precision == 0) {
+    status = gmres_core<double, Op64, NoPrecond>(p, p->ws64, A, nullptr, reinterpret_cast<const double2*>(b),
+                                                 reinterpret_cast<double2*>(x), tol, o.restart, o.maxit,
+                                                 o.use_x0 != 0, true, st);
+  } else if (o.precision == 1) {
+    if (!p->goct32) return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
+    if (!p->v32a) {
+      HIPTRY(p, hipMalloc(&p->v32a, sizeof(float2) * n));
+      HIPTRY(p, hipMalloc(&p->v32b, sizeof(float2) * n));
+    }
+    Op32 A32{p};
+    // right preconditioner: z = inner FP32 GMRES solve of A z = v
+    auto inner = [&](const void* v, void* z, Stats& outer) -> hipError_t {
+      hipError_t e = convert<double, float>(reinterpret_cast<const double2*>(v), p->v32a, n, p->stream);
+      if (e) return e;
+      Stats si;
+      int rc = gmres_core<float, Op32, NoPrecond>(p, p->ws32, A32, nullptr, p->v32a, p->v32b, o.inner_tol,
+                                                   o.inner_restart, o.inner_restart, false, false, si);
+      outer.inner += si.iters;
+      if (rc != VIE_OK && rc != VIE_ENOCONV) return hipErrorUnknown;
+      return convert<float, double>(p->v32b, reinterpret_cast<double2*>(z), n, p->stream);
+    };
+    struct Pc {
+      decltype(inner)& f;
+      hipError_t operator()(const void* v, void* z, Stats& s) { return f(v, z, s); }
+    } pc{inner};
+    status = gmres_core<double, Op64, Pc>(p, p->ws64, A, &pc, reinterpret_cast<const double2*>(b),
+                                          reinterpret_cast<double2*>(x), tol, o.restart, o.maxit, o.use_x0 != 0,
+                                          true, st);
+  } else {
+    return fail(p, VIE_EINVAL, "unknown precision tier");
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->iters = st.iters;
+    info->inner_iters = st.inner;
+    info->restarts = st.restarts;
+    info->matvecs = st.matvecs;
+    info->status = status;
+    info->rel_res_true = st.rel_true;
+    info->rel_res_est = st.est;
+    info->seconds = secs;
+  }
+  if (status == VIE_ENOCONV && p->err.empty()) p->err = "tolerance not reached within maxit";
+  return status;
+}
+
+void vie_destroy(vie_plan_t p) {
+  if (!p) return;
+  p->ws64.release();
+  p->ws32.release();
+  for (void* q : {(void*)p->goct64, (void*)p->goct32, (void*)p->chi64, (void*)p->chi32, (void*)p->U64,
+                  (void*)p->U32, (void*)p->rvec, (void*)p->v32a, (void*)p->v32b, (void*)p->flag})
+    if (q) (void)hipFree(q);
+  for (int d = 0; d < 3; ++d) {
+    if (p->tw64[d]) (void)hipFree(p->tw64[d]);
+    if (p->tw32[d]) (void)hipFree(p->tw32[d]);
+  }
+  delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Internal declarations shared by the host side of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstddef>
+
+namespace vie {
+
+// Host FP64 Toeplitz table (green_table.cpp): out[6][n1][n2][n3].
+int green_table(const int n[3], double kappa, std::complex<double>* out, int nthreads);
+
+// Geometry and launch shapes of one operator, passed to the kernel launchers.
+struct Geom {
+  int n1, n2, n3;           // voxel grid
+  int M1, M2, M3;           // circulant sizes (powers of two)
+  int L1, L2, L3;           // log2 of M
+  int H1, H2, H3;           // octant extents M/2 + 1
+  long N;                   // voxels
+};
+
+struct Tune {
+  int tp;        // z-pencils per workgroup in the z passes
+  int zthreads;  // threads per workgroup in the z passes
+  int cc;        // column chunk in the xy pass
+  int xythreads; // threads per workgroup in the xy pass
+};
+
+// ---- matvec passes (kernels.hip) ----------------------------------------
+// mode for the inverse z pass: 0 -> y = x - chi u ; 1 -> y = b - (x - chi u)
+template <typename T>
+hipError_t launch_matvec(const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
+                         void* U, const void* goct, const void* chi, const void* const tw[3],
+                         hipStream_t s);
+
+// ---- plan-time spectrum -----------------------------------------------------
+hipError_t launch_spectrum(const Geom& g, const double2* table_dev, double2* full_tmp, double2* goct64,
+                           float2* goct32, const double2* const tw64[3], hipStream_t s);
+
+// ---- contrast / rhs ---------------------------------------------------------
+hipError_t launch_contrast(long N, const double2* eps, double eps_b, double2* chi64, float2* chi32,
+                           int* bad_flag, hipStream_t s);
+hipError_t launch_rhs(long N, double scale, const double2* chi, const double2* einc, double2* b,
+                      hipStream_t s);
+
+// ---- Krylov building blocks (krylov.hip) -----------------------------------
+template <typename T>
+struct KrylovWork;
+
+// LDS budget the kernels may use per workgroup (queried once per device)
+size_t lds_budget(int device);
+
+}  // namespace vie

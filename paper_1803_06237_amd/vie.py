@@ -1,0 +1,192 @@
+"""Python binding of libvie.so: argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts torch
+device tensors to pointers and forwards the calls of include/vie.h.  If the
+library has not been built the import of ``lib()`` raises -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvie.so")
+
+VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENUMERIC, VIE_ESTATE, VIE_ENOTIMPL = \
+    0, -1, -2, -3, -4, -5, -6, -7
+VIE_FP64, VIE_WITH_FP32 = 0, 1
+
+_lib = None
+
+
+class VieError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vie error {code}: {msg}")
+        self.code = code
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("use_x0", ctypes.c_int),
+                ("precision", ctypes.c_int), ("inner_restart", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("inner_iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("matvecs", ctypes.c_int), ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double),
+                ("rel_res_est", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libvie.so (built by paper_1803_06237_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run python -m paper_1803_06237_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.vie_version.restype = ctypes.c_char_p
+        L.vie_last_error.restype = ctypes.c_char_p
+        L.vie_last_error.argtypes = [vp]
+        L.vie_green_table.argtypes = [ip, ctypes.c_double, vp, ctypes.c_int]
+        L.vie_plan.argtypes = [ctypes.POINTER(vp), ip, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_uint, vp]
+        L.vie_set_contrast.argtypes = [vp, vp]
+        L.vie_rhs.argtypes = [vp, vp, vp]
+        L.vie_matvec.argtypes = [vp, vp, vp]
+        L.vie_matvec_c64.argtypes = [vp, vp, vp]
+        L.vie_residual.argtypes = [vp, vp, vp, vp]
+        L.vie_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(SolveOpts),
+                                ctypes.POINTER(SolveInfo)]
+        L.vie_destroy.argtypes = [vp]
+        L.vie_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(code: int, plan=None):
+    if code != VIE_OK:
+        msg = lib().vie_last_error(plan).decode()
+        raise VieError(code, msg)
+
+
+def _grid(n: Sequence[int]):
+    return (ctypes.c_int * 3)(*[int(v) for v in n])
+
+
+def green_table(grid: Sequence[int], kappa: float, nthreads: int = 0) -> np.ndarray:
+    """Host FP64 Toeplitz table N^{ab}(m), shape (6, n1, n2, n3), components xx xy xz yy yz zz."""
+    out = np.empty((6,) + tuple(int(v) for v in grid), dtype=np.complex128)
+    _check(lib().vie_green_table(_grid(grid), float(kappa), out.ctypes.data, int(nthreads)))
+    return out
+
+
+def _ptr(t, dtype, numel: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Operator I - M_eps N on one grid (see include/vie.h)."""
+
+    def __init__(self, grid: Sequence[int], h: float, k0: float, eps_b: float, fp32: bool = True,
+                 stream=None):
+        import torch
+        self.n = tuple(int(v) for v in grid)
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self.h, self.k0, self.eps_b = float(h), float(k0), float(eps_b)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        flags = VIE_WITH_FP32 if fp32 else VIE_FP64
+        code = lib().vie_plan(ctypes.byref(handle), _grid(self.n), self.h, self.k0, self.eps_b, flags,
+                              ctypes.c_void_p(stream.cuda_stream))
+        _check(code, None)
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vie_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_contrast(self, eps):
+        import torch
+        _check(lib().vie_set_contrast(self._h, _ptr(eps, torch.complex128, self.N, "eps")), self._h)
+
+    def rhs(self, e_inc, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(e_inc)
+        _check(lib().vie_rhs(self._h, _ptr(e_inc, torch.complex128, 3 * self.N, "e_inc"),
+                             _ptr(out, torch.complex128, 3 * self.N, "b")), self._h)
+        return out
+
+    def matvec(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().vie_matvec(self._h, _ptr(x, torch.complex128, 3 * self.N, "x"),
+                                _ptr(y, torch.complex128, 3 * self.N, "y")), self._h)
+        return y
+
+    def matvec_c64(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().vie_matvec_c64(self._h, _ptr(x, torch.complex64, 3 * self.N, "x"),
+                                    _ptr(y, torch.complex64, 3 * self.N, "y")), self._h)
+        return y
+
+    def residual(self, x, b, r=None):
+        import torch
+        if r is None:
+            r = torch.empty_like(b)
+        _check(lib().vie_residual(self._h, _ptr(x, torch.complex128, 3 * self.N, "x"),
+                                  _ptr(b, torch.complex128, 3 * self.N, "b"),
+                                  _ptr(r, torch.complex128, 3 * self.N, "r")), self._h)
+        return r
+
+    def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000,
+              precision: int = 0, use_x0: bool = False, inner_restart: int = 20,
+              inner_tol: float = 1e-4, raise_on_noconv: bool = False):
+        """GMRES(restart) (precision 0) or FP32-inner / FP64-outer FGMRES (precision 1).
+
+        Returns (x, info dict).  info['status'] is VIE_OK or VIE_ENOCONV."""
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        opts = SolveOpts(int(restart), int(maxit), int(bool(use_x0)), int(precision), int(inner_restart),
+                         float(inner_tol))
+        info = SolveInfo()
+        code = lib().vie_solve(self._h, _ptr(b, torch.complex128, 3 * self.N, "b"),
+                               _ptr(x, torch.complex128, 3 * self.N, "x"), float(tol), ctypes.byref(opts),
+                               ctypes.byref(info))
+        if code not in (VIE_OK, VIE_ENOCONV) or (raise_on_noconv and code != VIE_OK):
+            _check(code, self._h)
+        return x, info.as_dict()

@@ -1,0 +1,198 @@
+"""GPU parity of the matvec y = (I - M_eps N) x against the oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import green, matvec as mv
+from paper_1803_06237_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1803_06237_amd import vie
+    vie.lib()
+    return vie
+
+
+def _cvec(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _t(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t if dtype is None else t.to(dtype)
+
+
+H, K0, EPSB = 0.05, inputs.K0, inputs.EPS_B
+
+# grids spanning several tiles and ragged tails (pencils per workgroup, column
+# chunks, non-power-of-two n in every axis), plus the degenerate single voxel
+GRIDS = [(8, 8, 32), (5, 7, 37), (3, 32, 20), (12, 20, 24), (2, 3, 4), (1, 1, 1), (1, 1, 9), (32, 1, 3)]
+
+
+@pytest.fixture(scope="module", params=GRIDS, ids=lambda g: "x".join(map(str, g)))
+def case(request):
+    vie = _dev()
+    n = request.param
+    rng = np.random.default_rng(sum(n))
+    kap = mv.kappa_of(H, K0, EPSB)
+    table = green.green_table(n, kap)
+    spec = mv.spectrum(table)
+    eps = EPSB + 10 * rng.random(n) + 1j * rng.random(n)
+    eps[rng.random(n) < 0.3] = EPSB          # background voxels: zero contrast
+    chi = mv.contrast(eps, EPSB)
+    plan = vie.Plan(n, H, K0, EPSB, fp32=True)
+    plan.set_contrast(_t(eps))
+    return dict(n=n, rng=rng, spec=spec, chi=chi, eps=eps, plan=plan, table=table)
+
+
+def test_fp64_matvec_matches_oracle(case):
+    n, rng = case["n"], case["rng"]
+    x = _cvec(rng, (3,) + n)
+    want = mv.matvec_fft(case["spec"], case["chi"], x)
+    got = case["plan"].matvec(_t(x)).cpu().numpy()
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"grid {n} fp64 rel err {err:.3e}")
+    assert err < 1e-12
+
+
+def test_fp32_matvec_matches_oracle(case):
+    n, rng = case["n"], case["rng"]
+    x = _cvec(rng, (3,) + n)
+    want = mv.matvec_fft(case["spec"], case["chi"], x)
+    got = case["plan"].matvec_c64(_t(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"grid {n} fp32 rel err {err:.3e}")
+    assert err < 5e-6
+
+
+def test_residual_variant_is_b_minus_matvec(case):
+    n, rng = case["n"], case["rng"]
+    x, b = _cvec(rng, (3,) + n), _cvec(rng, (3,) + n)
+    p = case["plan"]
+    xt, bt = _t(x), _t(b)
+    y = p.matvec(xt)
+    r = p.residual(xt, bt)
+    assert torch.equal(r, bt - y)
+
+
+def test_zero_contrast_is_identity_and_runs_are_deterministic(case):
+    vie = _dev()
+    n, rng = case["n"], case["rng"]
+    p = vie.Plan(n, H, K0, EPSB, fp32=False)
+    p.set_contrast(_t(np.full(n, EPSB, dtype=np.complex128)))
+    x = _t(_cvec(rng, (3,) + n))
+    assert torch.equal(p.matvec(x), x)
+    y1 = case["plan"].matvec(x)
+    y2 = case["plan"].matvec(x)
+    assert torch.equal(y1, y2)
+
+
+def test_rhs_is_projected_contrast_times_field(case):
+    n, rng = case["n"], case["rng"]
+    e = _cvec(rng, (3,) + n)
+    want = mv.rhs_from_field(case["eps"], EPSB, e, H)
+    got = case["plan"].rhs(_t(e)).cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 4e-16 * np.max(np.abs(want))
+
+
+def test_bad_contrast_is_rejected():
+    vie = _dev()
+    p = vie.Plan((2, 2, 2), H, K0, EPSB, fp32=False)
+    eps = np.full((2, 2, 2), 12.0 + 0j)
+    eps[1, 0, 1] = np.nan
+    with pytest.raises(vie.VieError) as ei:
+        p.set_contrast(_t(eps))
+    assert ei.value.code == vie.VIE_EINVAL
+    x = _t(np.zeros((3, 2, 2, 2), complex))
+    with pytest.raises(vie.VieError) as ei:
+        p.matvec(x)
+    assert ei.value.code == vie.VIE_ESTATE
+
+
+def _sparse_sample_check(vie, wg, nnz, nout, precision, seed):
+    """Full-size operator: x has nnz random non-zeros; nout outputs (half in the core)
+    are recomputed by the oracle from the Galerkin entries at the needed offsets."""
+    n = wg.n
+    rng = np.random.default_rng(seed)
+    kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+    eps = wg.eps()
+    chi = mv.contrast(eps, wg.eps_b)
+    plan = vie.Plan(n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    plan.set_contrast(_t(eps))
+    x = np.zeros((3,) + n, complex)
+    src = np.stack([rng.integers(0, n[d], nnz) for d in range(3)], 1)
+    comp = rng.integers(0, 3, nnz)
+    vals = _cvec(rng, nnz)
+    for s, c, v in zip(src, comp, vals):
+        x[(c,) + tuple(s)] += v
+    if precision == 64:
+        y = plan.matvec(_t(x)).cpu().numpy()
+    else:
+        y = plan.matvec_c64(_t(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    core = np.argwhere(wg.core_mask())
+    outs = np.concatenate([core[rng.integers(0, len(core), nout // 2)],
+                           np.stack([rng.integers(0, n[d], nout - nout // 2) for d in range(3)], 1)])
+    offs = (outs[:, None, :] - src[None, :, :]).reshape(-1, 3)
+    Nab = green.galerkin_N(offs, kap).reshape(6, len(outs), nnz)
+    full = {}
+    for ci, (a, b) in enumerate(green.COMPONENTS):
+        full[(a, b)] = full[(b, a)] = Nab[ci]
+    # per-offset parity is handled by integrating at the signed offsets directly
+    want = np.empty((len(outs), 3), complex)
+    for a in range(3):
+        Nx = np.zeros(len(outs), complex)
+        for b in range(3):
+            Nx += (full[(a, b)] * np.where(comp == b, vals, 0)[None, :]).sum(axis=1)
+        i = tuple(outs.T)
+        want[:, a] = x[(a,) + i] - chi[i] * Nx
+    got = np.stack([y[(a,) + tuple(outs.T)] for a in range(3)], 1)
+    return np.max(np.abs(got - want)) / np.max(np.abs(want))
+
+
+def test_full_size_long_guide_sampled_outputs():
+    """32 x 32 x 512, h = 25 nm, quadratic absorbers of 80 voxels: the bench workload."""
+    vie = _dev()
+    wg = inputs.strip_long(d=2)
+    err64 = _sparse_sample_check(vie, wg, nnz=24, nout=64, precision=64, seed=1)
+    err32 = _sparse_sample_check(vie, wg, nnz=24, nout=64, precision=32, seed=2)
+    print(f"32x32x512 sampled: fp64 {err64:.3e} fp32 {err32:.3e}")
+    assert err64 < 1e-12
+    assert err32 < 5e-6
+
+
+def test_full_size_family_grid_sampled_outputs():
+    """32 x 32 x 832: the longest absorber-family grid (circulant length 2048 along z)."""
+    vie = _dev()
+    wg = inputs.strip_family(8.0, 3)
+    err64 = _sparse_sample_check(vie, wg, nnz=16, nout=48, precision=64, seed=3)
+    print(f"32x32x832 sampled: fp64 {err64:.3e}")
+    assert err64 < 1e-12
+
+
+def test_maximum_grid_runs():
+    """n3 = 2048 (circulant 4096): the largest supported length."""
+    vie = _dev()
+    n = (4, 4, 2048)
+    p = vie.Plan(n, H, K0, EPSB, fp32=True)
+    eps = np.full(n, 12.11 + 0.5j)
+    p.set_contrast(_t(eps))
+    rng = np.random.default_rng(9)
+    x = np.zeros((3,) + n, complex)
+    x[1, 2, 1, 2047] = 1.0
+    y = p.matvec(_t(x)).cpu().numpy()
+    kap = mv.kappa_of(H, K0, EPSB)
+    chi = mv.contrast(eps, EPSB)
+    outs = np.array([[0, 0, 0], [2, 1, 2047], [3, 3, 1000], [1, 0, 5]])
+    for o in outs:
+        off = (o - np.array([2, 1, 2047]))[None]
+        Nab = green.galerkin_N(off, kap)[:, 0]
+        for a, ci in ((0, 1), (1, 3), (2, 4)):      # column b = 1: xy, yy, yz
+            want = x[(a,) + tuple(o)] - chi[tuple(o)] * Nab[ci]
+            assert abs(y[(a,) + tuple(o)] - want) < 1e-13

@@ -1,0 +1,105 @@
+"""GPU GMRES solves judged by the oracle: the oracle recomputes the residual of the
+GPU solution with its own matvec (several solutions are correct; the residual is
+what is unique)."""
+import numpy as np
+import pytest
+
+from oracle import green, matvec as mv, solve
+from paper_1803_06237_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1803_06237_amd import vie
+    vie.lib()
+    return vie
+
+
+@pytest.fixture(scope="module")
+def small_strip():
+    """8 x 8 x 32, h = 50 nm, 4 x 4 core, 8-voxel quadratic absorbers, sigma_max = 2."""
+    vie = _dev()
+    wg = inputs.strip_small(d=2)
+    kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+    op = mv.Operator(green.green_table(wg.n, kap), mv.contrast(wg.eps(), wg.eps_b))
+    plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+    e_inc = inputs.strip_small_dipole_rhs_field(wg)
+    b_dip = mv.rhs_from_field(wg.eps(), wg.eps_b, e_inc, wg.h)
+    b_gau = inputs.gaussian_rhs(wg.n, 0)
+    return wg, op, plan, b_dip, b_gau, e_inc
+
+
+def _oracle_rel_res(op, b, x):
+    return np.linalg.norm(b.ravel() - op(x.ravel())) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("rhs", ["dipole", "gaussian"])
+@pytest.mark.parametrize("restart", [50, 400])
+def test_fp64_gmres(small_strip, rhs, restart):
+    wg, op, plan, b_dip, b_gau, _ = small_strip
+    b = b_dip if rhs == "dipole" else b_gau
+    x, info = plan.solve(torch.from_numpy(b).cuda(), tol=1e-8, restart=restart)
+    rr = _oracle_rel_res(op, b, x.cpu().numpy())
+    print(rhs, restart, info, "oracle rel res", rr)
+    assert info["status"] == 0
+    assert info["rel_res_true"] <= 1e-8
+    assert rr <= 1.01e-8
+
+
+def test_gpu_rhs_builds_the_same_system(small_strip):
+    wg, op, plan, b_dip, _, e_inc = small_strip
+    b = plan.rhs(torch.from_numpy(e_inc).cuda())
+    assert np.max(np.abs(b.cpu().numpy() - b_dip)) <= 4e-16 * np.max(np.abs(b_dip))
+
+
+def test_mixed_precision_reaches_fp64_tolerance(small_strip):
+    wg, op, plan, b_dip, b_gau, _ = small_strip
+    for b in (b_dip, b_gau):
+        x, info = plan.solve(torch.from_numpy(b).cuda(), tol=1e-8, restart=30, precision=1,
+                             inner_restart=20, inner_tol=1e-4)
+        rr = _oracle_rel_res(op, b, x.cpu().numpy())
+        print("mixed", info, "oracle rel res", rr)
+        assert info["status"] == 0 and rr <= 1.01e-8
+        assert info["inner_iters"] > 0
+
+
+def test_solution_matches_dense_lu_within_conditioning():
+    vie = _dev()
+    wg = inputs.Waveguide(n=(4, 4, 12), h=0.05, core_x=(1, 3), core_y=(1, 3), core_z=(0, 12), n_abs=3,
+                          d=1, sigma_max=2.0)
+    kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+    T = green.green_table(wg.n, kap)
+    chi = mv.contrast(wg.eps(), wg.eps_b)
+    A = mv.dense_A(T, chi)
+    b = inputs.gaussian_rhs(wg.n, 7)
+    x_lu = solve.solve_lu(A, b.ravel())
+    plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=False)
+    plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+    x, info = plan.solve(torch.from_numpy(b).cuda(), tol=1e-10, restart=200)
+    err = np.linalg.norm(x.cpu().numpy().ravel() - x_lu) / np.linalg.norm(x_lu)
+    assert err < 10 * np.linalg.cond(A) * 1e-10
+
+
+def test_zero_rhs_and_warm_start(small_strip):
+    wg, op, plan, b_dip, _, _ = small_strip
+    z = torch.zeros((3,) + wg.n, dtype=torch.complex128, device="cuda")
+    x, info = plan.solve(z, tol=1e-8)
+    assert info["status"] == 0 and torch.count_nonzero(x) == 0
+    b = torch.from_numpy(b_dip).cuda()
+    x1, i1 = plan.solve(b, tol=1e-8)
+    x2, i2 = plan.solve(b, x=x1.clone(), tol=1e-8, use_x0=True)
+    assert i2["iters"] == 0 and i2["status"] == 0
+
+
+def test_maxit_reports_noconv_with_best_iterate(small_strip):
+    vie = _dev()
+    wg, op, plan, _, b_gau, _ = small_strip
+    x, info = plan.solve(torch.from_numpy(b_gau).cuda(), tol=1e-14, restart=5, maxit=5)
+    assert info["status"] == vie.VIE_ENOCONV
+    rr = _oracle_rel_res(op, b_gau, x.cpu().numpy())
+    assert rr < 1.0 and abs(rr - info["rel_res_true"]) < 1e-10
