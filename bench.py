@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the voxel J-VIE hot path on one MI355X.
+
+A step is one FP64 product y = (I - M_eps N) x on the 32 x 32 x 512 voxel
+waveguide (1.57 M unknowns, h = 25 nm, 500 x 225 nm silicon core in silica,
+quadratic absorbers of 2 um at both ends): forward z FFT, xy FFT with the fused
+Green product, inverse z FFT with the fused contrast.  Inputs are resident in
+HBM before the timed region.  After the timed steps the same operator is solved
+to a relative residual of 1e-8 from a dipole source with FP64 GMRES(50) and with
+the FP32-inner / FP64-outer flexible GMRES, and the oracle's FFT matvec is timed
+on the host as the CPU baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "VIE matvecs/s + HBM %peak; time-to-1e-8 residual: mixed/learned vs FP64"
+
+
+def pass_bytes(n, M, cs):
+    """Algorithmic HBM bytes of the three passes for complex element size cs."""
+    n1, n2, n3 = n
+    M1, M2, M3 = M
+    N = n1 * n2 * n3
+    U = 3 * n1 * n2 * M3 * cs
+    G = 6 * (M1 // 2 + 1) * (M2 // 2 + 1) * (M3 // 2 + 1) * cs
+    return [3 * N * cs + U,                      # pass 1: read x, write U
+            2 * U + G,                           # pass 2: read/write U, read spectrum octant
+            U + 3 * N * cs + N * cs + 3 * N * cs]  # pass 3: read U, x, chi; write y
+
+
+def circulant(n):
+    out = []
+    for v in n:
+        m = 1
+        while m < 2 * v - 1:
+            m *= 2
+        out.append(m)
+    return tuple(out)
+
+
+def cpu_baseline(n, seconds_budget=30.0):
+    """The oracle's FFT matvec at the same grid, host cores, bounded sample."""
+    import numpy as np
+
+    from oracle import matvec as mv
+    rng = np.random.default_rng(0)
+    M = tuple(2 * v for v in n)
+    spec = rng.standard_normal((6,) + M) + 1j * rng.standard_normal((6,) + M)
+    chi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x = rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)
+    t0 = time.perf_counter()
+    runs = 0
+    while True:
+        mv.matvec_fft(spec, chi, x)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el > seconds_budget / 2 or runs >= 3:
+            break
+    return {"value": runs / el, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{runs} oracle FFT matvec(s) at {n[0]}x{n[1]}x{n[2]} (own radix-2 FFT, numpy, "
+                      f"one thread) with a synthetic spectrum of the full circulant shape; table build excluded; "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver in this build is "
+              "single-GPU; see DESIGN.md for how the path would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1803_06237_amd import inputs, vie
+    torch.cuda.set_device(0)
+    wg = inputs.strip_long(d=2)
+    n = wg.n
+    M = circulant(n)
+    t0 = time.perf_counter()
+    plan = vie.Plan(n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    plan_s = time.perf_counter() - t0
+    plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+    rng = np.random.default_rng(0)
+    xh = rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)
+    x = torch.from_numpy(xh).cuda()
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        plan.matvec(x, y)
+    torch.cuda.synchronize()
+    # timed region: K FP64 products, HIP events around each pass on the plan's stream
+    t0 = time.perf_counter()
+    pass_ms, tot_ms = plan.profile_matvec(x, y, args.steps, precision=0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = el / args.steps * 1e3
+    value = args.steps / el
+
+    b64 = pass_bytes(n, M, 16)
+    names = ["k_zfwd<double>", "k_xy64<double>" if M[0] == 64 and M[1] == 64 else "k_xyg<double>", "k_zinv<double,0>"]
+    dom = int(np.argmax(pass_ms))
+    achieved = b64[dom] / (pass_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[dom],
+                "algorithmic_bytes": b64[dom], "avg_ms": round(pass_ms[dom], 5)}
+    passes = {names[i]: {"avg_us": round(pass_ms[i] * 1e3, 2), "bytes": b64[i],
+                         "GBs": round(b64[i] / (pass_ms[i] * 1e-3) / 1e9, 1)} for i in range(3)}
+    matvec_bytes = sum(b64)
+
+    # FP32 product (mixed tier inner operator)
+    x32 = x.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    for _ in range(args.warmup):
+        plan.matvec_c64(x32, y32)
+    torch.cuda.synchronize()
+    p32, t32 = plan.profile_matvec(x32, y32, max(20, args.steps // 2), precision=1)
+    b32 = pass_bytes(n, M, 8)
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "matvecs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "32x32x512 voxel J-VIE matvec (1.57M unknowns), h=25nm, 20x9-voxel Si core "
+                                  "in SiO2, quadratic absorbers 80 voxels each end, FP64",
+                      "grid": list(n), "circulant": list(M), "unknowns": 3 * wg.N, "parallelism": "1 GPU"},
+           "roofline": roofline,
+           "matvec_hbm": {"modelled_bytes": matvec_bytes,
+                          "GBs": round(matvec_bytes / (tot_ms * 1e-3) / 1e9, 1),
+                          "frac": round(matvec_bytes / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+           "passes": passes,
+           "fp32_matvec": {"matvecs_per_s": round(1e3 / t32, 1), "avg_us": round(t32 * 1e3, 2),
+                           "GBs": round(sum(b32) / (t32 * 1e-3) / 1e9, 1),
+                           "passes_us": [round(v * 1e3, 2) for v in p32]},
+           "plan_seconds": round(plan_s, 3)}
+
+    if not args.no_solve:
+        e_inc = inputs.transverse_dipole_field(wg)
+        b = plan.rhs(torch.from_numpy(e_inc).cuda())
+        res = {}
+        for name, prec in (("fp64_gmres50", 0), ("mixed_fgmres", 1)):
+            plan.solve(b, tol=1e-8, restart=50, maxit=200, precision=prec)   # warm (allocations)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs, info = plan.solve(b, tol=1e-8, restart=50, maxit=20000, precision=prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            its = info["iters"] + info["inner_iters"]
+            res[name] = {"seconds": round(dt, 4), "outer_iters": info["iters"],
+                         "inner_iters": info["inner_iters"], "rel_res_true_fp64": info["rel_res_true"],
+                         "status": info["status"],
+                         "unknown_iterations_per_s": round(3 * wg.N * its / dt, 1)}
+        res["mixed_speedup_vs_fp64"] = round(res["fp64_gmres50"]["seconds"] / res["mixed_fgmres"]["seconds"], 3)
+        out["solve_to_1e-8"] = res
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -149,6 +149,17 @@ typedef struct {
 int vie_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol,
               const vie_solve_opts* opts, vie_solve_info* info);
 
+/*
+ * vie_profile_matvec -- diagnostic.  Runs `reps` products y = (I - M_eps N) x on the
+ * plan's stream (precision 0: FP64 on vie_c128 vectors; 1: FP32 on vie_c64) with HIP
+ * events around each of the three passes (0: forward z FFT; 1: xy FFT + Green
+ * product + inverse xy FFT; 2: inverse z FFT + crop + contrast).  pass_ms[3]
+ * receives each pass's average duration in milliseconds and *total_ms (may be
+ * NULL) the average per product.  x, y device, 3N values, no overlap.  Synchronises.
+ */
+int vie_profile_matvec(vie_plan_t plan, int precision, const void* x, void* y, int reps, double pass_ms[3],
+                       double* total_ms);
+
 /* Message for the last failing call on this plan (plan = NULL: on this thread). */
 const char* vie_last_error(vie_plan_t plan);
 

@@ -24,6 +24,11 @@
 
 namespace vie {
 
+template <typename T>
+hipError_t launch_xy64(const Geom& g, void* U, const void* goct, const void* tw1, hipStream_t s);
+template <typename T>
+hipError_t allow_lds_xy64();
+
 constexpr int kMaxV = 16;   // complex values per thread per FFT stage
 
 // ------------------------------------------------------------------ pass 1
@@ -166,25 +171,43 @@ size_t xy_lds_bytes(const Geom& g, int cc) {
 }
 
 template <typename T>
-hipError_t launch_matvec(const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
-                         void* U, const void* goct, const void* chi, const void* const tw[3],
-                         hipStream_t s) {
+hipError_t launch_pass(int which, const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
+                       void* U, const void* goct, const void* chi, const void* const tw[3], hipStream_t s) {
   using C = cx<T>;
   const int nb1 = (g.n1 + t.tp - 1) / t.tp;
   const dim3 gz(3 * g.n2 * nb1);
   const size_t zl = z_lds_bytes<T>(g, t.tp);
-  hipLaunchKernelGGL((k_zfwd<T>), gz, dim3(t.zthreads), zl, s, (const C*)x, (C*)U, g, t.tp, (const C*)tw[2]);
-  hipLaunchKernelGGL((k_xyg<T>), dim3(g.M3), dim3(t.xythreads), xy_lds_bytes<T>(g, t.cc), s, (C*)U,
-                     (const C*)goct, g, t.cc, (const C*)tw[0], (const C*)tw[1]);
-  if (mode == 0)
+  if (which == 0) {
+    hipLaunchKernelGGL((k_zfwd<T>), gz, dim3(t.zthreads), zl, s, (const C*)x, (C*)U, g, t.tp, (const C*)tw[2]);
+  } else if (which == 1 && g.M1 == 64 && g.M2 == 64) {
+    return launch_xy64<T>(g, U, goct, tw[0], s);
+  } else if (which == 1) {
+    hipLaunchKernelGGL((k_xyg<T>), dim3(g.M3), dim3(t.xythreads), xy_lds_bytes<T>(g, t.cc), s, (C*)U,
+                       (const C*)goct, g, t.cc, (const C*)tw[0], (const C*)tw[1]);
+  } else if (mode == 0) {
     hipLaunchKernelGGL((k_zinv<T, 0>), gz, dim3(t.zthreads), zl, s, (const C*)U, (const C*)x, (C*)y,
                        (const C*)nullptr, (const C*)chi, g, t.tp, (const C*)tw[2]);
-  else
+  } else {
     hipLaunchKernelGGL((k_zinv<T, 1>), gz, dim3(t.zthreads), zl, s, (const C*)U, (const C*)x, (C*)y,
                        (const C*)b, (const C*)chi, g, t.tp, (const C*)tw[2]);
+  }
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_matvec(const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
+                         void* U, const void* goct, const void* chi, const void* const tw[3],
+                         hipStream_t s) {
+  hipError_t e;
+  for (int which = 0; which < 3; ++which)
+    if ((e = launch_pass<T>(which, g, t, x, y, b, mode, U, goct, chi, tw, s))) return e;
+  return hipSuccess;
+}
+
+template hipError_t launch_pass<double>(int, const Geom&, const Tune&, const void*, void*, const void*, int, void*,
+                                        const void*, const void*, const void* const[3], hipStream_t);
+template hipError_t launch_pass<float>(int, const Geom&, const Tune&, const void*, void*, const void*, int, void*,
+                                       const void*, const void*, const void* const[3], hipStream_t);
 template hipError_t launch_matvec<double>(const Geom&, const Tune&, const void*, void*, const void*, int, void*,
                                           const void*, const void*, const void* const[3], hipStream_t);
 template hipError_t launch_matvec<float>(const Geom&, const Tune&, const void*, void*, const void*, int, void*,
@@ -200,6 +223,7 @@ hipError_t allow_lds(size_t bytes) {
     return e;
   if ((e = hipFuncSetAttribute((const void*)k_zinv<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)))
     return e;
+  if ((e = allow_lds_xy64<T>())) return e;
   return hipFuncSetAttribute((const void*)k_xyg<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 template hipError_t allow_lds<double>(size_t);

@@ -536,6 +536,47 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
   return status;
 }
 
+int vie_profile_matvec(vie_plan_t p, int precision, const void* x, void* y, int reps, double pass_ms[3],
+                       double* total_ms) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!x || !y || x == y || reps < 1 || !pass_ms) return fail(p, VIE_EINVAL, "bad arguments");
+  if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
+  if (precision == 1 && !p->goct32) return fail(p, VIE_ESTATE, "plan built without VIE_WITH_FP32");
+  if (precision != 0 && precision != 1) return fail(p, VIE_EINVAL, "precision must be 0 or 1");
+  std::vector<hipEvent_t> ev((size_t)reps * 4);
+  for (auto& e : ev) HIPTRY(p, hipEventCreate(&e));
+  const void* tw64[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+  const void* tw32[3] = {p->tw32[0], p->tw32[1], p->tw32[2]};
+  for (int r = 0; r < reps; ++r) {
+    HIPTRY(p, hipEventRecord(ev[4 * r], p->stream));
+    for (int w = 0; w < 3; ++w) {
+      if (precision == 0)
+        HIPTRY(p, launch_pass<double>(w, p->g, p->t64, x, y, nullptr, 0, p->U64, p->goct64, p->chi64, tw64,
+                                      p->stream));
+      else
+        HIPTRY(p, launch_pass<float>(w, p->g, p->t32, x, y, nullptr, 0, p->U32, p->goct32, p->chi32, tw32,
+                                     p->stream));
+      HIPTRY(p, hipEventRecord(ev[4 * r + w + 1], p->stream));
+    }
+  }
+  HIPTRY(p, hipStreamSynchronize(p->stream));
+  double acc[3] = {0, 0, 0}, tot = 0;
+  for (int r = 0; r < reps; ++r) {
+    for (int w = 0; w < 3; ++w) {
+      float ms = 0;
+      HIPTRY(p, hipEventElapsedTime(&ms, ev[4 * r + w], ev[4 * r + w + 1]));
+      acc[w] += ms;
+    }
+    float ms = 0;
+    HIPTRY(p, hipEventElapsedTime(&ms, ev[4 * r], ev[4 * r + 3]));
+    tot += ms;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  for (int w = 0; w < 3; ++w) pass_ms[w] = acc[w] / reps;
+  if (total_ms) *total_ms = tot / reps;
+  return VIE_OK;
+}
+
 void vie_destroy(vie_plan_t p) {
   if (!p) return;
   p->ws64.release();

@@ -33,6 +33,11 @@ hipError_t launch_matvec(const Geom& g, const Tune& t, const void* x, void* y, c
                          void* U, const void* goct, const void* chi, const void* const tw[3],
                          hipStream_t s);
 
+// one of the three passes (0: forward z, 1: xy + Green, 2: inverse z + contrast)
+template <typename T>
+hipError_t launch_pass(int which, const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
+                       void* U, const void* goct, const void* chi, const void* const tw[3], hipStream_t s);
+
 // ---- plan-time spectrum -----------------------------------------------------
 hipError_t launch_spectrum(const Geom& g, const double2* table_dev, double2* full_tmp, double2* goct64,
                            float2* goct32, const double2* const tw64[3], hipStream_t s);

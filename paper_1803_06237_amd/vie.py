@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
         L.vie_residual.argtypes = [vp, vp, vp, vp]
         L.vie_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(SolveOpts),
                                 ctypes.POINTER(SolveInfo)]
+        L.vie_profile_matvec.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.vie_destroy.argtypes = [vp]
         L.vie_destroy.restype = None
         _lib = L
@@ -171,6 +173,17 @@ class Plan:
                                   _ptr(b, torch.complex128, 3 * self.N, "b"),
                                   _ptr(r, torch.complex128, 3 * self.N, "r")), self._h)
         return r
+
+    def profile_matvec(self, x, y, reps: int, precision: int = 0):
+        """Average per-pass and per-product durations (ms) over reps products, HIP events."""
+        import torch
+        dt = torch.complex128 if precision == 0 else torch.complex64
+        ms = (ctypes.c_double * 3)()
+        tot = ctypes.c_double()
+        _check(lib().vie_profile_matvec(self._h, int(precision), _ptr(x, dt, 3 * self.N, "x"),
+                                        _ptr(y, dt, 3 * self.N, "y"), int(reps), ms, ctypes.byref(tot)),
+               self._h)
+        return list(ms), tot.value
 
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000,
               precision: int = 0, use_x0: bool = False, inner_restart: int = 20,
