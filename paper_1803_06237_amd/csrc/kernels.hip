@@ -28,6 +28,11 @@ template <typename T>
 hipError_t launch_xy64(const Geom& g, void* U, const void* goct, const void* tw1, hipStream_t s);
 template <typename T>
 hipError_t allow_lds_xy64();
+template <typename T>
+hipError_t launch_z4(int which, const Geom& g, const void* x, void* y, const void* b, int mode, void* U,
+                     const void* chi, const void* twz, hipStream_t st);
+template <typename T>
+hipError_t allow_lds_z4();
 
 constexpr int kMaxV = 16;   // complex values per thread per FFT stage
 
@@ -174,6 +179,7 @@ template <typename T>
 hipError_t launch_pass(int which, const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
                        void* U, const void* goct, const void* chi, const void* const tw[3], hipStream_t s) {
   using C = cx<T>;
+  if (which != 1 && t.z4) return launch_z4<T>(which, g, x, y, b, mode, U, chi, tw[2], s);
   const int nb1 = (g.n1 + t.tp - 1) / t.tp;
   const dim3 gz(3 * g.n2 * nb1);
   const size_t zl = z_lds_bytes<T>(g, t.tp);
@@ -224,6 +230,7 @@ hipError_t allow_lds(size_t bytes) {
   if ((e = hipFuncSetAttribute((const void*)k_zinv<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)))
     return e;
   if ((e = allow_lds_xy64<T>())) return e;
+  if ((e = allow_lds_z4<T>())) return e;
   return hipFuncSetAttribute((const void*)k_xyg<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 template hipError_t allow_lds<double>(size_t);

@@ -153,6 +153,8 @@ bool pick_tune(const Geom& g, size_t budget, size_t zbudget, Tune* t) {
   if (xt < 256) xt = need >= 256 ? 256 : 64;
   if (xt > 1024) return false;
   t->xythreads = xt;
+  const size_t z4 = z4_lds_bytes<T>(g.M3);
+  t->z4 = (z4 > 0 && z4 <= budget) ? 1 : 0;
   return true;
 }
 

@@ -24,7 +24,11 @@ struct Tune {
   int zthreads;  // threads per workgroup in the z passes
   int cc;        // column chunk in the xy pass
   int xythreads; // threads per workgroup in the xy pass
+  int z4;        // 1: z passes use the register four-step kernels
 };
+
+template <typename T>
+size_t z4_lds_bytes(int M3);   // 0 when no four-step instance exists for M3
 
 // ---- matvec passes (kernels.hip) ----------------------------------------
 // mode for the inverse z pass: 0 -> y = x - chi u ; 1 -> y = b - (x - chi u)

@@ -15,6 +15,9 @@
 //          processed in two halves of kx so that the exchange of one half
 //          (3 components x 32 columns x 64) fits where the rows were kept.
 // Stage C: rows inverse, crop, store.
+// A workgroup transforms the two planes kz and M3 - kz one after the other: both
+// use the same slab of the folded Green spectrum, so the second reads it from L2
+// (workgroup 0 takes kz = 0 and M3/2, whose slabs are unpaired).
 // LDS: one region of 3 x 32 x 64 complex values (96 KiB FP64, 48 KiB FP32),
 // element (c, y, kx) at (c*32 + y)*64 + (kx ^ (y & 7)) so the column accesses
 // of 8 threads with consecutive y hit distinct banks.
@@ -52,13 +55,16 @@ __global__ __launch_bounds__(256) void k_xy64(cx<T>* __restrict__ U, const cx<T>
   const int tid = threadIdx.x;
   const int a = tid & 7;
   const int q = tid >> 3;                            // 0..31
-  const int kz = blockIdx.x;
   const int n1 = g.n1, n2 = g.n2;
-  cx<T>* P = U + (long)kz * 3 * n1 * n2;
   // W64^(a k), k = 0..7
   cx<T> w[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) w[k] = tw64[a * k];
+  const int half = g.M3 / 2;
+  const int nplanes = g.M3 == 1 ? 1 : 2;
+  for (int pi = 0; pi < nplanes; ++pi) {
+  const int kz = blockIdx.x == 0 ? (pi == 0 ? 0 : half) : (pi == 0 ? (int)blockIdx.x : g.M3 - (int)blockIdx.x);
+  cx<T>* P = U + (long)kz * 3 * n1 * n2;
 
   // ---------------- stage A: forward FFT along x for row y = q, all components
   cx<T> v[3][8];
@@ -206,12 +212,15 @@ __global__ __launch_bounds__(256) void k_xy64(cx<T>* __restrict__ U, const cx<T>
       }
     }
   }
+  __syncthreads();
+  }
 }
 
 template <typename T>
 hipError_t launch_xy64(const Geom& g, void* U, const void* goct, const void* tw1, hipStream_t s) {
   const size_t lds = (size_t)3 * 32 * 64 * sizeof(cx<T>);
-  hipLaunchKernelGGL((k_xy64<T>), dim3(g.M3), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
+  const int blocks = g.M3 == 1 ? 1 : g.M3 / 2;
+  hipLaunchKernelGGL((k_xy64<T>), dim3(blocks), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
                      (const cx<T>*)tw1);
   return hipGetLastError();
 }

@@ -1,0 +1,237 @@
+// Passes 1 and 3 of the matvec (zero-padded z FFT / inverse z FFT with crop and
+// contrast) as four-step transforms held in registers.
+//
+// Length M3 = A * B.  Each pencil is handled by A threads.  Thread a holds
+// x[a + A b] (b < B), takes a B-point DFT over b in registers, multiplies by
+// W_M3^(a k1), and one LDS exchange hands the values of frequency k1 of all A
+// threads to the thread that owns task k1 (tasks k1 = a + A t, t < B / A),
+// which finishes with an A-point DFT: X[k1 + B k2], k2 < A.  The inverse is the
+// same with conjugate twiddles.  The zero padding (x[n] = 0 for n >= n3) and
+// the crop (only n < n3 kept) come for free from the index ranges.
+//
+// A block handles P pencils of consecutive i1 at fixed (component, i2), so the
+// kz-plane-major intermediate U[kz][c][i2][i1] is written and read in runs of P
+// elements through an LDS staging array [kz][P + 1] (padded against bank
+// conflicts); the z-contiguous vectors x, y, chi are accessed directly.
+#include <hip/hip_runtime.h>
+
+#include "dft_reg.hpp"
+#include "vie_internal.hpp"
+
+namespace vie {
+
+namespace {
+// exchange slot of (pencil p, frequency k1, source thread a): rotated so that
+// the A reads of one thread and the A writes of one frequency hit distinct banks
+template <int A>
+__device__ __forceinline__ int xslot(int p, int M, int k1, int a) {
+  return p * M + k1 * A + ((a + k1) & (A - 1));
+}
+}  // namespace
+
+template <typename T, int A, int B>
+__global__ __launch_bounds__(256) void k_zfwd4(const cx<T>* __restrict__ x, cx<T>* __restrict__ U, Geom g,
+                                                int P, const cx<T>* __restrict__ tw) {
+  constexpr int M = A * B;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);     // M * (P + 1)
+  const int nb1 = (g.n1 + P - 1) / P;
+  int blk = blockIdx.x;
+  const int ib1 = blk % nb1;
+  blk /= nb1;
+  const int i2 = blk % g.n2;
+  const int c = blk / g.n2;
+  const int i1_0 = ib1 * P;
+  const int np = min(P, g.n1 - i1_0);
+  const int p = threadIdx.x / A, a = threadIdx.x % A;
+  const int ld = P + 1;
+  cx<T> v[B];
+  if (p < np) {
+    const cx<T>* src = x + (((long)c * g.n1 + i1_0 + p) * g.n2 + i2) * g.n3;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int n = a + A * b;
+      v[b] = (b < B / 2 && n < g.n3) ? src[n] : cx<T>{(T)0, (T)0};   // n >= M/2 >= n3 is padding
+    }
+    dft_reg<T, false, B>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < B; ++k1) v[k1] = cmul(v[k1], tw[a * k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < B; ++k1) S[xslot<A>(p, M, k1, a)] = v[k1];
+  }
+  __syncthreads();
+  if (p < np) {
+#pragma unroll
+    for (int t = 0; t < B / A; ++t) {
+      const int k1 = a + A * t;
+      cx<T> z[A];
+#pragma unroll
+      for (int j = 0; j < A; ++j) z[j] = S[xslot<A>(p, M, k1, j)];
+      dft_reg<T, false, A>(z);
+#pragma unroll
+      for (int k2 = 0; k2 < A; ++k2) v[t * A + k2] = z[k2];
+    }
+  }
+  __syncthreads();
+  if (p < np) {
+#pragma unroll
+    for (int t = 0; t < B / A; ++t)
+#pragma unroll
+      for (int k2 = 0; k2 < A; ++k2) S[(a + A * t + B * k2) * ld + p] = v[t * A + k2];
+  }
+  __syncthreads();
+  const long plane = 3L * g.n1 * g.n2;
+  cx<T>* dst = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;
+  for (int t = threadIdx.x; t < np * M; t += blockDim.x) {
+    const int pp = t % np, kz = t / np;
+    dst[kz * plane + pp] = S[kz * ld + pp];
+  }
+}
+
+template <typename T, int A, int B, int MODE>
+__global__ __launch_bounds__(256) void k_zinv4(const cx<T>* __restrict__ U, const cx<T>* __restrict__ x,
+                                                cx<T>* __restrict__ y, const cx<T>* __restrict__ bvec,
+                                                const cx<T>* __restrict__ chi, Geom g, int P,
+                                                const cx<T>* __restrict__ tw) {
+  constexpr int M = A * B;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);
+  const int nb1 = (g.n1 + P - 1) / P;
+  int blk = blockIdx.x;
+  const int ib1 = blk % nb1;
+  blk /= nb1;
+  const int i2 = blk % g.n2;
+  const int c = blk / g.n2;
+  const int i1_0 = ib1 * P;
+  const int np = min(P, g.n1 - i1_0);
+  const int p = threadIdx.x / A, a = threadIdx.x % A;
+  const int ld = P + 1;
+  const long plane = 3L * g.n1 * g.n2;
+  const cx<T>* src = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;
+  for (int t = threadIdx.x; t < np * M; t += blockDim.x) {
+    const int pp = t % np, kz = t / np;
+    S[kz * ld + pp] = src[kz * plane + pp];
+  }
+  __syncthreads();
+  cx<T> v[B];
+  if (p < np) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[b] = S[(a + A * b) * ld + p];
+    dft_reg<T, true, B>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < B; ++k1) v[k1] = cmulc(v[k1], tw[a * k1]);
+  }
+  __syncthreads();
+  if (p < np) {
+#pragma unroll
+    for (int k1 = 0; k1 < B; ++k1) S[xslot<A>(p, M, k1, a)] = v[k1];
+  }
+  __syncthreads();
+  if (p < np) {
+    const long vox = ((long)(i1_0 + p) * g.n2 + i2) * g.n3;
+    const long off = (long)c * g.N + vox;
+#pragma unroll
+    for (int t = 0; t < B / A; ++t) {
+      const int k1 = a + A * t;
+      cx<T> z[A];
+#pragma unroll
+      for (int j = 0; j < A; ++j) z[j] = S[xslot<A>(p, M, k1, j)];
+      dft_reg<T, true, A>(z);
+#pragma unroll
+      for (int k2 = 0; k2 < A; ++k2) {
+        const int n = k1 + B * k2;
+        if (k2 < A / 2 && n < g.n3) {   // n >= M/2 >= n3 is cropped
+          const cx<T> r = csub(x[off + n], cmul(chi[vox + n], z[k2]));
+          y[off + n] = MODE == 0 ? r : csub(bvec[off + n], r);
+        }
+      }
+    }
+  }
+}
+
+// Launch: returns hipErrorNotSupported when (M3, precision) has no four-step
+// instance, so the caller falls back to the generic LDS Stockham passes.
+template <typename T>
+struct ZShape {
+  int A, B, P;
+};
+
+template <typename T>
+static bool zshape(int M3, ZShape<T>* s) {
+  const bool dbl = sizeof(T) == 8;
+  if (M3 == 512) *s = {16, 32, dbl ? 8 : 16};
+  else if (M3 == 1024) *s = {32, 32, dbl ? 4 : 8};
+  else if (M3 == 2048 && !dbl) *s = {32, 64, 4};
+  else return false;
+  return true;
+}
+
+template <typename T>
+size_t z4_lds_bytes(int M3) {
+  ZShape<T> s;
+  if (!zshape<T>(M3, &s)) return 0;
+  return (size_t)M3 * (s.P + 1) * sizeof(cx<T>);
+}
+
+template <typename T>
+hipError_t launch_z4(int which, const Geom& g, const void* x, void* y, const void* b, int mode, void* U,
+                     const void* chi, const void* twz, hipStream_t st) {
+  using C = cx<T>;
+  ZShape<T> s;
+  if (!zshape<T>(g.M3, &s)) return hipErrorNotSupported;
+  const int nb1 = (g.n1 + s.P - 1) / s.P;
+  const dim3 grid(3 * g.n2 * nb1), block(s.A * s.P);
+  const size_t lds = (size_t)g.M3 * (s.P + 1) * sizeof(C);
+#define VIE_Z4(AA, BB)                                                                                        \
+  if (s.A == AA && s.B == BB) {                                                                               \
+    if (which == 0)                                                                                           \
+      hipLaunchKernelGGL((k_zfwd4<T, AA, BB>), grid, block, lds, st, (const C*)x, (C*)U, g, s.P, (const C*)twz); \
+    else if (mode == 0)                                                                                       \
+      hipLaunchKernelGGL((k_zinv4<T, AA, BB, 0>), grid, block, lds, st, (const C*)U, (const C*)x, (C*)y,      \
+                         (const C*)nullptr, (const C*)chi, g, s.P, (const C*)twz);                             \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_zinv4<T, AA, BB, 1>), grid, block, lds, st, (const C*)U, (const C*)x, (C*)y,      \
+                         (const C*)b, (const C*)chi, g, s.P, (const C*)twz);                                   \
+    return hipGetLastError();                                                                                 \
+  }
+  VIE_Z4(16, 32)
+  VIE_Z4(32, 32)
+  if constexpr (sizeof(T) == 4) {
+    VIE_Z4(32, 64)
+  }
+#undef VIE_Z4
+  return hipErrorNotSupported;
+}
+
+template <typename T>
+hipError_t allow_lds_z4() {
+  hipError_t e;
+  const int big = 160 * 1024;
+#define VIE_ALLOW(AA, BB)                                                                                   \
+  if ((e = hipFuncSetAttribute((const void*)k_zfwd4<T, AA, BB>, hipFuncAttributeMaxDynamicSharedMemorySize, big))) \
+    return e;                                                                                                 \
+  if ((e = hipFuncSetAttribute((const void*)k_zinv4<T, AA, BB, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,    \
+                               big)))                                                                         \
+    return e;                                                                                                 \
+  if ((e = hipFuncSetAttribute((const void*)k_zinv4<T, AA, BB, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,    \
+                               big)))                                                                         \
+    return e;
+  VIE_ALLOW(16, 32)
+  VIE_ALLOW(32, 32)
+  if constexpr (sizeof(T) == 4) {
+    VIE_ALLOW(32, 64)
+  }
+#undef VIE_ALLOW
+  return hipSuccess;
+}
+
+template hipError_t launch_z4<double>(int, const Geom&, const void*, void*, const void*, int, void*, const void*,
+                                      const void*, hipStream_t);
+template hipError_t launch_z4<float>(int, const Geom&, const void*, void*, const void*, int, void*, const void*,
+                                     const void*, hipStream_t);
+template hipError_t allow_lds_z4<double>();
+template hipError_t allow_lds_z4<float>();
+template size_t z4_lds_bytes<double>(int);
+template size_t z4_lds_bytes<float>(int);
+
+}  // namespace vie

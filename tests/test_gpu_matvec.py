@@ -32,8 +32,11 @@ def _t(a, dtype=None):
 H, K0, EPSB = 0.05, inputs.K0, inputs.EPS_B
 
 # grids spanning several tiles and ragged tails (pencils per workgroup, column
-# chunks, non-power-of-two n in every axis), plus the degenerate single voxel
-GRIDS = [(8, 8, 32), (5, 7, 37), (3, 32, 20), (12, 20, 24), (2, 3, 4), (1, 1, 1), (1, 1, 9), (32, 1, 3)]
+# chunks, every z-transform shape: circulant lengths 512, 1024, 2048 along z and
+# the 64 x 64 cross-section kernel via (17, 32, 6); non-power-of-two n in every
+# axis), plus the degenerate single voxel
+GRIDS = [(8, 8, 32), (5, 7, 37), (3, 32, 20), (12, 20, 24), (2, 3, 4), (1, 1, 1), (1, 1, 9), (32, 1, 3),
+         (3, 5, 200), (7, 1, 129), (2, 3, 300), (2, 2, 600), (17, 32, 6)]
 
 
 @pytest.fixture(scope="module", params=GRIDS, ids=lambda g: "x".join(map(str, g)))
