@@ -125,6 +125,7 @@ typedef struct {
   int precision;      /* 0: FP64 GMRES; 1: mixed (FP32 inner GMRES, FP64 outer FGMRES) */
   int inner_restart;  /* mixed tier: inner GMRES dimension; <= 0 -> 20 */
   double inner_tol;   /* mixed tier: inner relative tolerance; <= 0 -> 1e-4 */
+  int use_graph;      /* vie_solve_batch: 1 = capture one restart cycle as a HIP graph and replay it */
 } vie_solve_opts;
 
 typedef struct {
@@ -148,6 +149,25 @@ typedef struct {
  */
 int vie_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol,
               const vie_solve_opts* opts, vie_solve_info* info);
+
+/*
+ * vie_solve_batch -- `count` independent systems, each with its own plan (grids
+ * may differ), solved together: every Krylov kernel and every matvec pass covers
+ * all systems in one launch per kernel shape, the systems advance in lockstep,
+ * and a system that reaches tol is masked on the device for the rest of its
+ * restart cycle.  opts->precision 0: GMRES(restart); 1: FP64 flexible
+ * GMRES(restart) preconditioned by inner_restart FP32 GMRES steps (plans built
+ * with VIE_WITH_FP32).  With opts->use_graph one restart cycle is captured as a
+ * HIP graph and replayed.  rhs[s], x[s]: device, 3N_s values each, x[s] out
+ * (in with use_x0).  infos: host array of count entries or NULL.  Runs on a
+ * stream of its own after synchronising the first plan's stream; returns
+ * synchronised.  Returns VIE_OK when every system converged, else the first
+ * non-OK status (each system's status is in infos[s].status).  A plan may appear
+ * several times (same operator, different right-hand sides): each system gets
+ * its own intermediate buffers.
+ */
+int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* rhs, vie_c128* const* x, int count,
+                    double tol, const vie_solve_opts* opts, vie_solve_info* infos);
 
 /*
  * vie_profile_matvec -- diagnostic.  Runs `reps` products y = (I - M_eps N) x on the

@@ -33,6 +33,11 @@ hipError_t launch_z4(int which, const Geom& g, const void* x, void* y, const voi
                      const void* chi, const void* twz, hipStream_t st);
 template <typename T>
 hipError_t allow_lds_z4();
+template <typename T>
+hipError_t launch_z4_batch(int which, int mode, const PassDesc* d, const int* prefix, int nsys, int total, int A,
+                           int B, int P, int jx, int jy, hipStream_t st);
+template <typename T>
+hipError_t launch_xy64_batch(const PassDesc* d, const int* prefix, int nsys, int total, hipStream_t s);
 
 constexpr int kMaxV = 16;   // complex values per thread per FFT stage
 
@@ -209,6 +214,17 @@ hipError_t launch_matvec(const Geom& g, const Tune& t, const void* x, void* y, c
     if ((e = launch_pass<T>(which, g, t, x, y, b, mode, U, goct, chi, tw, s))) return e;
   return hipSuccess;
 }
+
+template <typename T>
+hipError_t launch_pass_batch(int which, int mode, const PassDesc* d, const int* prefix, int nsys, int total, int A,
+                             int B, int P, int jx, int jy, hipStream_t s) {
+  if (which == 1) return launch_xy64_batch<T>(d, prefix, nsys, total, s);
+  return launch_z4_batch<T>(which, mode, d, prefix, nsys, total, A, B, P, jx, jy, s);
+}
+template hipError_t launch_pass_batch<double>(int, int, const PassDesc*, const int*, int, int, int, int, int, int,
+                                              int, hipStream_t);
+template hipError_t launch_pass_batch<float>(int, int, const PassDesc*, const int*, int, int, int, int, int, int,
+                                             int, hipStream_t);
 
 template hipError_t launch_pass<double>(int, const Geom&, const Tune&, const void*, void*, const void*, int, void*,
                                         const void*, const void*, const void* const[3], hipStream_t);

@@ -302,6 +302,28 @@ int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, const cx<T>* b, cx<T>
 
 }  // namespace
 
+int vie::plan_export(vie_plan_t p, Geom* g, Tune* t64, Tune* t32, void** U64, void** U32, void** goct64,
+                     void** goct32, void** chi64, void** chi32, const void** tw64, const void** tw32,
+                     hipStream_t* stream, int* has_contrast) {
+  if (!p) return VIE_EINVAL;
+  *g = p->g;
+  *t64 = p->t64;
+  *t32 = p->t32;
+  *U64 = p->U64;
+  *U32 = p->U32;
+  *goct64 = p->goct64;
+  *goct32 = p->goct32;
+  *chi64 = p->chi64;
+  *chi32 = p->chi32;
+  for (int d = 0; d < 3; ++d) {
+    tw64[d] = p->tw64[d];
+    tw32[d] = p->tw32[d];
+  }
+  *stream = p->stream;
+  *has_contrast = p->has_contrast ? 1 : 0;
+  return VIE_OK;
+}
+
 size_t vie::lds_budget(int device) {
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
@@ -480,7 +502,7 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
   if (!b || !x || (const void*)b == (const void*)x) return fail(p, VIE_EINVAL, "b, x null or aliased");
   if (!(tol > 0) || !std::isfinite(tol)) return fail(p, VIE_EINVAL, "tol must be positive");
   if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
-  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4};
+  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4, 0};
   if (opts) o = *opts;
   if (o.restart <= 0) o.restart = 50;
   if (o.maxit <= 0) o.maxit = 10000;

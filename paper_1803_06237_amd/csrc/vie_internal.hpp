@@ -52,11 +52,49 @@ hipError_t launch_contrast(long N, const double2* eps, double eps_b, double2* ch
 hipError_t launch_rhs(long N, double scale, const double2* chi, const double2* einc, double2* b,
                       hipStream_t s);
 
+// ---- batched passes ---------------------------------------------------------
+// One system of a batch as seen by the batched pass kernels.  The vector
+// operands are xb + jx * xs and yb + jy * ys (elements), with (jx, jy) passed
+// to the launch, so one descriptor serves every Krylov step of a cycle.
+struct PassDesc {
+  Geom g;
+  const void* xb;
+  long xs;
+  void* yb;
+  long ys;
+  const void* b;        // residual mode: y = b - A x
+  void* U;
+  const void* goct;
+  const void* chi;
+  const void* twz;      // z twiddles, length M3
+  const void* twx;      // x twiddles, length M1
+  int P;                // pencils per workgroup in the z passes
+  const int* active;    // device flag; 0 skips the system (nullptr: always on)
+};
+
+// which: 0 forward z, 1 xy + Green, 2 inverse z (+ contrast; mode 1: residual).
+// items: prefix[s] = first item of system s (z passes: pencil blocks; xy pass:
+// plane pairs), prefix[nsys] = total.  All systems share (A, B) for the z passes.
+template <typename T>
+hipError_t launch_pass_batch(int which, int mode, const PassDesc* d, const int* prefix, int nsys, int total, int A,
+                             int B, int P, int jx, int jy, hipStream_t s);
+template <typename T>
+bool z4_shape(int M3, int* A, int* B, int* P);
+
 // ---- Krylov building blocks (krylov.hip) -----------------------------------
 template <typename T>
 struct KrylovWork;
 
 // LDS budget the kernels may use per workgroup (queried once per device)
 size_t lds_budget(int device);
+
+struct Tune;
+}  // namespace vie
+typedef struct vie_plan_s* vie_plan_t;
+namespace vie {
+// The parts of a plan the batched solver needs (vie_api.cpp).
+int plan_export(vie_plan_t p, Geom* g, Tune* t64, Tune* t32, void** U64, void** U32, void** goct64, void** goct32,
+                void** chi64, void** chi32, const void** tw64, const void** tw32, hipStream_t* stream,
+                int* has_contrast);
 
 }  // namespace vie

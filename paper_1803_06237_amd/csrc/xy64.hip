@@ -48,10 +48,8 @@ __device__ __forceinline__ void twiddle8(cx<T>* v, const cx<T>* w) {
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_xy64(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, Geom g,
-                                              const cx<T>* __restrict__ tw64) {
-  extern __shared__ unsigned char smem_raw[];
-  cx<T>* R = reinterpret_cast<cx<T>*>(smem_raw);   // 3 * 32 * 64
+__device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
+                                          const cx<T>* __restrict__ tw64, int blk, cx<T>* R) {
   const int tid = threadIdx.x;
   const int a = tid & 7;
   const int q = tid >> 3;                            // 0..31
@@ -63,7 +61,7 @@ __global__ __launch_bounds__(256) void k_xy64(cx<T>* __restrict__ U, const cx<T>
   const int half = g.M3 / 2;
   const int nplanes = g.M3 == 1 ? 1 : 2;
   for (int pi = 0; pi < nplanes; ++pi) {
-  const int kz = blockIdx.x == 0 ? (pi == 0 ? 0 : half) : (pi == 0 ? (int)blockIdx.x : g.M3 - (int)blockIdx.x);
+  const int kz = blk == 0 ? (pi == 0 ? 0 : half) : (pi == 0 ? blk : g.M3 - blk);
   cx<T>* P = U + (long)kz * 3 * n1 * n2;
 
   // ---------------- stage A: forward FFT along x for row y = q, all components
@@ -217,6 +215,42 @@ __global__ __launch_bounds__(256) void k_xy64(cx<T>* __restrict__ U, const cx<T>
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_xy64(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, Geom g,
+                                              const cx<T>* __restrict__ tw64) {
+  extern __shared__ unsigned char smem_raw[];
+  xy64_body<T>(U, goct, g, tw64, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_xy64_batch(const PassDesc* __restrict__ d, const int* __restrict__ prefix,
+                                                    int nsys, int total) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* R = reinterpret_cast<cx<T>*>(smem_raw);
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const PassDesc& D = d[lo];
+    if (D.active && *D.active == 0) continue;
+    xy64_body<T>((cx<T>*)D.U, (const cx<T>*)D.goct, D.g, (const cx<T>*)D.twx, item - prefix[lo], R);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_xy64_batch(const PassDesc* d, const int* prefix, int nsys, int total, hipStream_t s) {
+  const size_t lds = (size_t)3 * 32 * 64 * sizeof(cx<T>);
+  hipLaunchKernelGGL((k_xy64_batch<T>), dim3(total < 4096 ? total : 4096), dim3(256), lds, s, d, prefix, nsys,
+                     total);
+  return hipGetLastError();
+}
+template hipError_t launch_xy64_batch<double>(const PassDesc*, const int*, int, int, hipStream_t);
+template hipError_t launch_xy64_batch<float>(const PassDesc*, const int*, int, int, hipStream_t);
+
+template <typename T>
 hipError_t launch_xy64(const Geom& g, void* U, const void* goct, const void* tw1, hipStream_t s) {
   const size_t lds = (size_t)3 * 32 * 64 * sizeof(cx<T>);
   const int blocks = g.M3 == 1 ? 1 : g.M3 / 2;
@@ -227,7 +261,10 @@ hipError_t launch_xy64(const Geom& g, void* U, const void* goct, const void* tw1
 
 template <typename T>
 hipError_t allow_lds_xy64() {
-  return hipFuncSetAttribute((const void*)k_xy64<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_xy64<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)((size_t)3 * 32 * 64 * sizeof(cx<T>)));
+  if (e) return e;
+  return hipFuncSetAttribute((const void*)k_xy64_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)((size_t)3 * 32 * 64 * sizeof(cx<T>)));
 }
 

@@ -30,13 +30,10 @@ __device__ __forceinline__ int xslot(int p, int M, int k1, int a) {
 }  // namespace
 
 template <typename T, int A, int B>
-__global__ __launch_bounds__(256) void k_zfwd4(const cx<T>* __restrict__ x, cx<T>* __restrict__ U, Geom g,
-                                                int P, const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void zfwd4_body(const cx<T>* __restrict__ x, cx<T>* __restrict__ U, const Geom& g,
+                                           int P, const cx<T>* __restrict__ tw, int blk, cx<T>* S) {
   constexpr int M = A * B;
-  extern __shared__ unsigned char smem_raw[];
-  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);     // M * (P + 1)
   const int nb1 = (g.n1 + P - 1) / P;
-  int blk = blockIdx.x;
   const int ib1 = blk % nb1;
   blk /= nb1;
   const int i2 = blk % g.n2;
@@ -86,18 +83,23 @@ __global__ __launch_bounds__(256) void k_zfwd4(const cx<T>* __restrict__ x, cx<T
     const int pp = t % np, kz = t / np;
     dst[kz * plane + pp] = S[kz * ld + pp];
   }
+  __syncthreads();
+}
+
+template <typename T, int A, int B>
+__global__ __launch_bounds__(256) void k_zfwd4(const cx<T>* __restrict__ x, cx<T>* __restrict__ U, Geom g,
+                                                int P, const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  zfwd4_body<T, A, B>(x, U, g, P, tw, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 template <typename T, int A, int B, int MODE>
-__global__ __launch_bounds__(256) void k_zinv4(const cx<T>* __restrict__ U, const cx<T>* __restrict__ x,
-                                                cx<T>* __restrict__ y, const cx<T>* __restrict__ bvec,
-                                                const cx<T>* __restrict__ chi, Geom g, int P,
-                                                const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void zinv4_body(const cx<T>* __restrict__ U, const cx<T>* __restrict__ x,
+                                           cx<T>* __restrict__ y, const cx<T>* __restrict__ bvec,
+                                           const cx<T>* __restrict__ chi, const Geom& g, int P,
+                                           const cx<T>* __restrict__ tw, int blk, cx<T>* S) {
   constexpr int M = A * B;
-  extern __shared__ unsigned char smem_raw[];
-  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);
   const int nb1 = (g.n1 + P - 1) / P;
-  int blk = blockIdx.x;
   const int ib1 = blk % nb1;
   blk /= nb1;
   const int i2 = blk % g.n2;
@@ -147,6 +149,16 @@ __global__ __launch_bounds__(256) void k_zinv4(const cx<T>* __restrict__ U, cons
       }
     }
   }
+  __syncthreads();
+}
+
+template <typename T, int A, int B, int MODE>
+__global__ __launch_bounds__(256) void k_zinv4(const cx<T>* __restrict__ U, const cx<T>* __restrict__ x,
+                                                cx<T>* __restrict__ y, const cx<T>* __restrict__ bvec,
+                                                const cx<T>* __restrict__ chi, Geom g, int P,
+                                                const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  zinv4_body<T, A, B, MODE>(U, x, y, bvec, chi, g, P, tw, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 // Launch: returns hipErrorNotSupported when (M3, precision) has no four-step
@@ -203,6 +215,81 @@ hipError_t launch_z4(int which, const Geom& g, const void* x, void* y, const voi
   return hipErrorNotSupported;
 }
 
+__device__ __forceinline__ int find_sys(const int* prefix, int nsys, int item) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent batched z passes: each workgroup walks the (system, pencil block)
+// items of the batch with a grid stride.
+template <typename T, int A, int B>
+__global__ __launch_bounds__(256) void k_zfwd4_batch(const PassDesc* __restrict__ d, const int* __restrict__ prefix,
+                                                     int nsys, int total, int jx, int jy) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_sys(prefix, nsys, item);
+    const PassDesc& D = d[s];
+    if (D.active && *D.active == 0) continue;
+    zfwd4_body<T, A, B>((const cx<T>*)D.xb + (long)jx * D.xs, (cx<T>*)D.U, D.g, D.P, (const cx<T>*)D.twz,
+                        item - prefix[s], S);
+  }
+}
+
+template <typename T, int A, int B, int MODE>
+__global__ __launch_bounds__(256) void k_zinv4_batch(const PassDesc* __restrict__ d, const int* __restrict__ prefix,
+                                                     int nsys, int total, int jx, int jy) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_sys(prefix, nsys, item);
+    const PassDesc& D = d[s];
+    if (D.active && *D.active == 0) continue;
+    zinv4_body<T, A, B, MODE>((const cx<T>*)D.U, (const cx<T>*)D.xb + (long)jx * D.xs,
+                              (cx<T>*)D.yb + (long)jy * D.ys, (const cx<T>*)D.b, (const cx<T>*)D.chi, D.g, D.P,
+                              (const cx<T>*)D.twz, item - prefix[s], S);
+  }
+}
+
+template <typename T>
+bool z4_shape(int M3, int* A, int* B, int* P) {
+  ZShape<T> s;
+  if (!zshape<T>(M3, &s)) return false;
+  *A = s.A;
+  *B = s.B;
+  *P = s.P;
+  return true;
+}
+
+template <typename T>
+hipError_t launch_z4_batch(int which, int mode, const PassDesc* d, const int* prefix, int nsys, int total, int A,
+                           int B, int P, int jx, int jy, hipStream_t st) {
+  const size_t lds = (size_t)A * B * (P + 1) * sizeof(cx<T>);
+  const dim3 grid(total < 4096 ? total : 4096), block(A * P);
+#define VIE_Z4B(AA, BB)                                                                                      \
+  if (A == AA && B == BB) {                                                                                  \
+    if (which == 0)                                                                                          \
+      hipLaunchKernelGGL((k_zfwd4_batch<T, AA, BB>), grid, block, lds, st, d, prefix, nsys, total, jx, jy);  \
+    else if (mode == 0)                                                                                      \
+      hipLaunchKernelGGL((k_zinv4_batch<T, AA, BB, 0>), grid, block, lds, st, d, prefix, nsys, total, jx, jy); \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_zinv4_batch<T, AA, BB, 1>), grid, block, lds, st, d, prefix, nsys, total, jx, jy); \
+    return hipGetLastError();                                                                                \
+  }
+  VIE_Z4B(16, 32)
+  VIE_Z4B(32, 32)
+  if constexpr (sizeof(T) == 4) {
+    VIE_Z4B(32, 64)
+  }
+#undef VIE_Z4B
+  return hipErrorNotSupported;
+}
+
 template <typename T>
 hipError_t allow_lds_z4() {
   hipError_t e;
@@ -222,6 +309,22 @@ hipError_t allow_lds_z4() {
     VIE_ALLOW(32, 64)
   }
 #undef VIE_ALLOW
+#define VIE_ALLOWB(AA, BB)                                                                                         \
+  if ((e = hipFuncSetAttribute((const void*)k_zfwd4_batch<T, AA, BB>,                                           \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, big)))                                \
+    return e;                                                                                                      \
+  if ((e = hipFuncSetAttribute((const void*)k_zinv4_batch<T, AA, BB, 0>,                                        \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, big)))                                \
+    return e;                                                                                                      \
+  if ((e = hipFuncSetAttribute((const void*)k_zinv4_batch<T, AA, BB, 1>,                                        \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, big)))                                \
+    return e;
+  VIE_ALLOWB(16, 32)
+  VIE_ALLOWB(32, 32)
+  if constexpr (sizeof(T) == 4) {
+    VIE_ALLOWB(32, 64)
+  }
+#undef VIE_ALLOWB
   return hipSuccess;
 }
 
@@ -232,6 +335,12 @@ template hipError_t launch_z4<float>(int, const Geom&, const void*, void*, const
 template hipError_t allow_lds_z4<double>();
 template hipError_t allow_lds_z4<float>();
 template size_t z4_lds_bytes<double>(int);
+template bool z4_shape<double>(int, int*, int*, int*);
+template bool z4_shape<float>(int, int*, int*, int*);
+template hipError_t launch_z4_batch<double>(int, int, const PassDesc*, const int*, int, int, int, int, int, int, int,
+                                            hipStream_t);
+template hipError_t launch_z4_batch<float>(int, int, const PassDesc*, const int*, int, int, int, int, int, int, int,
+                                           hipStream_t);
 template size_t z4_lds_bytes<float>(int);
 
 }  // namespace vie

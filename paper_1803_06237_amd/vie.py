@@ -31,7 +31,8 @@ class VieError(RuntimeError):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("use_x0", ctypes.c_int),
-                ("precision", ctypes.c_int), ("inner_restart", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("inner_restart", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("use_graph", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -67,6 +68,8 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(SolveInfo)]
         L.vie_profile_matvec.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.vie_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
+                                      ctypes.c_double, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]
         L.vie_destroy.argtypes = [vp]
         L.vie_destroy.restype = None
         _lib = L
@@ -195,7 +198,7 @@ class Plan:
         if x is None:
             x = torch.zeros_like(b)
         opts = SolveOpts(int(restart), int(maxit), int(bool(use_x0)), int(precision), int(inner_restart),
-                         float(inner_tol))
+                         float(inner_tol), 0)
         info = SolveInfo()
         code = lib().vie_solve(self._h, _ptr(b, torch.complex128, 3 * self.N, "b"),
                                _ptr(x, torch.complex128, 3 * self.N, "x"), float(tol), ctypes.byref(opts),
@@ -203,3 +206,23 @@ class Plan:
         if code not in (VIE_OK, VIE_ENOCONV) or (raise_on_noconv and code != VIE_OK):
             _check(code, self._h)
         return x, info.as_dict()
+
+
+def solve_batch(plans, bs, xs=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000,
+                precision: int = 0, use_x0: bool = False, inner_restart: int = 20, inner_tol: float = 1e-4,
+                use_graph: bool = True):
+    """Solve len(plans) systems together (vie_solve_batch).  Returns (xs, infos, status)."""
+    import torch
+    n = len(plans)
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    P = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    Bp = (ctypes.c_void_p * n)(*[_ptr(b, torch.complex128, 3 * p.N, "b").value for b, p in zip(bs, plans)])
+    Xp = (ctypes.c_void_p * n)(*[_ptr(x, torch.complex128, 3 * p.N, "x").value for x, p in zip(xs, plans)])
+    opts = SolveOpts(int(restart), int(maxit), int(bool(use_x0)), int(precision), int(inner_restart),
+                     float(inner_tol), int(bool(use_graph)))
+    infos = (SolveInfo * n)()
+    code = lib().vie_solve_batch(P, Bp, Xp, n, float(tol), ctypes.byref(opts), infos)
+    if code not in (VIE_OK, VIE_ENOCONV):
+        raise VieError(code, "vie_solve_batch failed")
+    return xs, [i.as_dict() for i in infos], code
