@@ -1,0 +1,98 @@
+"""Pins of the oracle's network reference (convolution, its gradients, pooling,
+rounding, Adam) against facts that do not depend on its code."""
+import numpy as np
+
+from oracle import nn
+
+RNG = np.random.default_rng(21)
+
+
+def test_bf16_round_to_nearest_even():
+    one = 1.0
+    ulp = 2.0 ** -7                       # bfloat16 spacing on [1, 2)
+    assert nn.bf16_round(one) == one
+    assert nn.bf16_round(one + ulp / 2) == one                 # tie -> even (mantissa 0)
+    assert nn.bf16_round(one + 3 * ulp / 2) == one + 2 * ulp   # tie -> even (mantissa 2)
+    assert nn.bf16_round(one + 0.6 * ulp) == one + ulp
+    assert nn.bf16_round(-3.0) == -3.0
+    x = RNG.standard_normal(1000)
+    r = nn.bf16_round(x)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8 * (1 + 1e-6))
+
+
+def test_one_tap_convolution_is_a_matrix_product():
+    X = RNG.standard_normal((3, 4, 5, 6))
+    W = RNG.standard_normal((1, 7, 6))
+    Y = nn.conv3d(X, W, round_inputs=False)
+    assert np.allclose(Y, np.einsum("dhwi,oi->dhwo", X, W[0]), atol=1e-13)
+
+
+def test_delta_kernel_is_a_zero_padded_shift():
+    X = RNG.standard_normal((4, 5, 6, 2))
+    for ti, (dz, dy, dx) in enumerate(nn.TAPS):
+        W = np.zeros((27, 2, 2))
+        W[ti] = np.eye(2)
+        Y = nn.conv3d(X, W, round_inputs=False)
+        for z in range(4):
+            for y in range(5):
+                for x in range(6):
+                    zz, yy, xx = z + dz, y + dy, x + dx
+                    inside = 0 <= zz < 4 and 0 <= yy < 5 and 0 <= xx < 6
+                    want = X[zz, yy, xx] if inside else np.zeros(2)
+                    assert np.array_equal(Y[z, y, x], want)
+
+
+def test_gradients_are_adjoints():
+    X = RNG.standard_normal((4, 3, 5, 3))
+    W = RNG.standard_normal((27, 4, 3))
+    dY = RNG.standard_normal((4, 3, 5, 4))
+    Y = nn.conv3d(X, W, round_inputs=False)
+    dX = nn.conv3d_dgrad(dY, W, round_inputs=False)
+    dW = nn.conv3d_wgrad(X, dY, round_inputs=False)
+    assert abs(np.sum(Y * dY) - np.sum(X * dX)) < 1e-10 * np.abs(Y * dY).sum()
+    assert abs(np.sum(Y * dY) - np.sum(W * dW)) < 1e-10 * np.abs(Y * dY).sum()
+
+
+def test_gradients_match_central_differences():
+    X = RNG.standard_normal((3, 3, 4, 2))
+    W = RNG.standard_normal((27, 3, 2))
+    T = RNG.standard_normal((3, 3, 4, 3))
+
+    def loss(X_, W_):
+        return 0.5 * np.sum((nn.conv3d(X_, W_, relu=True, round_inputs=False) - T) ** 2)
+
+    Y = nn.conv3d(X, W, relu=True, round_inputs=False)
+    dY = (Y - T) * (Y > 0)
+    dX = nn.conv3d_dgrad(dY, W, round_inputs=False)
+    dW = nn.conv3d_wgrad(X, dY, round_inputs=False)
+    eps = 1e-6
+    for _ in range(10):
+        idx = tuple(RNG.integers(0, s) for s in X.shape)
+        Xp, Xm = X.copy(), X.copy()
+        Xp[idx] += eps
+        Xm[idx] -= eps
+        fd = (loss(Xp, W) - loss(Xm, W)) / (2 * eps)
+        assert abs(fd - dX[idx]) < 1e-6 * max(1, abs(fd))
+        jdx = tuple(RNG.integers(0, s) for s in W.shape)
+        Wp, Wm = W.copy(), W.copy()
+        Wp[jdx] += eps
+        Wm[jdx] -= eps
+        fd = (loss(X, Wp) - loss(X, Wm)) / (2 * eps)
+        assert abs(fd - dW[jdx]) < 1e-6 * max(1, abs(fd))
+
+
+def test_pool_and_upsample_adjoints():
+    X = RNG.standard_normal((4, 6, 8, 3))
+    Yp = RNG.standard_normal((2, 3, 4, 3))
+    assert abs(np.sum(nn.avgpool2(X) * Yp) - np.sum(X * nn.avgpool2_grad(Yp))) < 1e-12
+    Xs = RNG.standard_normal((2, 3, 4, 3))
+    Yu = RNG.standard_normal((4, 6, 8, 3))
+    assert abs(np.sum(nn.upsample2(Xs) * Yu) - np.sum(Xs * nn.upsample2_grad(Yu))) < 1e-12
+    assert np.allclose(nn.avgpool2(nn.upsample2(Xs)), Xs)
+
+
+def test_adam_first_step_is_a_sign_step():
+    w = RNG.standard_normal(20)
+    g = RNG.standard_normal(20)
+    w1, m, v = nn.adam_step(w, g, np.zeros(20), np.zeros(20), 1, lr=1e-3)
+    assert np.allclose(w1, w - 1e-3 * np.sign(g), atol=1e-9)
