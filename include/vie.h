@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct vie_plan_s* vie_plan_t;            /* opaque; owned by the library until vie_destroy */
+typedef struct vie_net_s* vie_net_t;              /* opaque learned preconditioner; vie_net_destroy */
 typedef struct { double re, im; } vie_c128;       /* interleaved FP64 complex */
 typedef struct { float re, im; } vie_c64;         /* interleaved FP32 complex */
 
@@ -122,7 +123,8 @@ typedef struct {
   int restart;        /* Krylov dimension m of GMRES(m) / outer FGMRES(m); <= 0 -> 50 */
   int maxit;          /* total outer iterations; <= 0 -> 10000 */
   int use_x0;         /* 1: x holds the initial guess; 0: start from zero */
-  int precision;      /* 0: FP64 GMRES; 1: mixed (FP32 inner GMRES, FP64 outer FGMRES) */
+  int precision;      /* 0: FP64 GMRES; 1: mixed (FP32 inner GMRES, FP64 outer FGMRES);
+                         2: learned (FP64 FGMRES with the attached network, plain GMRES fallback) */
   int inner_restart;  /* mixed tier: inner GMRES dimension; <= 0 -> 20 */
   double inner_tol;   /* mixed tier: inner relative tolerance; <= 0 -> 1e-4 */
   int use_graph;      /* vie_solve_batch: 1 = capture one restart cycle as a HIP graph and replay it */
@@ -137,6 +139,7 @@ typedef struct {
   double rel_res_true;   /* ||b - A x|| / ||b|| with the FP64 matvec */
   double rel_res_est;    /* last Hessenberg estimate */
   double seconds;        /* wall time of the call */
+  int fallback;          /* learned tier: 1 when it switched to plain GMRES */
 } vie_solve_info;
 
 /*
@@ -179,6 +182,45 @@ int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* rhs, vie_c12
  */
 int vie_profile_matvec(vie_plan_t plan, int precision, const void* x, void* y, int reps, double pass_ms[3],
                        double* total_ms);
+
+/*
+ * Learned preconditioner (this library's addition; not part of the paper's
+ * method).  A fixed 4-level 3-D U-Net (3x3x3 convolutions, channels 16/32/48/64,
+ * bias-free ReLU, 2x average pooling, nearest upsampling, skip concatenation, a
+ * final 1x1x1 convolution to 6 channels) maps a residual r and the contrast chi
+ * to an approximate A^{-1} r:  z = net(r s, chi) / s with s = sqrt(3N)/||r||.
+ * Activations are bfloat16, convolutions run on the matrix cores with FP32
+ * accumulation, master weights and Adam moments are FP32.
+ *
+ * vie_net_create: grid dims must be multiples of 8 (three poolings).  Weights
+ *   are He-initialised from `seed` (deterministic).  hip_stream as in vie_plan.
+ * vie_net_num_params / get / set: the FP32 master weights, host buffer of
+ *   vie_net_num_params floats (layer by layer, each [taps][cout][cin] padded).
+ * vie_net_apply: z = net applied to r (device, 3N) with chi (device, N contrast
+ *   values, e.g. 1 - eps_b/eps); z device, 3N.  Asynchronous.
+ * vie_net_train_step: one Adam step (lr) on the mean squared error between
+ *   net(r_i) and target_i over `count` samples (device pointers, 3N / N / 3N);
+ *   *loss receives the mean loss.  Synchronises.
+ * vie_set_preconditioner: attach a network with the plan's grid (NULL detaches);
+ *   vie_solve with precision 2 uses it.  The plan does not own the network.
+ * vie_nn_conv_test: diagnostic single layer on FP32 device buffers (rounded to
+ *   bfloat16 on entry): mode 0 forward y[V][cout] (relu optional) from x[V][cin]
+ *   and w[taps][cout][cin]; mode 1 input gradient dx[V][cin] from x = dy[V][cout];
+ *   mode 2 weight gradient dw[taps][cout][cin] from x[V][cin] and w = dy[V][cout].
+ *   taps 1 or 27, cin and cout multiples of 16.  Synchronises.
+ */
+int vie_net_create(vie_net_t* out, const int grid[3], unsigned seed, void* hip_stream);
+void vie_net_destroy(vie_net_t net);
+int vie_net_num_params(vie_net_t net, size_t* count);
+int vie_net_get_params(vie_net_t net, float* host, size_t count);
+int vie_net_set_params(vie_net_t net, const float* host, size_t count);
+int vie_net_apply(vie_net_t net, const vie_c128* r, const vie_c128* chi, vie_c128* z);
+int vie_net_train_step(vie_net_t net, int count, const vie_c128* const* r, const vie_c128* const* chi,
+                       const vie_c128* const* target, float lr, double* loss);
+int vie_set_preconditioner(vie_plan_t plan, vie_net_t net);
+int vie_nn_conv_test(int mode, const int dims[3], int taps, int cin, int cout, const float* x, const float* w,
+                     float* out, int relu, void* hip_stream);
+const char* vie_net_last_error(vie_net_t net);
 
 /* Message for the last failing call on this plan (plan = NULL: on this thread). */
 const char* vie_last_error(vie_plan_t plan);

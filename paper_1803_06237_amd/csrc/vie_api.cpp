@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <complex>
 #include <cstdio>
 #include <cstring>
@@ -18,6 +19,9 @@
 namespace vie {
 template <typename T>
 hipError_t allow_lds(size_t bytes);
+hipError_t net_apply(vie_net_s* N, const double2* r, const double2* chi, double2* z);
+const int* net_grid(vie_net_s* N);
+void net_set_stream(vie_net_s* N, hipStream_t s);
 }
 
 using namespace vie;
@@ -99,6 +103,7 @@ struct vie_plan_s {
   float2* v32b = nullptr;
   int* flag = nullptr;
   bool has_contrast = false;
+  vie_net_s* net = nullptr;    // learned preconditioner (not owned)
   GmresWs<double> ws64;
   GmresWs<float> ws32;
   std::string err;
@@ -195,7 +200,7 @@ struct Op32 {
 };
 
 struct Stats {
-  int iters = 0, restarts = 0, matvecs = 0, inner = 0;
+  int iters = 0, restarts = 0, matvecs = 0, inner = 0, fallback = 0;
   double est = 0, rel_true = INFINITY;
 };
 
@@ -542,6 +547,45 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
     status = gmres_core<double, Op64, Pc>(p, p->ws64, A, &pc, reinterpret_cast<const double2*>(b),
                                           reinterpret_cast<double2*>(x), tol, o.restart, o.maxit, o.use_x0 != 0,
                                           true, st);
+  } else if (o.precision == 2) {
+    // learned tier: x0 = net(b), FGMRES with z = net(v); a cycle that reduces the
+    // true residual by less than half switches to plain GMRES for the rest
+    if (!p->net) return fail(p, VIE_ESTATE, "no preconditioner attached (vie_set_preconditioner)");
+    net_set_stream(p->net, p->stream);
+    double2* xd = reinterpret_cast<double2*>(x);
+    const double2* bd = reinterpret_cast<const double2*>(b);
+    int napply = 0;
+    struct Pc {
+      vie_plan_s* p;
+      int* count;
+      hipError_t operator()(const void* v, void* z, Stats&) {
+        ++*count;
+        return net_apply(p->net, reinterpret_cast<const double2*>(v), p->chi64, reinterpret_cast<double2*>(z));
+      }
+    } pc{p, &napply};
+    bool have_x0 = o.use_x0 != 0;
+    if (!have_x0) {
+      HIPTRY(p, net_apply(p->net, bd, p->chi64, xd));
+      ++napply;
+      have_x0 = true;
+    }
+    double prev = INFINITY;
+    status = VIE_ENOCONV;
+    bool fell_back = false;
+    while (st.iters < o.maxit) {
+      const int budget = fell_back ? o.maxit : std::min(o.maxit, st.iters + o.restart);
+      if (fell_back)
+        status = gmres_core<double, Op64, NoPrecond>(p, p->ws64, A, nullptr, bd, xd, tol, o.restart, budget, true,
+                                                     true, st);
+      else
+        status = gmres_core<double, Op64, Pc>(p, p->ws64, A, &pc, bd, xd, tol, o.restart, budget, true, true, st);
+      if (status != VIE_OK && status != VIE_ENOCONV) break;
+      if (status == VIE_OK || fell_back) break;
+      if (!(st.rel_true < 0.5 * prev)) fell_back = true;
+      prev = st.rel_true;
+    }
+    st.inner = napply;
+    st.fallback = fell_back ? 1 : 0;
   } else {
     return fail(p, VIE_EINVAL, "unknown precision tier");
   }
@@ -555,6 +599,7 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
     info->rel_res_true = st.rel_true;
     info->rel_res_est = st.est;
     info->seconds = secs;
+    info->fallback = st.fallback;
   }
   if (status == VIE_ENOCONV && p->err.empty()) p->err = "tolerance not reached within maxit";
   return status;
@@ -598,6 +643,17 @@ int vie_profile_matvec(vie_plan_t p, int precision, const void* x, void* y, int 
   for (auto& e : ev) (void)hipEventDestroy(e);
   for (int w = 0; w < 3; ++w) pass_ms[w] = acc[w] / reps;
   if (total_ms) *total_ms = tot / reps;
+  return VIE_OK;
+}
+
+int vie_set_preconditioner(vie_plan_t p, vie_net_t net) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (net) {
+    const int* g = net_grid(net);
+    if (g[0] != p->g.n1 || g[1] != p->g.n2 || g[2] != p->g.n3)
+      return fail(p, VIE_EINVAL, "network grid differs from the plan's grid");
+  }
+  p->net = net;
   return VIE_OK;
 }
 

@@ -38,7 +38,7 @@ class SolveOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("inner_iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("matvecs", ctypes.c_int), ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double),
-                ("rel_res_est", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_res_est", ctypes.c_double), ("seconds", ctypes.c_double), ("fallback", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,6 +72,20 @@ def lib() -> ctypes.CDLL:
                                       ctypes.c_double, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]
         L.vie_destroy.argtypes = [vp]
         L.vie_destroy.restype = None
+        L.vie_net_create.argtypes = [ctypes.POINTER(vp), ip, ctypes.c_uint, vp]
+        L.vie_net_destroy.argtypes = [vp]
+        L.vie_net_destroy.restype = None
+        L.vie_net_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.vie_net_get_params.argtypes = [vp, vp, ctypes.c_size_t]
+        L.vie_net_set_params.argtypes = [vp, vp, ctypes.c_size_t]
+        L.vie_net_apply.argtypes = [vp, vp, vp, vp]
+        L.vie_net_train_step.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.c_float, ctypes.POINTER(ctypes.c_double)]
+        L.vie_set_preconditioner.argtypes = [vp, vp]
+        L.vie_nn_conv_test.argtypes = [ctypes.c_int, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                       ctypes.c_int, vp]
+        L.vie_net_last_error.restype = ctypes.c_char_p
+        L.vie_net_last_error.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -188,6 +202,10 @@ class Plan:
                self._h)
         return list(ms), tot.value
 
+    def set_preconditioner(self, net):
+        _check(lib().vie_set_preconditioner(self._h, net.handle if net is not None else None), self._h)
+        self._net = net
+
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000,
               precision: int = 0, use_x0: bool = False, inner_restart: int = 20,
               inner_tol: float = 1e-4, raise_on_noconv: bool = False):
@@ -226,3 +244,92 @@ def solve_batch(plans, bs, xs=None, tol: float = 1e-8, restart: int = 50, maxit:
     if code not in (VIE_OK, VIE_ENOCONV):
         raise VieError(code, "vie_solve_batch failed")
     return xs, [i.as_dict() for i in infos], code
+
+
+class Net:
+    """The learned preconditioner network (see vie_net_* in include/vie.h)."""
+
+    def __init__(self, grid: Sequence[int], seed: int = 0, stream=None):
+        import torch
+        self.n = tuple(int(v) for v in grid)
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        code = lib().vie_net_create(ctypes.byref(h), _grid(self.n), int(seed), ctypes.c_void_p(stream.cuda_stream))
+        if code != VIE_OK:
+            raise VieError(code, "vie_net_create failed")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vie_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self) -> int:
+        c = ctypes.c_size_t()
+        lib().vie_net_num_params(self._h, ctypes.byref(c))
+        return c.value
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params(), dtype=np.float32)
+        if lib().vie_net_get_params(self._h, out.ctypes.data, out.size) != VIE_OK:
+            raise VieError(VIE_EDEVICE, "vie_net_get_params failed")
+        return out
+
+    def set_params(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if lib().vie_net_set_params(self._h, w.ctypes.data, w.size) != VIE_OK:
+            raise VieError(VIE_EINVAL, "vie_net_set_params failed")
+
+    def apply(self, r, chi, z=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        code = lib().vie_net_apply(self._h, _ptr(r, torch.complex128, 3 * self.N, "r"),
+                                   _ptr(chi, torch.complex128, self.N, "chi"),
+                                   _ptr(z, torch.complex128, 3 * self.N, "z"))
+        if code != VIE_OK:
+            raise VieError(code, "vie_net_apply failed")
+        return z
+
+    def train_step(self, rs, chis, targets, lr: float) -> float:
+        import torch
+        n = len(rs)
+        R = (ctypes.c_void_p * n)(*[_ptr(r, torch.complex128, 3 * self.N, "r").value for r in rs])
+        C = (ctypes.c_void_p * n)(*[_ptr(c, torch.complex128, self.N, "chi").value for c in chis])
+        T = (ctypes.c_void_p * n)(*[_ptr(t, torch.complex128, 3 * self.N, "target").value for t in targets])
+        loss = ctypes.c_double()
+        code = lib().vie_net_train_step(self._h, n, R, C, T, float(lr), ctypes.byref(loss))
+        if code != VIE_OK:
+            raise VieError(code, "vie_net_train_step failed")
+        return loss.value
+
+
+def conv_test(mode: int, dims, taps: int, cin: int, cout: int, x, w, relu: bool = False):
+    """Diagnostic single convolution layer (vie_nn_conv_test) on FP32 device tensors."""
+    import torch
+    V = int(np.prod(dims))
+    if mode == 0:
+        out = torch.empty((V, cout), dtype=torch.float32, device=x.device)
+    elif mode == 1:
+        out = torch.empty((V, cin), dtype=torch.float32, device=x.device)
+    else:
+        out = torch.empty((taps, cout, cin), dtype=torch.float32, device=x.device)
+    code = lib().vie_nn_conv_test(int(mode), _grid(dims), int(taps), int(cin), int(cout),
+                                  ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), int(bool(relu)),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if code != VIE_OK:
+        raise VieError(code, "vie_nn_conv_test failed")
+    return out
