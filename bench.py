@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiler run: one device copy of a vector (counter calibration, bytes known) and the "
+                         "timed FP64 products only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver in this build is "
@@ -103,6 +106,10 @@ def main():
     xh = rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)
     x = torch.from_numpy(xh).cuda()
     y = torch.empty_like(x)
+    if args.profile:
+        y.copy_(x)        # calibration: reads and writes exactly 3N * 16 bytes
+        torch.cuda.synchronize()
+        args.no_solve = args.no_cpu = True
     for _ in range(args.warmup):
         plan.matvec(x, y)
     torch.cuda.synchronize()

@@ -95,6 +95,12 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
 int vie_set_contrast(vie_plan_t plan, const vie_c128* eps);
 
 /*
+ * vie_get_contrast -- copy the plan's FP64 contrast (eps_r - 1)/eps_r per voxel into
+ * chi (device, N values [n1][n2][n3]).  Asynchronous on the plan's stream.
+ */
+int vie_get_contrast(vie_plan_t plan, vie_c128* chi);
+
+/*
  * vie_rhs -- b = h^{3/2} M_eps e_inc: the Galerkin projection of an incident field
  * sampled at voxel centres, times the contrast (Section III-A right-hand side).
  * e_inc, b: device, 3N values each; may alias.

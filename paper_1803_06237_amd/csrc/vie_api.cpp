@@ -462,6 +462,14 @@ int vie_set_contrast(vie_plan_t p, const vie_c128* eps) {
   return VIE_OK;
 }
 
+int vie_get_contrast(vie_plan_t p, vie_c128* chi) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!chi) return fail(p, VIE_EINVAL, "null chi");
+  if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
+  HIPTRY(p, hipMemcpyAsync(chi, p->chi64, sizeof(double2) * p->g.N, hipMemcpyDeviceToDevice, p->stream));
+  return VIE_OK;
+}
+
 int vie_rhs(vie_plan_t p, const vie_c128* e_inc, vie_c128* b) {
   if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
   if (!e_inc || !b) return fail(p, VIE_EINVAL, "null vector");

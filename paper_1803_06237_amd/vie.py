@@ -61,6 +61,7 @@ def lib() -> ctypes.CDLL:
                                ctypes.c_uint, vp]
         L.vie_set_contrast.argtypes = [vp, vp]
         L.vie_rhs.argtypes = [vp, vp, vp]
+        L.vie_get_contrast.argtypes = [vp, vp]
         L.vie_matvec.argtypes = [vp, vp, vp]
         L.vie_matvec_c64.argtypes = [vp, vp, vp]
         L.vie_residual.argtypes = [vp, vp, vp, vp]
@@ -157,6 +158,13 @@ class Plan:
     def set_contrast(self, eps):
         import torch
         _check(lib().vie_set_contrast(self._h, _ptr(eps, torch.complex128, self.N, "eps")), self._h)
+
+    def contrast(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.complex128, device="cuda")
+        _check(lib().vie_get_contrast(self._h, _ptr(out, torch.complex128, self.N, "chi")), self._h)
+        return out
 
     def rhs(self, e_inc, out=None):
         import torch
