@@ -40,6 +40,33 @@ def pass_bytes(n, M, cs):
             U + 3 * N * cs + N * cs + 3 * N * cs]  # pass 3: read U, x, chi; write y
 
 
+KERNEL_SOURCES = {
+    "k_xy64<double>": ["xy64.hip", "fft_device.hpp"],
+    "k_zfwd4<double, 32, 32>": ["zpass.hip", "dft_reg.hpp"],
+    "k_zinv4<double, 32, 32, 0>": ["zpass.hip", "dft_reg.hpp"],
+}
+
+
+def profiled_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/matvec_32x32x512_fp64.md), or None when the kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "matvec_32x32x512_fp64.md")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    m = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        m.update(open(os.path.join(ROOT, "paper_1803_06237_amd", "csrc", f), "rb").read())
+    digest = m.hexdigest()[:16]
+    for line in open(path):
+        if line.startswith(f"traffic_bytes {kernel} ="):
+            val, sha = line.split("=", 1)[1].split(";")
+            if sha.split("=")[1].strip() == digest:
+                return int(float(val))
+    return None
+
+
 def circulant(n):
     out = []
     for v in n:
@@ -122,11 +149,15 @@ def main():
     value = args.steps / el
 
     b64 = pass_bytes(n, M, 16)
-    names = ["k_zfwd<double>", "k_xy64<double>" if M[0] == 64 and M[1] == 64 else "k_xyg<double>", "k_zinv<double,0>"]
+    z4 = M[2] in (512, 1024)
+    names = ["k_zfwd4<double, 32, 32>" if z4 else "k_zfwd<double>",
+             "k_xy64<double>" if M[0] == 64 and M[1] == 64 else "k_xyg<double>",
+             "k_zinv4<double, 32, 32, 0>" if z4 else "k_zinv<double, 0>"]
     dom = int(np.argmax(pass_ms))
     achieved = b64[dom] / (pass_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[dom],
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(names[dom]),
+                "kernel": names[dom],
                 "algorithmic_bytes": b64[dom], "avg_ms": round(pass_ms[dom], 5)}
     passes = {names[i]: {"avg_us": round(pass_ms[i] * 1e3, 2), "bytes": b64[i],
                          "GBs": round(b64[i] / (pass_ms[i] * 1e-3) / 1e9, 1)} for i in range(3)}
