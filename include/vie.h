@@ -194,7 +194,8 @@ int vie_profile_matvec(vie_plan_t plan, int precision, const void* x, void* y, i
  * method).  A fixed 4-level 3-D U-Net (3x3x3 convolutions, channels 16/32/48/64,
  * bias-free ReLU, 2x average pooling, nearest upsampling, skip concatenation, a
  * final 1x1x1 convolution to 6 channels) maps a residual r and the contrast chi
- * to an approximate A^{-1} r:  z = net(r s, chi) / s with s = sqrt(3N)/||r||.
+ * to an approximate A^{-1} r:  z = r + net(r s, chi) / s with s = sqrt(3N)/||r||
+ * (the network predicts the correction A^{-1} r - r).
  * Activations are bfloat16, convolutions run on the matrix cores with FP32
  * accumulation, master weights and Adam moments are FP32.
  *
@@ -205,7 +206,8 @@ int vie_profile_matvec(vie_plan_t plan, int precision, const void* x, void* y, i
  * vie_net_apply: z = net applied to r (device, 3N) with chi (device, N contrast
  *   values, e.g. 1 - eps_b/eps); z device, 3N.  Asynchronous.
  * vie_net_train_step: one Adam step (lr) on the mean squared error between
- *   net(r_i) and target_i over `count` samples (device pointers, 3N / N / 3N);
+ *   net(r_i s) and (target_i - r_i) s over `count` samples (device pointers,
+ *   3N / N / 3N), i.e. z = r + net approximates target;
  *   *loss receives the mean loss.  Synchronises.
  * vie_set_preconditioner: attach a network with the plan's grid (NULL detaches);
  *   vie_solve with precision 2 uses it.  The plan does not own the network.

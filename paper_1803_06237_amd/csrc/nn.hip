@@ -1,6 +1,7 @@
 // Learned preconditioner: a 4-level 3-D U-Net (channels 16/32/48/64, 3x3x3
 // convolutions, bias-free ReLU) that maps a normalised residual r (and the
-// contrast chi) to an approximate error A^{-1} r.  It is used as the right
+// contrast chi) to the correction A^{-1} r - r; the preconditioner is
+// z = r + net(r).  It is used as the right
 // preconditioner of flexible GMRES and as an initial guess, with plain GMRES as
 // the fallback.  This part is this library's addition, not the paper's method.
 //
@@ -242,30 +243,34 @@ __global__ void k_pack(const double2* __restrict__ r, const double2* __restrict_
   }
 }
 
-// z[c][v] = (out[v][2c] + i out[v][2c+1]) / s
+// z[c][v] = r[c][v] + (out[v][2c] + i out[v][2c+1]) / s: the network predicts the
+// correction A^{-1} r - r, so an untrained (small) network is the identity
 __global__ void k_unpack(const float* __restrict__ out, const double2* __restrict__ sumsq, long N,
-                         double2* __restrict__ z) {
+                         const double2* __restrict__ r, double2* __restrict__ z) {
   const double s = sumsq->x > 0 ? sqrt(3.0 * (double)N / sumsq->x) : 0.0;
   const double is = s > 0 ? 1.0 / s : 0.0;
   for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x)
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      z[(long)c * N + v] = double2{out[v * 16 + 2 * c] * is, out[v * 16 + 2 * c + 1] * is};
+    for (int c = 0; c < 3; ++c) {
+      const double2 rv = r[(long)c * N + v];
+      z[(long)c * N + v] = double2{rv.x + out[v * 16 + 2 * c] * is, rv.y + out[v * 16 + 2 * c + 1] * is};
+    }
 }
 
-// mean squared error of out against target * s over 6 channels; dOut = d(loss)/d(out)
+// mean squared error of out against (target - r) * s over 6 channels; dOut = d(loss)/d(out)
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, const double2* __restrict__ target,
-                                              const double2* __restrict__ sumsq, long N, bf16_t* __restrict__ dOut,
-                                              float gscale, double* __restrict__ partial) {
+                                              const double2* __restrict__ r, const double2* __restrict__ sumsq,
+                                              long N, bf16_t* __restrict__ dOut, float gscale,
+                                              double* __restrict__ partial) {
   __shared__ double red[256];
   const double s = sumsq->x > 0 ? sqrt(3.0 * (double)N / sumsq->x) : 0.0;
   double acc = 0.0;
   for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double2 t = target[(long)c * N + v];
-      const float d0 = out[v * 16 + 2 * c] - (float)(t.x * s);
-      const float d1 = out[v * 16 + 2 * c + 1] - (float)(t.y * s);
+      const double2 t = target[(long)c * N + v], rv = r[(long)c * N + v];
+      const float d0 = out[v * 16 + 2 * c] - (float)((t.x - rv.x) * s);
+      const float d1 = out[v * 16 + 2 * c + 1] - (float)((t.y - rv.y) * s);
       acc += (double)d0 * d0 + (double)d1 * d1;
       dOut[v * 16 + 2 * c] = f2bf(gscale * d0);
       dOut[v * 16 + 2 * c + 1] = f2bf(gscale * d1);
@@ -526,7 +531,7 @@ hipError_t net_apply(vie_net_s* N, const double2* r, const double2* chi, double2
   if ((e = KrylovOps<double>::nrm2sq(r, 3 * V, N->red, N->sumsq, N->stream))) return e;
   hipLaunchKernelGGL(k_pack, dim3(gblocks(V)), dim3(256), 0, N->stream, r, chi, N->sumsq, V, N->X0);
   if ((e = net_forward(N))) return e;
-  hipLaunchKernelGGL(k_unpack, dim3(gblocks(V)), dim3(256), 0, N->stream, N->out, N->sumsq, V, z);
+  hipLaunchKernelGGL(k_unpack, dim3(gblocks(V)), dim3(256), 0, N->stream, N->out, N->sumsq, V, r, z);
   return hipGetLastError();
 }
 const int* net_grid(vie_net_s* N) { return N->n; }
@@ -568,7 +573,7 @@ int vie_net_create(vie_net_t* out, const int grid[3], unsigned seed, void* hip_s
     // He initialisation over the real fan-in; padded input channels and the
     // padded outputs of the last layer stay zero
     std::vector<float> w(n, 0.f);
-    std::normal_distribution<double> nd(0.0, std::sqrt(2.0 / (C.taps * C.cin_real)) * (i == 14 ? 0.5 : 1.0));
+    std::normal_distribution<double> nd(0.0, std::sqrt(2.0 / (C.taps * C.cin_real)) * (i == 14 ? 0.1 : 1.0));
     const int cout_real = i == 14 ? 6 : C.cout;
     for (int t = 0; t < C.taps; ++t)
       for (int o = 0; o < cout_real; ++o)
@@ -669,7 +674,7 @@ int vie_net_train_step(vie_net_t N, int count, const vie_c128* const* r, const v
     if (net_forward(N)) return VIE_EDEVICE;
     const float gscale = 2.0f / (6.0f * (float)V * (float)count);
     hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, N->stream, N->out, reinterpret_cast<const double2*>(target[i]),
-                       N->sumsq, V, N->gOut, gscale, N->lpart);
+                       ri, N->sumsq, V, N->gOut, gscale, N->lpart);
     if (net_backward(N, i > 0 ? 1 : 0)) return VIE_EDEVICE;
     if (hipMemcpyAsync(N->lpart_h, N->lpart, sizeof(double) * nb, hipMemcpyDeviceToHost, N->stream) ||
         hipStreamSynchronize(N->stream))

@@ -6,6 +6,10 @@
 
 #include <chrono>
 #include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
 #include <algorithm>
 #include <complex>
 #include <cstdio>
@@ -29,6 +33,24 @@ using namespace vie;
 namespace {
 
 thread_local std::string g_thread_error;
+
+// Host Toeplitz tables depend only on (grid, kappa); plans of one process share them.
+std::shared_ptr<const std::vector<std::complex<double>>> cached_table(const int n[3], double kappa) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, double>, std::shared_ptr<const std::vector<std::complex<double>>>> cache;
+  const auto key = std::make_tuple(n[0], n[1], n[2], kappa);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  auto t = std::make_shared<std::vector<std::complex<double>>>((size_t)6 * n[0] * n[1] * n[2]);
+  vie::green_table(n, kappa, t->data(), 0);
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache.size() >= 16) cache.clear();
+  cache[key] = t;
+  return t;
+}
 
 template <typename T>
 struct GmresWs {
@@ -400,8 +422,7 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
   if ((e = allow_lds<double>(budget)) || (e = allow_lds<float>(budget)))
     return bail(hipfail(nullptr, e, "hipFuncSetAttribute"));
   // host table
-  std::vector<std::complex<double>> table((size_t)6 * g.N);
-  vie::green_table(grid, p->kappa, table.data(), 0);
+  const auto table = cached_table(grid, p->kappa);
   const bool f32 = (flags & VIE_WITH_FP32) != 0;
   const long H = (long)g.H1 * g.H2 * g.H3;
   const long P = (long)g.M1 * g.M2 * g.M3;
@@ -433,7 +454,7 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
   PLANTRY(hipMalloc(&p->flag, sizeof(int)));
   PLANTRY(hipMalloc(&table_dev, sizeof(double2) * 6 * g.N));
   PLANTRY(hipMalloc(&full, sizeof(double2) * P));
-  PLANTRY(hipMemcpyAsync(table_dev, table.data(), sizeof(double2) * 6 * g.N, hipMemcpyHostToDevice, p->stream));
+  PLANTRY(hipMemcpyAsync(table_dev, table->data(), sizeof(double2) * 6 * g.N, hipMemcpyHostToDevice, p->stream));
   {
     const double2* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
     PLANTRY(launch_spectrum(g, table_dev, full, p->goct64, p->goct32, tw, p->stream));

@@ -15,9 +15,9 @@
 //          processed in two halves of kx so that the exchange of one half
 //          (3 components x 32 columns x 64) fits where the rows were kept.
 // Stage C: rows inverse, crop, store.
-// A workgroup transforms the two planes kz and M3 - kz one after the other: both
-// use the same slab of the folded Green spectrum, so the second reads it from L2
-// (workgroup 0 takes kz = 0 and M3/2, whose slabs are unpaired).
+// Planes kz and M3 - kz use the same slab of the folded Green spectrum: the
+// single-system kernel puts them on workgroups b and b + 8 (same XCD), the
+// batched kernel transforms the pair in one workgroup.
 // LDS: one region of 3 x 32 x 64 complex values (96 KiB FP64, 48 KiB FP32),
 // element (c, y, kx) at (c*32 + y)*64 + (kx ^ (y & 7)) so the column accesses
 // of 8 threads with consecutive y hit distinct banks.
@@ -48,8 +48,9 @@ __device__ __forceinline__ void twiddle8(cx<T>* v, const cx<T>* w) {
 }  // namespace
 
 template <typename T>
-__device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
-                                          const cx<T>* __restrict__ tw64, int blk, cx<T>* R) {
+__device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
+                                            const cx<T>* __restrict__ tw64, int kz_first, int nplanes, int kz_second,
+                                            cx<T>* R) {
   const int tid = threadIdx.x;
   const int a = tid & 7;
   const int q = tid >> 3;                            // 0..31
@@ -58,10 +59,8 @@ __device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __
   cx<T> w[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) w[k] = tw64[a * k];
-  const int half = g.M3 / 2;
-  const int nplanes = g.M3 == 1 ? 1 : 2;
   for (int pi = 0; pi < nplanes; ++pi) {
-  const int kz = blk == 0 ? (pi == 0 ? 0 : half) : (pi == 0 ? blk : g.M3 - blk);
+  const int kz = pi == 0 ? kz_first : kz_second;
   cx<T>* P = U + (long)kz * 3 * n1 * n2;
 
   // ---------------- stage A: forward FFT along x for row y = q, all components
@@ -214,11 +213,32 @@ __device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __
   }
 }
 
+// plane pair p: (0, M3/2) for p = 0, (p, M3 - p) otherwise
+__device__ __forceinline__ void pair_planes(int p, int M3, int* a, int* b) {
+  *a = p == 0 ? 0 : p;
+  *b = p == 0 ? M3 / 2 : M3 - p;
+}
+
+template <typename T>
+__device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
+                                          const cx<T>* __restrict__ tw64, int pair, cx<T>* R) {
+  int a, b;
+  pair_planes(pair, g.M3, &a, &b);
+  xy64_planes<T>(U, goct, g, tw64, a, g.M3 == 1 ? 1 : 2, b, R);
+}
+
+// One plane per workgroup.  The two planes of a pair read the same spectrum
+// slab; they go to workgroups b and b + 8 (same XCD under round-robin
+// dispatch, launched one after the other) so the second read hits L2.
 template <typename T>
 __global__ __launch_bounds__(256) void k_xy64(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, Geom g,
                                               const cx<T>* __restrict__ tw64) {
   extern __shared__ unsigned char smem_raw[];
-  xy64_body<T>(U, goct, g, tw64, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+  const int b = blockIdx.x;
+  const int base = (b / 16) * 16, r = b - base;
+  int pa, pb;
+  pair_planes(base / 2 + (r % 8), g.M3, &pa, &pb);
+  xy64_planes<T>(U, goct, g, tw64, r < 8 ? pa : pb, 1, 0, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 template <typename T>
@@ -241,6 +261,13 @@ __global__ __launch_bounds__(256) void k_xy64_batch(const PassDesc* __restrict__
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_xy64_batch_single(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct,
+                                                           Geom g, const cx<T>* __restrict__ tw64) {
+  extern __shared__ unsigned char smem_raw[];
+  xy64_body<T>(U, goct, g, tw64, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
+template <typename T>
 hipError_t launch_xy64_batch(const PassDesc* d, const int* prefix, int nsys, int total, hipStream_t s) {
   const size_t lds = (size_t)3 * 32 * 64 * sizeof(cx<T>);
   hipLaunchKernelGGL((k_xy64_batch<T>), dim3(total < 4096 ? total : 4096), dim3(256), lds, s, d, prefix, nsys,
@@ -253,8 +280,12 @@ template hipError_t launch_xy64_batch<float>(const PassDesc*, const int*, int, i
 template <typename T>
 hipError_t launch_xy64(const Geom& g, void* U, const void* goct, const void* tw1, hipStream_t s) {
   const size_t lds = (size_t)3 * 32 * 64 * sizeof(cx<T>);
-  const int blocks = g.M3 == 1 ? 1 : g.M3 / 2;
-  hipLaunchKernelGGL((k_xy64<T>), dim3(blocks), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
+  if (g.M3 % 16 != 0) {   // short z circulant: one workgroup per plane pair
+    hipLaunchKernelGGL((k_xy64_batch_single<T>), dim3(g.M3 == 1 ? 1 : g.M3 / 2), dim3(256), lds, s, (cx<T>*)U,
+                       (const cx<T>*)goct, g, (const cx<T>*)tw1);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_xy64<T>), dim3(g.M3), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
                      (const cx<T>*)tw1);
   return hipGetLastError();
 }
@@ -263,6 +294,9 @@ template <typename T>
 hipError_t allow_lds_xy64() {
   hipError_t e = hipFuncSetAttribute((const void*)k_xy64<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)((size_t)3 * 32 * 64 * sizeof(cx<T>)));
+  if (e) return e;
+  e = hipFuncSetAttribute((const void*)k_xy64_batch_single<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)((size_t)3 * 32 * 64 * sizeof(cx<T>)));
   if (e) return e;
   return hipFuncSetAttribute((const void*)k_xy64_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)((size_t)3 * 32 * 64 * sizeof(cx<T>)));

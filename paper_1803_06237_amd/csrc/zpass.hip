@@ -27,6 +27,16 @@ template <int A>
 __device__ __forceinline__ int xslot(int p, int M, int k1, int a) {
   return p * M + k1 * A + ((a + k1) & (A - 1));
 }
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD b % 8).
+// Pencil blocks 2q and 2q+1 touch the two halves of the same cache lines of the
+// intermediate, so map them to workgroups b and b + 8: same XCD (same L2),
+// dispatched one after the other.  Identity on a tail shorter than 16.
+__device__ __forceinline__ int xcd_pair(int b, int nblocks) {
+  const int base = (b / 16) * 16;
+  if (base + 16 > nblocks) return b;
+  const int r = b - base;
+  return base + 2 * (r % 8) + r / 8;
+}
 }  // namespace
 
 template <typename T, int A, int B>
@@ -90,7 +100,7 @@ template <typename T, int A, int B>
 __global__ __launch_bounds__(256) void k_zfwd4(const cx<T>* __restrict__ x, cx<T>* __restrict__ U, Geom g,
                                                 int P, const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
-  zfwd4_body<T, A, B>(x, U, g, P, tw, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+  zfwd4_body<T, A, B>(x, U, g, P, tw, xcd_pair(blockIdx.x, gridDim.x), reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 template <typename T, int A, int B, int MODE>
@@ -158,7 +168,8 @@ __global__ __launch_bounds__(256) void k_zinv4(const cx<T>* __restrict__ U, cons
                                                 const cx<T>* __restrict__ chi, Geom g, int P,
                                                 const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
-  zinv4_body<T, A, B, MODE>(U, x, y, bvec, chi, g, P, tw, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+  zinv4_body<T, A, B, MODE>(U, x, y, bvec, chi, g, P, tw, xcd_pair(blockIdx.x, gridDim.x),
+                            reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 // Launch: returns hipErrorNotSupported when (M3, precision) has no four-step

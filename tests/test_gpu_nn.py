@@ -68,7 +68,7 @@ def test_training_reduces_the_loss_and_apply_is_deterministic():
     vt = torch.from_numpy(v).cuda()
     r = plan.matvec(vt)                  # training pair (A v, v)
     chi = _chi(wg)
-    losses = [net.train_step([r], [chi], [vt], lr=2e-3) for _ in range(40)]
+    losses = [net.train_step([r], [chi], [vt], lr=2e-3) for _ in range(40)]   # learns v - A v
     print(losses[0], losses[-1])
     assert losses[-1] < 0.5 * losses[0]
     z1 = net.apply(r, chi)
