@@ -8,7 +8,9 @@ Green product, inverse z FFT with the fused contrast.  Inputs are resident in
 HBM before the timed region.  After the timed steps the same operator is solved
 to a relative residual of 1e-8 from a dipole source with FP64 GMRES(50) and with
 the FP32-inner / FP64-outer flexible GMRES, and the oracle's FFT matvec is timed
-on the host as the CPU baseline.
+on the host as the CPU baseline.  Unless skipped, the 64-system absorber family is
+solved as one batch (reflection slopes reported) and the learned preconditioner
+is trained and compared on 32 x 32 x 256 rough guides.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
 
@@ -101,6 +103,36 @@ def cpu_baseline(n, seconds_budget=30.0):
                       f"{el:.1f} s"}
 
 
+def learned_comparison(n_geom: int = 32, epochs: int = 4):
+    """Train the network on seeded rough guides (32x32x256) and compare time to 1e-8 of FP64
+    GMRES(50), mixed FGMRES and learned FGMRES on two unseen guides."""
+    import torch
+
+    from paper_1803_06237_amd import inputs, learned
+    t0 = time.perf_counter()
+    tr = learned.Trainer((32, 32, 256), 0.025, seed=0)
+    for s in range(n_geom):
+        tr.add_geometry(inputs.rough_strip(s), n_operator_pairs=8)
+    losses = tr.train(epochs=epochs, lr=2e-3, batch=4, lr_decay=0.6)
+    train_s = time.perf_counter() - t0
+    res = {}
+    for seed in (10000, 10001):
+        wg = inputs.rough_strip(seed)
+        tr.plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+        b = tr.plan.rhs(torch.from_numpy(inputs.transverse_dipole_field(wg)).cuda())
+        cmp_ = learned.compare_tiers(tr.plan, tr.net, b)
+        res[str(seed)] = {k: {"seconds": round(v["wall"], 4), "outer_iters": v["iters"],
+                              "inner_or_net_applications": v["inner_iters"], "fallback": v["fallback"],
+                              "rel_res_fp64": v["rel_res_fp64"]} for k, v in cmp_.items()}
+    sp = [v["fp64"]["seconds"] / v["learned"]["seconds"] for v in res.values()]
+    spm = [v["fp64"]["seconds"] / v["mixed"]["seconds"] for v in res.values()]
+    return {"workload": "32x32x256 rough-sidewall guides (sigma 1 voxel, corr 8), quadratic 1 um absorbers; "
+                        f"trained on {n_geom} geometries x 8 operator pairs, {epochs} epochs",
+            "train_seconds": round(train_s, 2), "loss_first": round(losses[0], 4), "loss_last": round(losses[-1], 4),
+            "test": res, "learned_speedup_vs_fp64": round(float(np.mean(sp)), 3),
+            "mixed_speedup_vs_fp64": round(float(np.mean(spm)), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +140,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-family", action="store_true", help="skip the 64-system absorber-family batch")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--profile", action="store_true",
                     help="profiler run: one device copy of a vector (counter calibration, bytes known) and the "
                          "timed FP64 products only")
@@ -136,7 +170,7 @@ def main():
     if args.profile:
         y.copy_(x)        # calibration: reads and writes exactly 3N * 16 bytes
         torch.cuda.synchronize()
-        args.no_solve = args.no_cpu = True
+        args.no_solve = args.no_cpu = args.no_family = args.no_learned = True
     for _ in range(args.warmup):
         plan.matvec(x, y)
     torch.cuda.synchronize()
@@ -207,6 +241,20 @@ def main():
                          "unknown_iterations_per_s": round(3 * wg.N * its / dt, 1)}
         res["mixed_speedup_vs_fp64"] = round(res["fp64_gmres50"]["seconds"] / res["mixed_fgmres"]["seconds"], 3)
         out["solve_to_1e-8"] = res
+
+    if not args.no_family:
+        from paper_1803_06237_amd import experiments
+        fam = experiments.run_family(precision=1, restart=30)
+        out["batched_family"] = {
+            "workload": "64 systems, 32x32x{192,256,320,512,832}, absorbers L in {0.5,1,2,4,8} um x d in 0..3, "
+                        "20 dipole + 44 Gaussian rhs, FP32-inner/FP64-outer FGMRES, one vie_solve_batch call",
+            "solve_seconds": round(fam["solve_seconds"], 3), "plan_seconds": round(fam["plan_seconds"], 3),
+            "unknowns_total": fam["unknowns"], "max_rel_res_fp64": fam["max_rel_res"],
+            "reflection_slopes": fam["slopes"], "predicted_slopes": {str(d): -2 * (d + 1) for d in range(4)},
+            "reflection": fam["reflection"]}
+
+    if not args.no_learned:
+        out["learned_preconditioner"] = learned_comparison()
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)
