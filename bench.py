@@ -106,6 +106,7 @@ def cpu_baseline(n, seconds_budget=30.0):
 def learned_comparison(n_geom: int = 32, epochs: int = 4):
     """Train the network on seeded rough guides (32x32x256) and compare time to 1e-8 of FP64
     GMRES(50), mixed FGMRES and learned FGMRES on two unseen guides."""
+    import numpy as np
     import torch
 
     from paper_1803_06237_amd import inputs, learned

@@ -1,0 +1,147 @@
+"""Pins of the oracle's block-circulant preconditioner (Section V-D) against facts
+that do not depend on its code: the independently pinned dense operator, the
+first-order optimality of a Frobenius least-squares fit, T. Chan's closed form
+for a Toeplitz matrix, and the DFT diagonalisation of a block circulant."""
+import numpy as np
+import pytest
+
+from oracle import circulant as circ
+from oracle import green, matvec as mv
+from oracle import solve
+from paper_1803_06237_amd import inputs
+
+RNG = np.random.default_rng(5)
+KAPPA = 0.31
+
+
+def _case(n=(3, 3, 7), cols=((0, 0), (1, 1), (2, 1), (1, 2)), z_varying=True):
+    """Contrast on a few cross-section columns, varying along z (an absorber-like ramp) or not."""
+    chi = np.zeros(n, dtype=np.complex128)
+    for (i1, i2) in cols:
+        base = 2.0 + 0.3 * i1 - 0.2j * i2
+        ramp = 1.0 + 0.4j * np.linspace(0, 1, n[2]) ** 2 if z_varying else np.ones(n[2])
+        chi[i1, i2, :] = base * ramp
+    table = green.green_table(n, KAPPA)
+    return table, chi
+
+
+def _support_perm(n, S):
+    """Rows of the (3, n1, n2, n3) flattening in the slice-major support order (i3, a, p)."""
+    n1, n2, n3 = n
+    idx = []
+    for i3 in range(n3):
+        for a in range(3):
+            for (i1, i2) in S:
+                idx.append(((a * n1 + i1) * n2 + i2) * n3 + i3)
+    return np.array(idx)
+
+
+def test_support_operator_is_the_dense_operator_restricted():
+    table, chi = _case()
+    S = circ.support_columns(chi)
+    A = mv.dense_A(table, chi)
+    perm = _support_perm(chi.shape, S)
+    assert np.allclose(circ.dense_A_on_support(table, chi, S), A[np.ix_(perm, perm)], atol=1e-14, rtol=0)
+
+
+@pytest.mark.parametrize("z_varying", [False, True])
+def test_blocks_satisfy_frobenius_normal_equations(z_varying):
+    """W minimises ||A - circ(W)||_F over block circulants iff, for every k, the blocks of
+    A on the wrapped diagonal k sum to n3 W_k.  A comes from the dense operator."""
+    table, chi = _case(z_varying=z_varying)
+    n3 = chi.shape[2]
+    S = circ.support_columns(chi)
+    m = 3 * len(S)
+    A = mv.dense_A(table, chi)
+    perm = _support_perm(chi.shape, S)
+    As = A[np.ix_(perm, perm)]
+    W = circ.optimal_blocks(table, chi, S)
+    for k in range(n3):
+        acc = np.zeros((m, m), dtype=np.complex128)
+        for i in range(n3):
+            j = (i - k) % n3
+            acc += As[i * m:(i + 1) * m, j * m:(j + 1) * m]
+        assert np.allclose(acc / n3, W[k], atol=1e-14, rtol=0)
+    # and any block-circulant perturbation increases the distance
+    C = circ.block_circulant_dense(W)
+    base = np.linalg.norm(As - C)
+    for _ in range(3):
+        E = RNG.standard_normal(W.shape) + 1j * RNG.standard_normal(W.shape)
+        assert np.linalg.norm(As - circ.block_circulant_dense(W + 1e-3 * E)) > base
+
+
+def test_uniform_contrast_reduces_to_chans_optimal_circulant():
+    """With chi constant along z, each Toeplitz level t_k of a fixed (p, q) entry maps to
+    ((n - k) t_k + k t_{k-n}) / n (T. Chan, SIAM J. Sci. Stat. Comput. 9, 1988)."""
+    table, chi = _case(z_varying=False)
+    n3 = chi.shape[2]
+    S = circ.support_columns(chi)
+    s = len(S)
+    W = circ.optimal_blocks(table, chi, S)
+    T = mv.signed_table(table)                    # (3, 3, 2n1-1, 2n2-1, 2n3-1), offset + n - 1
+    n1, n2, _ = chi.shape
+    for k in range(n3):
+        for (pi, p) in enumerate(S):
+            for (qi, q) in enumerate(S):
+                d1, d2 = p[0] - q[0] + n1 - 1, p[1] - q[1] + n2 - 1
+                dp = chi[p[0], p[1], 0]
+                for a in range(3):
+                    for b in range(3):
+                        tk = T[a, b, d1, d2, k + n3 - 1]
+                        tkn = T[a, b, d1, d2, k - n3 + n3 - 1] if k > 0 else 0.0
+                        want = ((n3 - k) * tk + k * tkn) / n3
+                        want = (1.0 if (k == 0 and a == b and pi == qi) else 0.0) - dp * want
+                        assert abs(W[k, a * s + pi, b * s + qi] - want) < 1e-14
+
+
+def test_fft_apply_solves_the_block_circulant():
+    table, chi = _case()
+    n = chi.shape
+    S = circ.support_columns(chi)
+    W = circ.optimal_blocks(table, chi, S)
+    Winv = circ.spectrum_inverse(W)
+    r = RNG.standard_normal((3,) + n) + 1j * RNG.standard_normal((3,) + n)
+    z = circ.apply(Winv, S, r)
+    perm = _support_perm(n, S)
+    zs = np.linalg.solve(circ.block_circulant_dense(W), r.ravel()[perm])
+    assert np.allclose(z.ravel()[perm], zs, atol=1e-12, rtol=0)
+    outside = np.ones(3 * np.prod(n), dtype=bool)
+    outside[perm] = False
+    assert np.array_equal(z.ravel()[outside], r.ravel()[outside])
+
+
+def test_zero_contrast_gives_identity():
+    n = (2, 3, 5)
+    table = green.green_table(n, KAPPA)
+    chi = np.zeros(n, dtype=np.complex128)
+    chi[1, 1, :] = 0.0
+    chi[0, 0, 2] = 1e-300          # a single column with a negligible contrast
+    S = circ.support_columns(chi)
+    W = circ.optimal_blocks(table, chi, S)
+    assert np.allclose(W[0], np.eye(3 * len(S)), atol=1e-290)
+    assert np.allclose(W[1:], 0, atol=1e-290)
+
+
+def test_preconditioner_cuts_iterations_and_keeps_the_solution():
+    """Right-preconditioned FGMRES reaches the same 1e-8 solution in fewer iterations on a
+    small absorbing guide, and its count does not grow with the length."""
+    counts = {}
+    for n3 in (32, 64):
+        wg = inputs.Waveguide(n=(6, 6, n3), h=0.05, core_x=(1, 5), core_y=(2, 4), core_z=(0, n3), n_abs=8,
+                              d=2, sigma_max=2.0)
+        kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+        table = green.green_table(wg.n, kap)
+        chi = mv.contrast(wg.eps(), wg.eps_b)
+        op = mv.Operator(table, chi)
+        S = circ.support_columns(chi)
+        Winv = circ.spectrum_inverse(circ.optimal_blocks(table, chi, S))
+        b = mv.rhs_from_field(wg.eps(), wg.eps_b, inputs.gaussian_rhs(wg.n, 1), wg.h).ravel()
+        pc = lambda v: circ.apply(Winv, S, v.reshape((3,) + wg.n)).ravel()
+        x0, i0 = solve.gmres(op, b, tol=1e-8, restart=400)
+        x1, i1 = solve.fgmres(op, b, tol=1e-8, restart=400, precond=pc)
+        assert i0.converged and i1.converged
+        assert np.linalg.norm(x1 - x0) <= 1e-6 * np.linalg.norm(x0)
+        counts[n3] = (i0.iters, i1.iters)
+    for n3, (plain, pre) in counts.items():
+        assert pre < plain / 2, counts
+    assert counts[64][1] <= counts[32][1] + 3, counts
