@@ -130,7 +130,9 @@ typedef struct {
   int maxit;          /* total outer iterations; <= 0 -> 10000 */
   int use_x0;         /* 1: x holds the initial guess; 0: start from zero */
   int precision;      /* 0: FP64 GMRES; 1: mixed (FP32 inner GMRES, FP64 outer FGMRES);
-                         2: learned (FP64 FGMRES with the attached network, plain GMRES fallback) */
+                         2: learned (FP64 FGMRES with the attached network, plain GMRES fallback);
+                         3: FP64 FGMRES right-preconditioned by the block circulant of
+                            vie_circulant_build */
   int inner_restart;  /* mixed tier: inner GMRES dimension; <= 0 -> 20 */
   double inner_tol;   /* mixed tier: inner relative tolerance; <= 0 -> 1e-4 */
   int use_graph;      /* vie_solve_batch: 1 = capture one restart cycle as a HIP graph and replay it */
@@ -138,7 +140,8 @@ typedef struct {
 
 typedef struct {
   int iters;          /* outer Arnoldi steps */
-  int inner_iters;    /* FP32 matvecs spent in inner solves (mixed tier) */
+  int inner_iters;    /* FP32 matvecs spent in inner solves (mixed tier); preconditioner
+                         applications (learned and circulant tiers) */
   int restarts;
   int matvecs;        /* FP64 matvecs (incl. residual checks) */
   int status;         /* same code as returned */
@@ -177,6 +180,45 @@ int vie_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol,
  */
 int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* rhs, vie_c128* const* x, int count,
                     double tol, const vie_solve_opts* opts, vie_solve_info* infos);
+
+/*
+ * Block-circulant preconditioner (Section V-D: the block circulant W nearest to
+ * I - M_eps N in the Frobenius norm, after Chan and Olkin's preconditioners for
+ * Toeplitz-block matrices; the paper's conclusion allows a circulant
+ * approximation on one or more of the three Toeplitz levels).  This version
+ * takes the circulant along the third axis (the long guide axis, n3 slices)
+ * and keeps each cross-section block dense on the support S of the contrast
+ * (the voxel columns (i1, i2) where chi is non-zero on some slice; m = 3|S|):
+ *
+ *   W_k = delta_k0 I - (1/n3) [ U_k N_k + (U_0 - U_k) N_{k - n3} ],
+ *   U_k = diag over S of sum_{i3 >= k} chi(i1, i2, i3),
+ *
+ * with N_k the m x m block of N between slices k apart.  Voxels outside S keep
+ * the identity.  The DFT along the slices turns W into n3 dense m x m blocks,
+ * which are inverted once (FP64 Gauss-Jordan with partial pivoting on the
+ * device); the inverses are kept in FP32 (flags 0) or FP64 (VIE_CIRC_FP64).
+ *
+ * vie_circulant_build: for the plan's current contrast (set_contrast first; a
+ *   later set_contrast releases it).  Limits: m <= 2048, and 2 n3 m^2 * 16 bytes
+ *   of device memory during set-up (VIE_ENOMEM otherwise).  VIE_ENUMERIC if a
+ *   frequency block is singular.  info (host, may be NULL) receives the sizes,
+ *   the device bytes of the kept inverses and the set-up time.  Synchronises.
+ * vie_circulant_apply: z = W^{-1} r; r, z device, 3N values, no overlap.
+ *   Asynchronous on the plan's stream.  vie_solve with precision 3 uses it.
+ */
+enum { VIE_CIRC_FP32 = 0, VIE_CIRC_FP64 = 1 };
+
+typedef struct {
+  int support_columns;   /* |S| */
+  int block_size;        /* m = 3 |S| */
+  int blocks;            /* n3 (0 when S is empty: W = I) */
+  int fp64;              /* 1: inverse blocks kept in FP64 */
+  size_t bytes;          /* device bytes of the inverse blocks */
+  double seconds;        /* set-up wall time */
+} vie_circulant_info;
+
+int vie_circulant_build(vie_plan_t plan, unsigned flags, vie_circulant_info* info);
+int vie_circulant_apply(vie_plan_t plan, const vie_c128* r, vie_c128* z);
 
 /*
  * vie_profile_matvec -- diagnostic.  Runs `reps` products y = (I - M_eps N) x on the

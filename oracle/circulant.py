@@ -112,3 +112,22 @@ def apply(Winv_hat: np.ndarray, S: np.ndarray, r: np.ndarray) -> np.ndarray:
     for a in range(3):
         z[a][S[:, 0], S[:, 1], :] = Z[a * s:(a + 1) * s]
     return z
+
+
+def frequency_block(table: np.ndarray, chi: np.ndarray, S: np.ndarray, f: int) -> np.ndarray:
+    """One DFT block What_f = sum_k W_k exp(-2 pi i f k / n3), accumulated one W_k at a
+    time (for full-size grids whose n3 blocks do not fit in memory together)."""
+    n3 = chi.shape[2]
+    s = len(S)
+    m = 3 * s
+    D = np.stack([np.tile(chi[S[:, 0], S[:, 1], i], 3) for i in range(n3)])
+    suffix = np.cumsum(D[::-1], axis=0)[::-1]            # suffix[k] = sum_{i >= k} D_i
+    total = suffix[0]
+    out = np.eye(m, dtype=np.complex128)
+    for k in range(n3):
+        ph = np.exp(-2j * np.pi * ((f * k) % n3) / n3)
+        Wk = -(suffix[k][:, None] * _N_block(table, S, k)) / n3
+        if k > 0:
+            Wk -= ((total - suffix[k])[:, None] * _N_block(table, S, k - n3)) / n3
+        out += ph * Wk
+    return out

@@ -126,6 +126,8 @@ struct vie_plan_s {
   int* flag = nullptr;
   bool has_contrast = false;
   vie_net_s* net = nullptr;    // learned preconditioner (not owned)
+  vie::Circ* circ = nullptr;   // block-circulant preconditioner of the current contrast
+  std::shared_ptr<const std::vector<std::complex<double>>> table;   // host Toeplitz table
   GmresWs<double> ws64;
   GmresWs<float> ws32;
   std::string err;
@@ -423,6 +425,7 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
     return bail(hipfail(nullptr, e, "hipFuncSetAttribute"));
   // host table
   const auto table = cached_table(grid, p->kappa);
+  p->table = table;
   const bool f32 = (flags & VIE_WITH_FP32) != 0;
   const long H = (long)g.H1 * g.H2 * g.H3;
   const long P = (long)g.M1 * g.M2 * g.M3;
@@ -469,6 +472,11 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
 int vie_set_contrast(vie_plan_t p, const vie_c128* eps) {
   if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
   if (!eps) return fail(p, VIE_EINVAL, "null eps");
+  if (p->circ) {
+    HIPTRY(p, hipStreamSynchronize(p->stream));
+    circ_destroy(p->circ);
+    p->circ = nullptr;
+  }
   HIPTRY(p, hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
   HIPTRY(p, launch_contrast(p->g.N, reinterpret_cast<const double2*>(eps), p->eps_b, p->chi64, p->chi32, p->flag,
                             p->stream));
@@ -615,6 +623,19 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
     }
     st.inner = napply;
     st.fallback = fell_back ? 1 : 0;
+  } else if (o.precision == 3) {
+    // FP64 FGMRES right-preconditioned by the block circulant: z = W^{-1} v
+    if (!p->circ) return fail(p, VIE_ESTATE, "no circulant preconditioner (vie_circulant_build)");
+    struct Pc {
+      vie_plan_s* p;
+      hipError_t operator()(const void* v, void* z, Stats& s) {
+        ++s.inner;
+        return circ_apply(p->circ, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(z), p->stream);
+      }
+    } pc{p};
+    status = gmres_core<double, Op64, Pc>(p, p->ws64, A, &pc, reinterpret_cast<const double2*>(b),
+                                          reinterpret_cast<double2*>(x), tol, o.restart, o.maxit, o.use_x0 != 0,
+                                          true, st);
   } else {
     return fail(p, VIE_EINVAL, "unknown precision tier");
   }
@@ -686,8 +707,45 @@ int vie_set_preconditioner(vie_plan_t p, vie_net_t net) {
   return VIE_OK;
 }
 
+int vie_circulant_build(vie_plan_t p, unsigned flags, vie_circulant_info* info) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (flags & ~1u) return fail(p, VIE_EINVAL, "unknown circulant flags");
+  if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
+  if (p->circ) {
+    HIPTRY(p, hipStreamSynchronize(p->stream));
+    circ_destroy(p->circ);
+    p->circ = nullptr;
+  }
+  std::string err;
+  CircInfo ci{};
+  const int rc = circ_build(&p->circ, p->g, p->table->data(), p->chi64, (flags & VIE_CIRC_FP64) != 0, p->stream, err,
+                            &ci);
+  if (rc != VIE_OK) return fail(p, rc, err);
+  if (info) {
+    info->support_columns = ci.s;
+    info->block_size = ci.m;
+    info->blocks = ci.s ? p->g.n3 : 0;
+    info->fp64 = ci.fp64;
+    info->bytes = ci.bytes;
+    info->seconds = ci.seconds;
+  }
+  return VIE_OK;
+}
+
+int vie_circulant_apply(vie_plan_t p, const vie_c128* r, vie_c128* z) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!r || !z || (const void*)r == (const void*)z) return fail(p, VIE_EINVAL, "r, z null or aliased");
+  if (!p->circ) return fail(p, VIE_ESTATE, "no circulant preconditioner (vie_circulant_build)");
+  HIPTRY(p, circ_apply(p->circ, reinterpret_cast<const double2*>(r), reinterpret_cast<double2*>(z), p->stream));
+  return VIE_OK;
+}
+
 void vie_destroy(vie_plan_t p) {
   if (!p) return;
+  if (p->circ) {
+    (void)hipStreamSynchronize(p->stream);
+    circ_destroy(p->circ);
+  }
   p->ws64.release();
   p->ws32.release();
   for (void* q : {(void*)p->goct64, (void*)p->goct32, (void*)p->chi64, (void*)p->chi32, (void*)p->U64,

@@ -4,6 +4,7 @@
 
 #include <complex>
 #include <cstddef>
+#include <string>
 
 namespace vie {
 
@@ -84,6 +85,23 @@ bool z4_shape(int M3, int* A, int* B, int* P);
 // ---- Krylov building blocks (krylov.hip) -----------------------------------
 template <typename T>
 struct KrylovWork;
+
+// ---- block-circulant preconditioner (circulant.hip) -------------------------
+struct CircInfo {
+  int s;          // support columns
+  int m;          // block size 3 s
+  int fp64;       // 1: inverse blocks kept in FP64
+  size_t bytes;   // device bytes of the inverse blocks
+  double seconds; // set-up wall time
+};
+struct Circ;
+// Builds W^{-1} for the contrast chi64 (device, FP64) with the host Toeplitz table.
+int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, const double2* chi64, bool fp64,
+               hipStream_t s, std::string& err, CircInfo* info);
+// z = W^{-1} r on FP64 device vectors of 3N values (no overlap).
+hipError_t circ_apply(Circ* c, const double2* r, double2* z, hipStream_t s);
+void circ_destroy(Circ* c);
+const CircInfo& circ_info(const Circ* c);
 
 // LDS budget the kernels may use per workgroup (queried once per device)
 size_t lds_budget(int device);

@@ -44,6 +44,14 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CirculantInfo(ctypes.Structure):
+    _fields_ = [("support_columns", ctypes.c_int), ("block_size", ctypes.c_int), ("blocks", ctypes.c_int),
+                ("fp64", ctypes.c_int), ("bytes", ctypes.c_size_t), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def lib() -> ctypes.CDLL:
     """Load libvie.so (built by paper_1803_06237_amd.build); raise if it is missing."""
     global _lib
@@ -83,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.vie_net_train_step.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                          ctypes.POINTER(vp), ctypes.c_float, ctypes.POINTER(ctypes.c_double)]
         L.vie_set_preconditioner.argtypes = [vp, vp]
+        L.vie_circulant_build.argtypes = [vp, ctypes.c_uint, ctypes.POINTER(CirculantInfo)]
+        L.vie_circulant_apply.argtypes = [vp, vp, vp]
         L.vie_nn_conv_test.argtypes = [ctypes.c_int, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                        ctypes.c_int, vp]
         L.vie_net_last_error.restype = ctypes.c_char_p
@@ -214,10 +224,26 @@ class Plan:
         _check(lib().vie_set_preconditioner(self._h, net.handle if net is not None else None), self._h)
         self._net = net
 
+    def build_circulant(self, fp64: bool = False) -> dict:
+        """Block-circulant preconditioner of the current contrast (vie_circulant_build)."""
+        info = CirculantInfo()
+        _check(lib().vie_circulant_build(self._h, 1 if fp64 else 0, ctypes.byref(info)), self._h)
+        return info.as_dict()
+
+    def apply_circulant(self, r, z=None):
+        """z = W^{-1} r (vie_circulant_apply)."""
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().vie_circulant_apply(self._h, _ptr(r, torch.complex128, 3 * self.N, "r"),
+                                         _ptr(z, torch.complex128, 3 * self.N, "z")), self._h)
+        return z
+
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000,
               precision: int = 0, use_x0: bool = False, inner_restart: int = 20,
               inner_tol: float = 1e-4, raise_on_noconv: bool = False):
-        """GMRES(restart) (precision 0) or FP32-inner / FP64-outer FGMRES (precision 1).
+        """GMRES(restart) (precision 0), FP32-inner / FP64-outer FGMRES (1), learned (2) or
+        circulant-preconditioned FGMRES (3, after build_circulant).
 
         Returns (x, info dict).  info['status'] is VIE_OK or VIE_ENOCONV."""
         import torch

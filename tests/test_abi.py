@@ -71,4 +71,6 @@ def test_plan_rejects_bad_arguments_before_touching_the_device():
     # null plans are rejected by every call
     assert L.vie_matvec(None, None, None) == vie.VIE_EINVAL
     assert L.vie_set_contrast(None, None) == vie.VIE_EINVAL
+    assert L.vie_circulant_build(None, 0, None) == vie.VIE_EINVAL
+    assert L.vie_circulant_apply(None, None, None) == vie.VIE_EINVAL
     L.vie_destroy(None)

@@ -145,3 +145,12 @@ def test_preconditioner_cuts_iterations_and_keeps_the_solution():
     for n3, (plain, pre) in counts.items():
         assert pre < plain / 2, counts
     assert counts[64][1] <= counts[32][1] + 3, counts
+
+
+def test_single_frequency_block_matches_the_fft_of_all_blocks():
+    table, chi = _case()
+    S = circ.support_columns(chi)
+    W = circ.optimal_blocks(table, chi, S)
+    What = np.fft.fft(W, axis=0)                  # library DFT, independent of the oracle's FFT
+    for f in (0, 1, 4):
+        assert np.allclose(circ.frequency_block(table, chi, S, f), What[f], atol=1e-13, rtol=0)
