@@ -135,6 +135,27 @@ struct IoVoxelOut {  // rows[seq][t] -> FP64 voxel vector (through the support m
   }
 };
 
+template <typename T>
+struct IoRowsIn {    // FP64 support-compressed vector rows[seq][t] -> rows of T
+  const double2* r;
+  cx<T>* rows;
+  int n3;
+  __device__ cx<T> load(long seq, int t) const {
+    const double2 v = r[seq * n3 + t];
+    return cx<T>{(T)v.x, (T)v.y};
+  }
+  __device__ void store(long seq, int t, cx<T> v) const { rows[seq * n3 + t] = v; }
+};
+
+template <typename T>
+struct IoRowsOut {   // rows of T -> FP64 support-compressed vector
+  const cx<T>* rows;
+  double2* z;
+  int n3;
+  __device__ cx<T> load(long seq, int t) const { return rows[seq * n3 + t]; }
+  __device__ void store(long seq, int t, cx<T> v) const { z[seq * n3 + t] = double2{(double)v.x, (double)v.y}; }
+};
+
 struct IoBlocks {    // Wt[e][k] -> What[f][e]
   const double2* Wt;
   double2* Wh;
@@ -590,17 +611,18 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
   }
   CTRY(hipMalloc(&c->xhat, es * (size_t)m * n3));
   CTRY(hipMalloc(&c->yhat, es * (size_t)m * n3));
-  const size_t lds_need = 3 * (size_t)n3 * es;
+  const int lds_need = (int)(3 * (size_t)n3 * es);
+  const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
   if (fp64) {
-    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, false, IoVoxelIn<double>>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_need));
-    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, true, IoVoxelOut<double>>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_need));
+    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, false, IoVoxelIn<double>>, attr, lds_need));
+    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, true, IoVoxelOut<double>>, attr, lds_need));
+    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, false, IoRowsIn<double>>, attr, lds_need));
+    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, true, IoRowsOut<double>>, attr, lds_need));
   } else {
-    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<float, false, IoVoxelIn<float>>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_need));
-    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<float, true, IoVoxelOut<float>>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_need));
+    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<float, false, IoVoxelIn<float>>, attr, lds_need));
+    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<float, true, IoVoxelOut<float>>, attr, lds_need));
+    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<float, false, IoRowsIn<float>>, attr, lds_need));
+    CTRY(hipFuncSetAttribute((const void*)k_circ_fft<float, true, IoRowsOut<float>>, attr, lds_need));
   }
   c->info.bytes = (fp64 ? sizeof(double2) : sizeof(float2)) * (size_t)n3 * m2;
   c->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -610,17 +632,33 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
 }
 
 namespace {
-template <typename T>
-hipError_t apply_t(Circ* c, const cx<T>* inv, const double2* r, double2* z, hipStream_t s) {
-  const long n12 = (long)c->n1 * c->n2;
+// forward FFT of every support row, one product per frequency, inverse FFT
+template <typename T, class IN, class OUT>
+hipError_t apply_t(Circ* c, const cx<T>* inv, const IN& in, const OUT& out, hipStream_t s) {
   auto* xh = reinterpret_cast<cx<T>*>(c->xhat);
   auto* yh = reinterpret_cast<cx<T>*>(c->yhat);
-  hipError_t e = launch_fft<T, false>(c->rd, c->tw, IoVoxelIn<T>{r, xh, c->col, c->s, n12, c->n3}, c->m, 1.0, s);
+  hipError_t e = launch_fft<T, false>(c->rd, c->tw, in, c->m, 1.0, s);
   if (e) return e;
   hipLaunchKernelGGL(k_circ_gemv<T>, dim3((c->m + kGemvRows - 1) / kGemvRows, c->n3), dim3(kThreads), 0, s, inv, xh,
                      yh, c->m, c->n3);
   if ((e = hipGetLastError())) return e;
-  return launch_fft<T, true>(c->rd, c->tw, IoVoxelOut<T>{yh, z, c->col, c->s, n12, c->n3}, c->m, 1.0 / c->n3, s);
+  return launch_fft<T, true>(c->rd, c->tw, out, c->m, 1.0 / c->n3, s);
+}
+
+template <typename T>
+hipError_t apply_voxels(Circ* c, const cx<T>* inv, const double2* r, double2* z, hipStream_t s) {
+  const long n12 = (long)c->n1 * c->n2;
+  auto* xh = reinterpret_cast<cx<T>*>(c->xhat);
+  auto* yh = reinterpret_cast<cx<T>*>(c->yhat);
+  return apply_t<T>(c, inv, IoVoxelIn<T>{r, xh, c->col, c->s, n12, c->n3},
+                    IoVoxelOut<T>{yh, z, c->col, c->s, n12, c->n3}, s);
+}
+
+template <typename T>
+hipError_t apply_rows(Circ* c, const cx<T>* inv, const double2* r, double2* z, hipStream_t s) {
+  auto* xh = reinterpret_cast<cx<T>*>(c->xhat);
+  auto* yh = reinterpret_cast<cx<T>*>(c->yhat);
+  return apply_t<T>(c, inv, IoRowsIn<T>{r, xh, c->n3}, IoRowsOut<T>{yh, z, c->n3}, s);
 }
 }  // namespace
 
@@ -628,7 +666,12 @@ hipError_t circ_apply(Circ* c, const double2* r, double2* z, hipStream_t s) {
   const long n = 3 * (long)c->n1 * c->n2 * c->n3;
   hipError_t e = hipMemcpyAsync(z, r, sizeof(double2) * n, hipMemcpyDeviceToDevice, s);
   if (e || c->s == 0) return e;
-  return c->fp64 ? apply_t<double>(c, c->inv64, r, z, s) : apply_t<float>(c, c->inv32, r, z, s);
+  return c->fp64 ? apply_voxels<double>(c, c->inv64, r, z, s) : apply_voxels<float>(c, c->inv32, r, z, s);
+}
+
+hipError_t circ_apply_rows(Circ* c, const double2* r, double2* z, hipStream_t s) {
+  if (c->s == 0) return hipSuccess;
+  return c->fp64 ? apply_rows<double>(c, c->inv64, r, z, s) : apply_rows<float>(c, c->inv32, r, z, s);
 }
 
 const CircInfo& circ_info(const Circ* c) { return c->info; }

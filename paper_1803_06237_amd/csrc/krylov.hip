@@ -273,6 +273,43 @@ __global__ void k_set_g(double2* gvec, int m, const double2* sumsq) {
   if (threadIdx.x == 0) gvec[0] = double2{sqrt(sumsq->x), 0.0};
 }
 
+// ---- support compression ------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather(const cx<T>* __restrict__ full, cx<T>* comp, const cx<T>* sub,
+                                                      const int* __restrict__ col, int s, long n12, int n3) {
+  const long total = 3L * s * n3;
+  for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < total; e += (long)gridDim.x * kThreads) {
+    const long row = e / n3;
+    const int t = (int)(e - row * n3);
+    const int a = (int)(row / s), p = (int)(row - (long)a * s);
+    const cx<T> v = full[((long)a * n12 + col[p]) * n3 + t];
+    comp[e] = sub ? cx<T>{sub[e].x - v.x, sub[e].y - v.y} : v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter(const cx<T>* __restrict__ comp, cx<T>* __restrict__ full,
+                                                       const int* __restrict__ col, int s, long n12, int n3,
+                                                       int zero) {
+  const long total = 3L * s * n3;
+  for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < total; e += (long)gridDim.x * kThreads) {
+    const long row = e / n3;
+    const int t = (int)(e - row * n3);
+    const int a = (int)(row / s), p = (int)(row - (long)a * s);
+    full[((long)a * n12 + col[p]) * n3 + t] = zero ? cx<T>{(T)0, (T)0} : comp[e];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_column_flags(const double2* __restrict__ chi, long n12, int n3,
+                                                            int* __restrict__ flags) {
+  const long c = (long)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= n12) return;
+  const double2* z = chi + c * n3;
+  int any = 0;
+  for (int t = 0; t < n3; ++t) any |= (z[t].x != 0.0 || z[t].y != 0.0) ? 1 : 0;
+  flags[c] = any;
+}
+
 // ------------------------------------------------------------------ host-side helpers
 
 static inline int nblocks(long n) { return (int)((n + kChunk - 1) / kChunk); }
@@ -355,5 +392,47 @@ template hipError_t convert<float, double>(const cx<float>*, cx<double>*, long, 
 template hipError_t convert<double, double>(const cx<double>*, cx<double>*, long, hipStream_t);
 
 int partial_blocks(long n) { return nblocks(n); }
+
+static inline int grid_for(long n) {
+  const long b = (n + kThreads - 1) / kThreads;
+  return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+template <typename T>
+hipError_t gather(const Support& u, const cx<T>* full, cx<T>* comp, const cx<T>* sub, hipStream_t s) {
+  if (u.s == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather<T>), dim3(grid_for(u.size())), dim3(kThreads), 0, s, full, comp, sub, u.col, u.s,
+                     u.n12, u.n3);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t scatter(const Support& u, const cx<T>* comp, cx<T>* full, hipStream_t s) {
+  if (u.s == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_scatter<T>), dim3(grid_for(u.size())), dim3(kThreads), 0, s, comp, full, u.col, u.s, u.n12,
+                     u.n3, 0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t zero_support(const Support& u, cx<T>* full, hipStream_t s) {
+  if (u.s == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_scatter<T>), dim3(grid_for(u.size())), dim3(kThreads), 0, s, nullptr, full, u.col, u.s,
+                     u.n12, u.n3, 1);
+  return hipGetLastError();
+}
+
+hipError_t column_flags(const double2* chi, long n12, int n3, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_column_flags, dim3((unsigned)((n12 + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, chi,
+                     n12, n3, flags);
+  return hipGetLastError();
+}
+
+template hipError_t gather<double>(const Support&, const cx<double>*, cx<double>*, const cx<double>*, hipStream_t);
+template hipError_t gather<float>(const Support&, const cx<float>*, cx<float>*, const cx<float>*, hipStream_t);
+template hipError_t scatter<double>(const Support&, const cx<double>*, cx<double>*, hipStream_t);
+template hipError_t scatter<float>(const Support&, const cx<float>*, cx<float>*, hipStream_t);
+template hipError_t zero_support<double>(const Support&, cx<double>*, hipStream_t);
+template hipError_t zero_support<float>(const Support&, cx<float>*, hipStream_t);
 
 }  // namespace vie

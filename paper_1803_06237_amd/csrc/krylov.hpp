@@ -29,6 +29,29 @@ struct KrylovOps {
 template <typename TS, typename TD>
 hipError_t convert(const cx<TS>* src, cx<TD>* dst, long n, hipStream_t s);
 
+// The voxel columns (i1, i2) where the contrast is non-zero on some slice.  A
+// maps vectors supported on these columns (all slices, all three components) to
+// vectors supported there, so Krylov vectors can be stored compressed:
+// comp[(a s + p) n3 + i3] = full[a][col[p]][i3] with col[p] = i1 n2 + i2.
+struct Support {
+  const int* col;   // device, s entries, increasing
+  int s;
+  long n12;         // n1 n2
+  int n3;
+  long size() const { return 3L * s * n3; }
+};
+// comp = full on the support (sub != nullptr: comp = sub - full on the support; may alias comp)
+template <typename T>
+hipError_t gather(const Support& u, const cx<T>* full, cx<T>* comp, const cx<T>* sub, hipStream_t s);
+// full on the support = comp (other entries untouched)
+template <typename T>
+hipError_t scatter(const Support& u, const cx<T>* comp, cx<T>* full, hipStream_t s);
+// full on the support = 0
+template <typename T>
+hipError_t zero_support(const Support& u, cx<T>* full, hipStream_t s);
+// flags[c] = 1 if chi[c][i3] != 0 for some i3, else 0 (c < n12)
+hipError_t column_flags(const double2* chi, long n12, int n3, int* flags, hipStream_t s);
+
 int partial_blocks(long n);
 
 }  // namespace vie

@@ -123,6 +123,19 @@ struct vie_plan_s {
   double2* rvec = nullptr;     // FP64 scratch vector (residuals)
   float2* v32a = nullptr;      // FP32 scratch vectors (mixed tier)
   float2* v32b = nullptr;
+  // support of the contrast (voxel columns with chi != 0 on some slice); the
+  // solver keeps its Krylov vectors compressed to these columns
+  int* colflag = nullptr;      // device, n1 n2 flags
+  int* scol = nullptr;         // device, ns column indices i1 n2 + i2, increasing
+  int ns = 0;
+  double2* fx = nullptr;       // full FP64 operator input, zero off the support
+  double2* fy = nullptr;       // full FP64 operator output
+  float2* fx32 = nullptr;      // the same in FP32 (mixed tier)
+  float2* fy32 = nullptr;
+  double2* bc = nullptr;       // compressed right-hand side and solution
+  double2* xc = nullptr;
+  double2* partial_full = nullptr;   // reduction scratch for full-length norms
+  double2* sumsq_full = nullptr;
   int* flag = nullptr;
   bool has_contrast = false;
   vie_net_s* net = nullptr;    // learned preconditioner (not owned)
@@ -223,6 +236,46 @@ struct Op32 {
   }
 };
 
+// The operator on support-compressed vectors: scatter into a full vector that is
+// zero off the support, FFT product, gather the support back.
+struct Op64c {
+  vie_plan_s* p;
+  Support u;
+  hipError_t full(const double2* xc) {
+    hipError_t e = scatter<double>(u, xc, p->fx, p->stream);
+    if (e) return e;
+    const void* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+    return launch_matvec<double>(p->g, p->t64, p->fx, p->fy, nullptr, 0, p->U64, p->goct64, p->chi64, tw, p->stream);
+  }
+  hipError_t apply(const double2* xc, double2* yc) {
+    hipError_t e = full(xc);
+    return e ? e : gather<double>(u, p->fy, yc, nullptr, p->stream);
+  }
+  hipError_t residual(const double2* xc, const double2* bc, double2* rc) {
+    hipError_t e = full(xc);
+    return e ? e : gather<double>(u, p->fy, rc, bc, p->stream);
+  }
+};
+struct Op32c {
+  vie_plan_s* p;
+  Support u;
+  hipError_t full(const float2* xc) {
+    hipError_t e = scatter<float>(u, xc, p->fx32, p->stream);
+    if (e) return e;
+    const void* tw[3] = {p->tw32[0], p->tw32[1], p->tw32[2]};
+    return launch_matvec<float>(p->g, p->t32, p->fx32, p->fy32, nullptr, 0, p->U32, p->goct32, p->chi32, tw,
+                                p->stream);
+  }
+  hipError_t apply(const float2* xc, float2* yc) {
+    hipError_t e = full(xc);
+    return e ? e : gather<float>(u, p->fy32, yc, nullptr, p->stream);
+  }
+  hipError_t residual(const float2* xc, const float2* bc, float2* rc) {
+    hipError_t e = full(xc);
+    return e ? e : gather<float>(u, p->fy32, rc, bc, p->stream);
+  }
+};
+
 struct Stats {
   int iters = 0, restarts = 0, matvecs = 0, inner = 0, fallback = 0;
   double est = 0, rel_true = INFINITY;
@@ -243,11 +296,10 @@ hipError_t read_scalar(const double2* d, double* out, double* pinned, hipStream_
 // GMRES(m) (flexible when a preconditioner is given) on basis type T.
 // check_true: confirm convergence with the true residual and restart until then.
 template <typename T, typename OP, typename PC>
-int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, const cx<T>* b, cx<T>* x, double tol, int m,
+int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, long n, const cx<T>* b, cx<T>* x, double tol, int m,
                int maxit, bool use_x0, bool check_true, Stats& st) {
   using K = KrylovOps<T>;
   hipStream_t s = p->stream;
-  const long n = 3 * p->g.N;
   HIPTRY(p, W.ensure(n, m, M != nullptr));
   double bsq = 0;
   HIPTRY(p, K::nrm2sq(b, n, W.partial, W.sumsq, s));
@@ -455,6 +507,8 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
   if (f32) PLANTRY(hipMalloc(&p->U32, sizeof(float2) * 3 * (size_t)g.n1 * g.n2 * g.M3));
   PLANTRY(hipMalloc(&p->rvec, sizeof(double2) * 3 * g.N));
   PLANTRY(hipMalloc(&p->flag, sizeof(int)));
+  PLANTRY(hipMalloc(&p->colflag, sizeof(int) * (size_t)g.n1 * g.n2));
+  PLANTRY(hipMalloc(&p->scol, sizeof(int) * (size_t)g.n1 * g.n2));
   PLANTRY(hipMalloc(&table_dev, sizeof(double2) * 6 * g.N));
   PLANTRY(hipMalloc(&full, sizeof(double2) * P));
   PLANTRY(hipMemcpyAsync(table_dev, table->data(), sizeof(double2) * 6 * g.N, hipMemcpyHostToDevice, p->stream));
@@ -487,6 +541,16 @@ int vie_set_contrast(vie_plan_t p, const vie_c128* eps) {
     p->has_contrast = false;
     return fail(p, VIE_EINVAL, "eps has a non-finite or zero value");
   }
+  // support columns, in increasing i1 n2 + i2 order
+  const long n12 = (long)p->g.n1 * p->g.n2;
+  std::vector<int> flags(n12), cols;
+  HIPTRY(p, column_flags(p->chi64, n12, p->g.n3, p->colflag, p->stream));
+  HIPTRY(p, hipMemcpyAsync(flags.data(), p->colflag, sizeof(int) * n12, hipMemcpyDeviceToHost, p->stream));
+  HIPTRY(p, hipStreamSynchronize(p->stream));
+  for (long c = 0; c < n12; ++c)
+    if (flags[c]) cols.push_back((int)c);
+  p->ns = (int)cols.size();
+  if (p->ns) HIPTRY(p, hipMemcpy(p->scol, cols.data(), sizeof(int) * cols.size(), hipMemcpyHostToDevice));
   p->has_contrast = true;
   return VIE_OK;
 }
@@ -551,71 +615,152 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
   if (o.inner_restart <= 0) o.inner_restart = 20;
   if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
   if (o.restart > 4096 || o.inner_restart > 4096) return fail(p, VIE_EINVAL, "restart too large");
-  const long n = 3 * p->g.N;
+  if (o.precision < 0 || o.precision > 3) return fail(p, VIE_EINVAL, "unknown precision tier");
+  if (o.precision == 1 && !p->goct32) return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
+  if (o.precision == 2 && !p->net) return fail(p, VIE_ESTATE, "no preconditioner attached (vie_set_preconditioner)");
+  if (o.precision == 3 && !p->circ) return fail(p, VIE_ESTATE, "no circulant preconditioner (vie_circulant_build)");
+  if (o.precision == 3 && circ_info(p->circ).s != p->ns)
+    return fail(p, VIE_ESTATE, "circulant preconditioner built for another support");
+  hipStream_t s = p->stream;
+  const long nfull = 3 * p->g.N;
+  const double2* bd = reinterpret_cast<const double2*>(b);
+  double2* xd = reinterpret_cast<double2*>(x);
   Stats st;
-  int status;
-  Op64 A{p};
-  if (o.precision == 0) {
-    status = gmres_core<double, Op64, NoPrecond>(p, p->ws64, A, nullptr, reinterpret_cast<const double2*>(b),
-                                                 reinterpret_cast<double2*>(x), tol, o.restart, o.maxit,
-                                                 o.use_x0 != 0, true, st);
-  } else if (o.precision == 1) {
-    if (!p->goct32) return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
-    if (!p->v32a) {
-      HIPTRY(p, hipMalloc(&p->v32a, sizeof(float2) * n));
-      HIPTRY(p, hipMalloc(&p->v32b, sizeof(float2) * n));
+  int status = VIE_OK;
+  auto report = [&](int code) {
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) {
+      info->iters = st.iters;
+      info->inner_iters = st.inner;
+      info->restarts = st.restarts;
+      info->matvecs = st.matvecs;
+      info->status = code;
+      info->rel_res_true = st.rel_true;
+      info->rel_res_est = st.est;
+      info->seconds = secs;
+      info->fallback = st.fallback;
     }
-    Op32 A32{p};
+    if (code == VIE_ENOCONV && p->err.empty()) p->err = "tolerance not reached within maxit";
+    return code;
+  };
+  // Off the support A is the identity, so x = b there; on it the system is
+  // A_SS x_S = b_S - (A b_off)_S with b_off = b off the support.
+  auto x_is_b = [&]() { return hipMemcpyAsync(xd, bd, sizeof(double2) * nfull, hipMemcpyDeviceToDevice, s); };
+  if (p->ns == 0) {
+    HIPTRY(p, x_is_b());
+    HIPTRY(p, hipStreamSynchronize(s));
+    st.rel_true = st.est = 0;
+    return report(VIE_OK);
+  }
+  const Support u{p->scol, p->ns, (long)p->g.n1 * p->g.n2, p->g.n3};
+  const long n = u.size();
+  if (!p->fx) {
+    HIPTRY(p, hipMalloc(&p->fx, sizeof(double2) * nfull));
+    HIPTRY(p, hipMalloc(&p->fy, sizeof(double2) * nfull));
+    HIPTRY(p, hipMalloc(&p->bc, sizeof(double2) * nfull));
+    HIPTRY(p, hipMalloc(&p->xc, sizeof(double2) * nfull));
+    HIPTRY(p, hipMalloc(&p->partial_full, sizeof(double2) * (partial_blocks(nfull) + 1)));
+    HIPTRY(p, hipMalloc(&p->sumsq_full, sizeof(double2) * 2));
+  }
+  if (o.precision == 1 && !p->fx32) {
+    HIPTRY(p, hipMalloc(&p->fx32, sizeof(float2) * nfull));
+    HIPTRY(p, hipMalloc(&p->fy32, sizeof(float2) * nfull));
+    HIPTRY(p, hipMalloc(&p->v32a, sizeof(float2) * nfull));
+    HIPTRY(p, hipMalloc(&p->v32b, sizeof(float2) * nfull));
+  }
+  using K = KrylovOps<double>;
+  HIPTRY(p, K::zero(p->fx, nfull, s));
+  if (p->fx32) HIPTRY(p, KrylovOps<float>::zero(p->fx32, nfull, s));
+  double tmp_h[1];
+  auto read_norm2 = [&](const double2* v, long len, double* out) -> hipError_t {
+    hipError_t e = K::nrm2sq(v, len, p->partial_full, p->sumsq_full, s);
+    if (e) return e;
+    e = hipMemcpyAsync(tmp_h, p->sumsq_full, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e) return e;
+    e = hipStreamSynchronize(s);
+    *out = tmp_h[0];
+    return e;
+  };
+  double bsq_on = 0, bsq_off = 0, bcsq = 0;
+  HIPTRY(p, gather<double>(u, bd, p->bc, nullptr, s));
+  HIPTRY(p, read_norm2(p->bc, n, &bsq_on));
+  HIPTRY(p, hipMemcpyAsync(p->rvec, bd, sizeof(double2) * nfull, hipMemcpyDeviceToDevice, s));
+  HIPTRY(p, zero_support<double>(u, p->rvec, s));
+  HIPTRY(p, read_norm2(p->rvec, nfull, &bsq_off));
+  if (!std::isfinite(bsq_on) || !std::isfinite(bsq_off)) return fail(p, VIE_EINVAL, "right-hand side is not finite");
+  if (bsq_off > 0) {
+    const void* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+    HIPTRY(p, launch_matvec<double>(p->g, p->t64, p->rvec, p->fy, nullptr, 0, p->U64, p->goct64, p->chi64, tw, s));
+    st.matvecs++;
+    HIPTRY(p, gather<double>(u, p->fy, p->bc, p->bc, s));
+    HIPTRY(p, read_norm2(p->bc, n, &bcsq));
+  } else {
+    bcsq = bsq_on;
+  }
+  const double bnorm = std::sqrt(bsq_on + bsq_off);
+  if (bnorm == 0.0 || bcsq == 0.0) {
+    // b = 0, or b off the support only: x = b solves exactly
+    HIPTRY(p, x_is_b());
+    HIPTRY(p, hipStreamSynchronize(s));
+    st.rel_true = st.est = 0;
+    return report(VIE_OK);
+  }
+  const double ratio = std::sqrt(bcsq) / bnorm;   // ||b_c|| / ||b||
+  const double tolc = tol / ratio;
+  if (o.use_x0) HIPTRY(p, gather<double>(u, xd, p->xc, nullptr, s));
+  Op64c A{p, u};
+  if (o.precision == 0) {
+    status = gmres_core<double, Op64c, NoPrecond>(p, p->ws64, A, nullptr, n, p->bc, p->xc, tolc, o.restart, o.maxit,
+                                                  o.use_x0 != 0, true, st);
+  } else if (o.precision == 1) {
+    Op32c A32{p, u};
     // right preconditioner: z = inner FP32 GMRES solve of A z = v
     auto inner = [&](const void* v, void* z, Stats& outer) -> hipError_t {
-      hipError_t e = convert<double, float>(reinterpret_cast<const double2*>(v), p->v32a, n, p->stream);
+      hipError_t e = convert<double, float>(reinterpret_cast<const double2*>(v), p->v32a, n, s);
       if (e) return e;
       Stats si;
-      int rc = gmres_core<float, Op32, NoPrecond>(p, p->ws32, A32, nullptr, p->v32a, p->v32b, o.inner_tol,
-                                                   o.inner_restart, o.inner_restart, false, false, si);
+      int rc = gmres_core<float, Op32c, NoPrecond>(p, p->ws32, A32, nullptr, n, p->v32a, p->v32b, o.inner_tol,
+                                                    o.inner_restart, o.inner_restart, false, false, si);
       outer.inner += si.iters;
       if (rc != VIE_OK && rc != VIE_ENOCONV) return hipErrorUnknown;
-      return convert<float, double>(p->v32b, reinterpret_cast<double2*>(z), n, p->stream);
+      return convert<float, double>(p->v32b, reinterpret_cast<double2*>(z), n, s);
     };
     struct Pc {
       decltype(inner)& f;
-      hipError_t operator()(const void* v, void* z, Stats& s) { return f(v, z, s); }
+      hipError_t operator()(const void* v, void* z, Stats& st_) { return f(v, z, st_); }
     } pc{inner};
-    status = gmres_core<double, Op64, Pc>(p, p->ws64, A, &pc, reinterpret_cast<const double2*>(b),
-                                          reinterpret_cast<double2*>(x), tol, o.restart, o.maxit, o.use_x0 != 0,
-                                          true, st);
+    status = gmres_core<double, Op64c, Pc>(p, p->ws64, A, &pc, n, p->bc, p->xc, tolc, o.restart, o.maxit,
+                                           o.use_x0 != 0, true, st);
   } else if (o.precision == 2) {
-    // learned tier: x0 = net(b), FGMRES with z = net(v); a cycle that reduces the
-    // true residual by less than half switches to plain GMRES for the rest
-    if (!p->net) return fail(p, VIE_ESTATE, "no preconditioner attached (vie_set_preconditioner)");
-    net_set_stream(p->net, p->stream);
-    double2* xd = reinterpret_cast<double2*>(x);
-    const double2* bd = reinterpret_cast<const double2*>(b);
+    // learned tier: x0 = net(b), FGMRES with z = net(v) (full-grid network around
+    // the compressed vectors); a cycle that reduces the true residual by less
+    // than half switches to plain GMRES for the rest
+    net_set_stream(p->net, s);
     int napply = 0;
     struct Pc {
       vie_plan_s* p;
+      Support u;
       int* count;
       hipError_t operator()(const void* v, void* z, Stats&) {
         ++*count;
-        return net_apply(p->net, reinterpret_cast<const double2*>(v), p->chi64, reinterpret_cast<double2*>(z));
+        hipError_t e = scatter<double>(u, reinterpret_cast<const double2*>(v), p->fx, p->stream);
+        if (e) return e;
+        if ((e = net_apply(p->net, p->fx, p->chi64, p->fy))) return e;
+        return gather<double>(u, p->fy, reinterpret_cast<double2*>(z), nullptr, p->stream);
       }
-    } pc{p, &napply};
-    bool have_x0 = o.use_x0 != 0;
-    if (!have_x0) {
-      HIPTRY(p, net_apply(p->net, bd, p->chi64, xd));
-      ++napply;
-      have_x0 = true;
-    }
+    } pc{p, u, &napply};
+    if (!o.use_x0) HIPTRY(p, pc(p->bc, p->xc, st));
     double prev = INFINITY;
     status = VIE_ENOCONV;
     bool fell_back = false;
     while (st.iters < o.maxit) {
       const int budget = fell_back ? o.maxit : std::min(o.maxit, st.iters + o.restart);
       if (fell_back)
-        status = gmres_core<double, Op64, NoPrecond>(p, p->ws64, A, nullptr, bd, xd, tol, o.restart, budget, true,
-                                                     true, st);
+        status = gmres_core<double, Op64c, NoPrecond>(p, p->ws64, A, nullptr, n, p->bc, p->xc, tolc, o.restart,
+                                                      budget, true, true, st);
       else
-        status = gmres_core<double, Op64, Pc>(p, p->ws64, A, &pc, bd, xd, tol, o.restart, budget, true, true, st);
+        status = gmres_core<double, Op64c, Pc>(p, p->ws64, A, &pc, n, p->bc, p->xc, tolc, o.restart, budget, true,
+                                               true, st);
       if (status != VIE_OK && status != VIE_ENOCONV) break;
       if (status == VIE_OK || fell_back) break;
       if (!(st.rel_true < 0.5 * prev)) fell_back = true;
@@ -623,36 +768,27 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
     }
     st.inner = napply;
     st.fallback = fell_back ? 1 : 0;
-  } else if (o.precision == 3) {
+  } else {
     // FP64 FGMRES right-preconditioned by the block circulant: z = W^{-1} v
-    if (!p->circ) return fail(p, VIE_ESTATE, "no circulant preconditioner (vie_circulant_build)");
     struct Pc {
       vie_plan_s* p;
-      hipError_t operator()(const void* v, void* z, Stats& s) {
-        ++s.inner;
-        return circ_apply(p->circ, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(z), p->stream);
+      hipError_t operator()(const void* v, void* z, Stats& s_) {
+        ++s_.inner;
+        return circ_apply_rows(p->circ, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(z),
+                               p->stream);
       }
     } pc{p};
-    status = gmres_core<double, Op64, Pc>(p, p->ws64, A, &pc, reinterpret_cast<const double2*>(b),
-                                          reinterpret_cast<double2*>(x), tol, o.restart, o.maxit, o.use_x0 != 0,
-                                          true, st);
-  } else {
-    return fail(p, VIE_EINVAL, "unknown precision tier");
+    status = gmres_core<double, Op64c, Pc>(p, p->ws64, A, &pc, n, p->bc, p->xc, tolc, o.restart, o.maxit,
+                                           o.use_x0 != 0, true, st);
   }
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (info) {
-    info->iters = st.iters;
-    info->inner_iters = st.inner;
-    info->restarts = st.restarts;
-    info->matvecs = st.matvecs;
-    info->status = status;
-    info->rel_res_true = st.rel_true;
-    info->rel_res_est = st.est;
-    info->seconds = secs;
-    info->fallback = st.fallback;
+  if (status == VIE_OK || status == VIE_ENOCONV) {
+    HIPTRY(p, x_is_b());
+    HIPTRY(p, scatter<double>(u, p->xc, xd, s));
+    HIPTRY(p, hipStreamSynchronize(s));
   }
-  if (status == VIE_ENOCONV && p->err.empty()) p->err = "tolerance not reached within maxit";
-  return status;
+  st.rel_true *= ratio;
+  st.est *= ratio;
+  return report(status);
 }
 
 int vie_profile_matvec(vie_plan_t p, int precision, const void* x, void* y, int reps, double pass_ms[3],
@@ -749,7 +885,9 @@ void vie_destroy(vie_plan_t p) {
   p->ws64.release();
   p->ws32.release();
   for (void* q : {(void*)p->goct64, (void*)p->goct32, (void*)p->chi64, (void*)p->chi32, (void*)p->U64,
-                  (void*)p->U32, (void*)p->rvec, (void*)p->v32a, (void*)p->v32b, (void*)p->flag})
+                  (void*)p->U32, (void*)p->rvec, (void*)p->v32a, (void*)p->v32b, (void*)p->flag, (void*)p->colflag,
+                  (void*)p->scol, (void*)p->fx, (void*)p->fy, (void*)p->fx32, (void*)p->fy32, (void*)p->bc,
+                  (void*)p->xc, (void*)p->partial_full, (void*)p->sumsq_full})
     if (q) (void)hipFree(q);
   for (int d = 0; d < 3; ++d) {
     if (p->tw64[d]) (void)hipFree(p->tw64[d]);

@@ -100,6 +100,9 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
                hipStream_t s, std::string& err, CircInfo* info);
 // z = W^{-1} r on FP64 device vectors of 3N values (no overlap).
 hipError_t circ_apply(Circ* c, const double2* r, double2* z, hipStream_t s);
+// The same on support-compressed FP64 vectors (3 s n3 values, rows (a, p) of n3 slices,
+// columns in increasing i1 n2 + i2 order, as the solver stores them).
+hipError_t circ_apply_rows(Circ* c, const double2* r, double2* z, hipStream_t s);
 void circ_destroy(Circ* c);
 const CircInfo& circ_info(const Circ* c);
 
