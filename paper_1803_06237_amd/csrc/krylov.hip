@@ -21,9 +21,9 @@
 namespace vie {
 
 constexpr int kThreads = 256;
-constexpr int kEPT = 8;                     // elements per thread held in registers
-constexpr int kChunk = kThreads * kEPT;     // elements per block
-constexpr int kGroup = 4;                   // basis vectors reduced together
+constexpr int kEPT = 2;                     // elements per thread held in registers (reductions)
+constexpr int kChunk = kThreads * kEPT;     // elements per block (reductions)
+constexpr int kGroup = 4;                   // basis vectors per block of the multi-dot
 
 __device__ __forceinline__ double2 to_d(double2 v) { return v; }
 __device__ __forceinline__ double2 to_d(float2 v) { return double2{(double)v.x, (double)v.y}; }
@@ -56,7 +56,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
   __syncthreads();
 }
 
-// partial[i * nblk + blk] = sum over the block's chunk of conj(V_i) w   (i < nv)
+// partial[i * nblk + blk] = sum over the block's chunk of conj(V_i) w, for the
+// kGroup vectors i of blockIdx.y (nblk = gridDim.x element chunks)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_mdot(const cx<T>* __restrict__ V, long ldv, int nv,
                                                     const cx<T>* __restrict__ w, long n,
@@ -69,7 +70,8 @@ __global__ __launch_bounds__(kThreads) void k_mdot(const cx<T>* __restrict__ V, 
     const long e = e0 + (long)k * kThreads;
     wv[k] = e < n ? to_d(w[e]) : double2{0.0, 0.0};
   }
-  for (int i0 = 0; i0 < nv; i0 += kGroup) {
+  {
+    const int i0 = blockIdx.y * kGroup;
     double acc[2 * kGroup];
 #pragma unroll
     for (int q = 0; q < 2 * kGroup; ++q) acc[q] = 0.0;
@@ -113,7 +115,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double2* __restrict__
   }
 }
 
-// w += sign * sum_i coef[i] V_i
+// w += sign * sum_i coef[i] V_i, one element per thread (loads of the nv vectors
+// are independent, so they overlap)
 template <typename T, typename TW>
 __global__ __launch_bounds__(kThreads) void k_maxpy(const cx<T>* __restrict__ V, long ldv, int nv,
                                                      const double2* __restrict__ coef, double sign,
@@ -121,31 +124,18 @@ __global__ __launch_bounds__(kThreads) void k_maxpy(const cx<T>* __restrict__ V,
   __shared__ double2 c[512];
   for (int i = threadIdx.x; i < nv && i < 512; i += kThreads) c[i] = double2{sign * coef[i].x, sign * coef[i].y};
   __syncthreads();
-  const long e0 = (long)blockIdx.x * kChunk + threadIdx.x;
-  double2 acc[kEPT];
-#pragma unroll
-  for (int k = 0; k < kEPT; ++k) {
-    const long e = e0 + (long)k * kThreads;
-    acc[k] = e < n ? to_d(w[e]) : double2{0.0, 0.0};
-  }
+  const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= n) return;
+  double2 acc = to_d(w[e]);
+  const cx<T>* Ve = V + e;
+#pragma unroll 4
   for (int i = 0; i < nv; ++i) {
     const double2 ci = c[i];
-    const cx<T>* Vi = V + (long)i * ldv;
-#pragma unroll
-    for (int k = 0; k < kEPT; ++k) {
-      const long e = e0 + (long)k * kThreads;
-      if (e < n) {
-        const double2 a = to_d(Vi[e]);
-        acc[k].x += ci.x * a.x - ci.y * a.y;
-        acc[k].y += ci.x * a.y + ci.y * a.x;
-      }
-    }
+    const double2 a = to_d(Ve[(long)i * ldv]);
+    acc.x += ci.x * a.x - ci.y * a.y;
+    acc.y += ci.x * a.y + ci.y * a.x;
   }
-#pragma unroll
-  for (int k = 0; k < kEPT; ++k) {
-    const long e = e0 + (long)k * kThreads;
-    if (e < n) w[e] = from_d<cx<TW>>(acc[k]);
-  }
+  w[e] = from_d<cx<TW>>(acc);
 }
 
 // partial[blk] = sum |w|^2 over the block's chunk
@@ -326,7 +316,8 @@ template <typename T>
 hipError_t KrylovOps<T>::mdot(const cx<T>* V, long ldv, int nv, const cx<T>* w, long n, double2* partial,
                               double2* out, int accumulate, hipStream_t s) {
   const int nb = nblocks(n);
-  hipLaunchKernelGGL((k_mdot<T>), dim3(nb), dim3(kThreads), 0, s, V, ldv, nv, w, n, partial);
+  hipLaunchKernelGGL((k_mdot<T>), dim3(nb, (nv + kGroup - 1) / kGroup), dim3(kThreads), 0, s, V, ldv, nv, w, n,
+                     partial);
   hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kThreads), 0, s, partial, nb, out, accumulate);
   return hipGetLastError();
 }
@@ -337,7 +328,8 @@ hipError_t KrylovOps<T>::maxpy(const cx<T>* V, long ldv, int nv, const double2* 
                                long n, hipStream_t s) {
   for (int i0 = 0; i0 < nv; i0 += 512) {
     const int cnt = nv - i0 < 512 ? nv - i0 : 512;
-    hipLaunchKernelGGL((k_maxpy<T, TW>), dim3(nblocks(n)), dim3(kThreads), 0, s, V + (long)i0 * ldv, ldv, cnt,
+    hipLaunchKernelGGL((k_maxpy<T, TW>), dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       V + (long)i0 * ldv, ldv, cnt,
                        coef + i0, sign, w, n);
   }
   return hipGetLastError();
