@@ -112,3 +112,39 @@ def run_family(precision: int = 1, tol: float = 1e-8, restart: int = 50, inner_r
             "outer_iters": [i["iters"] for i in infos], "inner_iters": [i["inner_iters"] for i in infos],
             "reflection": {str(d): v for d, v in curve.items()}, "slopes": {str(d): v for d, v in slopes.items()},
             "lengths": list(LENGTHS)}
+
+
+def iterations_vs_length(n3s: Sequence[int] = (128, 256, 512, 1024), d: int = 2, tol: float = 1e-8,
+                         restart: int = 50) -> dict:
+    """GMRES iterations to tol with and without the block-circulant preconditioner for
+    straight guides of growing length (Section V-D: unpreconditioned counts grow with
+    the length, preconditioned counts stay flat).  32 x 32 x n3 guides, h = 25 nm,
+    80-voxel absorbers of degree d, x-dipole source."""
+    import torch
+    out = {"n3": list(n3s), "length_um": [], "plain_iters": [], "circulant_iters": [], "plain_seconds": [],
+           "circulant_solve_seconds": [], "circulant_setup_seconds": []}
+    for n3 in n3s:
+        wg = inputs.strip_long(d=d, n3=n3)
+        plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+        plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+        b = plan.rhs(torch.from_numpy(inputs.transverse_dipole_field(wg)).cuda())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, i0 = plan.solve(b, tol=tol, restart=restart, precision=0)
+        t_plain = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        plan.build_circulant()
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, i3 = plan.solve(b, tol=tol, restart=restart, precision=3)
+        t_circ = time.perf_counter() - t0
+        if i0["status"] != 0 or i3["status"] != 0:
+            raise RuntimeError(f"solve did not converge at n3={n3}: {i0} {i3}")
+        out["length_um"].append(round(n3 * wg.h, 3))
+        out["plain_iters"].append(i0["iters"])
+        out["circulant_iters"].append(i3["iters"])
+        out["plain_seconds"].append(round(t_plain, 4))
+        out["circulant_solve_seconds"].append(round(t_circ, 4))
+        out["circulant_setup_seconds"].append(round(t_setup, 4))
+        plan.close()
+    return out
