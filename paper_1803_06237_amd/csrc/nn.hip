@@ -605,7 +605,8 @@ int vie_net_create(vie_net_t* out, const int grid[3], unsigned seed, void* hip_s
   N->partial_cap = 8L << 20;   // floats
   if (nalloc(N, (void**)&N->partial, sizeof(float) * N->partial_cap)) return bail(VIE_ENOMEM);
   if (nalloc(N, (void**)&N->sumsq, sizeof(double2) * 2)) return bail(VIE_ENOMEM);
-  if (nalloc(N, (void**)&N->red, sizeof(double2) * (3 * V[0] / 2048 + 16))) return bail(VIE_ENOMEM);
+  // partials of KrylovOps::nrm2sq over the 3V residual values
+  if (nalloc(N, (void**)&N->red, sizeof(double2) * (partial_blocks(3 * V[0]) + 1))) return bail(VIE_ENOMEM);
   if (nalloc(N, (void**)&N->lpart, sizeof(double) * 4096)) return bail(VIE_ENOMEM);
   if (hipHostMalloc(&N->lpart_h, sizeof(double) * 4096, hipHostMallocDefault)) return bail(VIE_ENOMEM);
   if (refresh_weights(N, 0, 0.f) || hipStreamSynchronize(N->stream)) return bail(VIE_EDEVICE);
