@@ -43,7 +43,8 @@ def pass_bytes(n, M, cs):
 
 
 KERNEL_SOURCES = {
-    "k_xy64<double>": ["xy64.hip", "fft_device.hpp"],
+    "k_xy64<double, 0>": ["xy64.hip", "fft_device.hpp"],
+    "k_xy64<double, 1>": ["xy64.hip", "fft_device.hpp"],
     "k_zfwd4<double, 32, 32>": ["zpass.hip", "dft_reg.hpp"],
     "k_zinv4<double, 32, 32, 0>": ["zpass.hip", "dft_reg.hpp"],
 }
@@ -185,8 +186,9 @@ def main():
 
     b64 = pass_bytes(n, M, 16)
     z4 = M[2] in (512, 1024)
+    tune64 = plan.tune(0)
     names = ["k_zfwd4<double, 32, 32>" if z4 else "k_zfwd<double>",
-             "k_xy64<double>" if M[0] == 64 and M[1] == 64 else "k_xyg<double>",
+             f"k_xy64<double, {tune64['xy_variant']}>" if M[0] == 64 and M[1] == 64 else "k_xyg<double>",
              "k_zinv4<double, 32, 32, 0>" if z4 else "k_zinv<double, 0>"]
     dom = int(np.argmax(pass_ms))
     achieved = b64[dom] / (pass_ms[dom] * 1e-3) / 1e9
@@ -219,6 +221,7 @@ def main():
                           "GBs": round(matvec_bytes / (tot_ms * 1e-3) / 1e9, 1),
                           "frac": round(matvec_bytes / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
            "passes": passes,
+           "launch_shapes": {"fp64": tune64, "fp32": plan.tune(1)},
            "fp32_matvec": {"matvecs_per_s": round(1e3 / t32, 1), "avg_us": round(t32 * 1e3, 2),
                            "GBs": round(sum(b32) / (t32 * 1e-3) / 1e9, 1),
                            "passes_us": [round(v * 1e3, 2) for v in p32]},

@@ -25,11 +25,11 @@
 namespace vie {
 
 template <typename T>
-hipError_t launch_xy64(const Geom& g, void* U, const void* goct, const void* tw1, hipStream_t s);
+hipError_t launch_xy64(const Geom& g, int V, void* U, const void* goct, const void* tw1, hipStream_t s);
 template <typename T>
 hipError_t allow_lds_xy64();
 template <typename T>
-hipError_t launch_z4(int which, const Geom& g, const void* x, void* y, const void* b, int mode, void* U,
+hipError_t launch_z4(int which, const Geom& g, int P, const void* x, void* y, const void* b, int mode, void* U,
                      const void* chi, const void* twz, hipStream_t st);
 template <typename T>
 hipError_t allow_lds_z4();
@@ -184,14 +184,14 @@ template <typename T>
 hipError_t launch_pass(int which, const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
                        void* U, const void* goct, const void* chi, const void* const tw[3], hipStream_t s) {
   using C = cx<T>;
-  if (which != 1 && t.z4) return launch_z4<T>(which, g, x, y, b, mode, U, chi, tw[2], s);
+  if (which != 1 && t.z4) return launch_z4<T>(which, g, t.zp, x, y, b, mode, U, chi, tw[2], s);
   const int nb1 = (g.n1 + t.tp - 1) / t.tp;
   const dim3 gz(3 * g.n2 * nb1);
   const size_t zl = z_lds_bytes<T>(g, t.tp);
   if (which == 0) {
     hipLaunchKernelGGL((k_zfwd<T>), gz, dim3(t.zthreads), zl, s, (const C*)x, (C*)U, g, t.tp, (const C*)tw[2]);
   } else if (which == 1 && g.M1 == 64 && g.M2 == 64) {
-    return launch_xy64<T>(g, U, goct, tw[0], s);
+    return launch_xy64<T>(g, t.xyv, U, goct, tw[0], s);
   } else if (which == 1) {
     hipLaunchKernelGGL((k_xyg<T>), dim3(g.M3), dim3(t.xythreads), xy_lds_bytes<T>(g, t.cc), s, (C*)U,
                        (const C*)goct, g, t.cc, (const C*)tw[0], (const C*)tw[1]);

@@ -197,7 +197,98 @@ bool pick_tune(const Geom& g, size_t budget, size_t zbudget, Tune* t) {
   t->xythreads = xt;
   const size_t z4 = z4_lds_bytes<T>(g.M3);
   t->z4 = (z4 > 0 && z4 <= budget) ? 1 : 0;
+  t->xyv = sizeof(T) == 8 ? 1 : 0;
+  t->zp = 0;
   return true;
+}
+
+// ---- plan-time tuning of launch shapes ----------------------------------------
+// Candidates: the four-step z passes' pencils per workgroup (with the forward and
+// the inverse pass timed together, they share the choice) and the 64 x 64 xy
+// pass variant.  Each candidate runs two untimed and five timed launches between
+// HIP events; the fastest wins.  Results are kept per (device, grid, precision)
+// for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, Tune> g_tune_cache;
+
+template <typename T>
+hipError_t time_passes(const Geom& g, const Tune& t, int w0, int w1, const void* x, void* y, void* U,
+                       const void* goct, const void* chi, const void* const tw[3], hipStream_t s, float* ms) {
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0))) return e;
+  if ((e = hipEventCreate(&e1))) return e;
+  for (int r = 0; r < 7 && !e; ++r) {
+    if (r == 2) e = hipEventRecord(e0, s);
+    for (int w = w0; w <= w1 && !e; ++w) e = launch_pass<T>(w, g, t, x, y, nullptr, 0, U, goct, chi, tw, s);
+  }
+  if (!e) e = hipEventRecord(e1, s);
+  if (!e) e = hipEventSynchronize(e1);
+  if (!e) e = hipEventElapsedTime(ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return e;
+}
+
+template <typename T>
+hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goct, const void* chi,
+                    const void* const tw[3], hipStream_t s) {
+  const auto key = std::make_tuple(device, g.n1, g.n2, g.n3, (int)sizeof(T));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *t = it->second;
+      return hipSuccess;
+    }
+  }
+  const size_t bytes = sizeof(cx<T>) * 3 * (size_t)g.N;
+  void* x = nullptr;
+  void* y = nullptr;
+  hipError_t e = hipMalloc(&x, bytes);
+  if (!e) e = hipMalloc(&y, bytes);
+  if (!e) e = hipMemsetAsync(x, 0, bytes, s);
+  if (!e && t->z4) {
+    int opts[4];
+    const int n = z4_pencil_options<T>(g.M3, opts, 4);
+    float best = INFINITY;
+    int bestp = 0;
+    for (int i = 0; i < n && !e; ++i) {
+      Tune c = *t;
+      c.zp = opts[i];
+      float ms = 0;
+      e = time_passes<T>(g, c, 0, 0, x, y, U, goct, chi, tw, s, &ms);
+      float ms2 = 0;
+      if (!e) e = time_passes<T>(g, c, 2, 2, x, y, U, goct, chi, tw, s, &ms2);
+      if (!e && ms + ms2 < best) {
+        best = ms + ms2;
+        bestp = opts[i];
+      }
+    }
+    t->zp = bestp;
+  }
+  if (!e && g.M1 == 64 && g.M2 == 64) {
+    float best = INFINITY;
+    int bestv = t->xyv;
+    for (int v = 0; v < 2 && !e; ++v) {
+      Tune c = *t;
+      c.xyv = v;
+      float ms = 0;
+      e = time_passes<T>(g, c, 1, 1, x, y, U, goct, chi, tw, s, &ms);
+      if (!e && ms < best) {
+        best = ms;
+        bestv = v;
+      }
+    }
+    t->xyv = bestv;
+  }
+  if (x) (void)hipFree(x);
+  if (y) (void)hipFree(y);
+  if (!e) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = *t;
+  }
+  return e;
 }
 
 template <typename T>
@@ -518,6 +609,17 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
   }
   PLANTRY(hipStreamSynchronize(p->stream));
   cleanup_tmp();
+  table_dev = full = nullptr;
+  if (!(flags & VIE_NO_AUTOTUNE)) {
+    // launch-shape tuning on the plan's own buffers; the contrast is zeroed first
+    // (set_contrast overwrites it)
+    const void* tw64[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+    const void* tw32[3] = {p->tw32[0], p->tw32[1], p->tw32[2]};
+    PLANTRY(hipMemsetAsync(p->chi64, 0, sizeof(double2) * g.N, p->stream));
+    PLANTRY(hipMemsetAsync(p->chi32, 0, sizeof(float2) * g.N, p->stream));
+    PLANTRY(autotune<double>(g, p->device, &p->t64, p->U64, p->goct64, p->chi64, tw64, p->stream));
+    if (f32) PLANTRY(autotune<float>(g, p->device, &p->t32, p->U32, p->goct32, p->chi32, tw32, p->stream));
+  }
 #undef PLANTRY
   *out = p;
   return VIE_OK;
@@ -840,6 +942,37 @@ int vie_set_preconditioner(vie_plan_t p, vie_net_t net) {
       return fail(p, VIE_EINVAL, "network grid differs from the plan's grid");
   }
   p->net = net;
+  return VIE_OK;
+}
+
+int vie_get_tune(vie_plan_t p, int precision, int* xy_variant, int* z_pencils) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (precision != 0 && precision != 1) return fail(p, VIE_EINVAL, "precision must be 0 or 1");
+  const Tune& t = precision == 0 ? p->t64 : p->t32;
+  int opts[4];
+  const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 4)
+                               : z4_pencil_options<float>(p->g.M3, opts, 4);
+  if (xy_variant) *xy_variant = (p->g.M1 == 64 && p->g.M2 == 64) ? t.xyv : -1;
+  if (z_pencils) *z_pencils = t.z4 && n ? (t.zp ? t.zp : opts[0]) : 0;
+  return VIE_OK;
+}
+
+int vie_set_tune(vie_plan_t p, int precision, int xy_variant, int z_pencils) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (precision != 0 && precision != 1) return fail(p, VIE_EINVAL, "precision must be 0 or 1");
+  if (xy_variant != 0 && xy_variant != 1) return fail(p, VIE_EINVAL, "xy_variant must be 0 or 1");
+  int opts[4];
+  const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 4)
+                               : z4_pencil_options<float>(p->g.M3, opts, 4);
+  Tune& t = precision == 0 ? p->t64 : p->t32;
+  if (z_pencils != 0) {
+    bool ok = false;
+    for (int i = 0; i < n; ++i) ok = ok || opts[i] == z_pencils;
+    if (!ok || !t.z4) return fail(p, VIE_EINVAL, "z_pencils is not a candidate for this grid");
+  }
+  HIPTRY(p, hipStreamSynchronize(p->stream));
+  t.xyv = xy_variant;
+  t.zp = z_pencils;
   return VIE_OK;
 }
 

@@ -26,10 +26,17 @@ struct Tune {
   int cc;        // column chunk in the xy pass
   int xythreads; // threads per workgroup in the xy pass
   int z4;        // 1: z passes use the register four-step kernels
+  int xyv;       // 64 x 64 xy pass variant: 0 full plane, 1 x-frequency halves
+  int zp;        // pencils per workgroup in the four-step z passes (0: the default for M3)
 };
 
+// Candidate pencil counts of the four-step z passes for M3 (empty when none exist);
+// the first is the default.
 template <typename T>
-size_t z4_lds_bytes(int M3);   // 0 when no four-step instance exists for M3
+int z4_pencil_options(int M3, int* out, int cap);
+
+template <typename T>
+size_t z4_lds_bytes(int M3, int P = 0);   // 0 when no four-step instance exists for M3
 
 // ---- matvec passes (kernels.hip) ----------------------------------------
 // mode for the inverse z pass: 0 -> y = x - chi u ; 1 -> y = b - (x - chi u)

@@ -3,24 +3,35 @@
 // symmetric product with the Green spectrum, inverse 2-D FFT and crop
 // (Section III-A: N is block Toeplitz, its product a circular convolution).
 //
-// Each 64-point transform is a four-step radix-8 x 8 DFT done in registers:
-// thread "a" (a = lane & 7) of an 8-thread group holds x[a + 8 b] (b = 0..7),
-// takes an 8-point DFT over b, twiddles by W64^(a k), and one LDS exchange
-// hands thread k the values k of all eight threads for the second 8-point DFT.
+// Each 64-point transform is a four-step radix-8 x 8 DFT done in registers by
+// a group of 8 lanes: lane a holds x[a + 8 b] (b = 0..7), takes an 8-point DFT
+// over b, twiddles by W64^(a k), and an 8 x 8 transpose across the group's
+// lanes through LDS hands lane k the values k of all eight lanes for the second
+// 8-point DFT; lane a then holds X[a + 8 m].
 // Inputs are only 32 long (the upper half is the zero padding) and only the
 // first 32 outputs of each inverse transform are kept (the crop).
 //
-// Stage A: rows (x) forward, thread (y, a), all 3 components.
-// Stage B: columns (y) forward, Green product, columns inverse; thread (kx, a),
-//          processed in two halves of kx so that the exchange of one half
-//          (3 components x 32 columns x 64) fits where the rows were kept.
-// Stage C: rows inverse, crop, store.
+// Two variants, picked per grid and precision by timing at plan time:
+//  V = 0 (full plane): the rows of all 64 x-frequencies of the three components
+//   stay in LDS (3 x 32 x 64 values, 96 KiB FP64) and the same region serves the
+//   8 x 8 exchanges between workgroup barriers: rows forward; columns forward,
+//   Green product and inverse in two halves of kx; rows inverse, crop, store.
+//  V = 1 (x-frequency halves): the 64 x-frequencies are processed in two halves
+//   so that the row-to-column hand-off needs 3 x 32 x 32 values of LDS, and each
+//   group of 8 lanes exchanges through its own 64-value LDS area without
+//   workgroup barriers (80 KiB FP64 in all, two workgroups per CU):
+//   A_h: rows (x) forward for row y = group, all 3 components; the 32
+//        frequencies of half h go to LDS;
+//   B_h: columns (y) forward, Green product, columns inverse for column
+//        kx = 32 h + group, in place in LDS;
+//   C_h: rows inverse from the 32 frequencies of half h (the rest taken as
+//        zero); half 0 parks its partial row in the plane's own storage (after
+//        reading the row input again for A_1) and half 1 adds to it.
 // Planes kz and M3 - kz use the same slab of the folded Green spectrum: the
 // single-system kernel puts them on workgroups b and b + 8 (same XCD), the
 // batched kernel transforms the pair in one workgroup.
-// LDS: one region of 3 x 32 x 64 complex values (96 KiB FP64, 48 KiB FP32),
-// element (c, y, kx) at (c*32 + y)*64 + (kx ^ (y & 7)) so the column accesses
-// of 8 threads with consecutive y hit distinct banks.
+// LDS element (c, y, j) sits at (c*32 + y)*32 + (j ^ (y & 7)) so that the column
+// reads of the 8 lanes of a group (consecutive y) hit distinct banks.
 #include <hip/hip_runtime.h>
 
 #include "fft_device.hpp"
@@ -30,14 +41,16 @@ namespace vie {
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ int rpos(int c, int y, int kx) {
-  return (c * 32 + y) * 64 + (kx ^ (y & 7));
-}
+__device__ __forceinline__ int hpos(int c, int y, int j) { return (c * 32 + y) * 32 + (j ^ (y & 7)); }
 
-// 8 x 8 exchange block for group g (64 complex values), element (i, j) stored
-// rotated so 8 threads reading row i with j = 0..7 touch distinct banks.
-__device__ __forceinline__ int xpos(int g, int i, int j) { return g * 64 + i * 8 + ((i + j) & 7); }
+constexpr int kRowVals = 3 * 32 * 32;               // row/column hand-off of one half
+constexpr int kXyLdsVals = kRowVals + 32 * 64;      // + 32 groups x 64 exchange values
+constexpr int kFullLdsVals = 3 * 32 * 64;           // full-plane variant: rows of all 64 frequencies
+
+// full-plane variant: element (c, y, kx) of the row buffer, and the 8 x 8 exchange
+// block of group gr (64 values) with element (i, j) rotated as in xpos
+__device__ __forceinline__ int rpos(int c, int y, int kx) { return (c * 32 + y) * 64 + (kx ^ (y & 7)); }
+__device__ __forceinline__ int gpos(int gr, int i, int j) { return gr * 64 + i * 8 + ((i + j) & 7); }
 
 template <typename T, bool INV>
 __device__ __forceinline__ void twiddle8(cx<T>* v, const cx<T>* w) {
@@ -45,10 +58,36 @@ __device__ __forceinline__ void twiddle8(cx<T>* v, const cx<T>* w) {
   for (int k = 1; k < 8; ++k) v[k] = INV ? cmulc(v[k], w[k]) : cmul(v[k], w[k]);
 }
 
+// Exchange area of one group of 8 lanes (64 values): element (i, j) stored rotated
+// so that 8 lanes reading row i with j = 0..7 touch distinct banks.
+__device__ __forceinline__ int xpos(int i, int j) { return i * 8 + ((i + j) & 7); }
+
+// 8 x 8 transpose across the 8 lanes of a group through the group's own 64-value
+// LDS area X: lane a's v[k] becomes lane k's v[a].  The area belongs to one wave,
+// whose LDS accesses complete in program order, so no workgroup barrier is needed.
+template <typename T>
+__device__ __forceinline__ void transpose8(cx<T>* v, int a, cx<T>* X) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) X[xpos(k, a)] = v[k];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = X[xpos(a, j)];
+  __builtin_amdgcn_wave_barrier();
+}
+
+// 64-point transform of the group: in, lane a holds x[a + 8 b]; out, lane a holds X[a + 8 m]
+template <typename T, bool INV>
+__device__ __forceinline__ void fft64(cx<T>* v, const cx<T>* w, int a, cx<T>* X) {
+  dft8<T, INV>(v);
+  twiddle8<T, INV>(v, w);
+  transpose8<T>(v, a, X);
+  dft8<T, INV>(v);
+}
+
 }  // namespace
 
 template <typename T>
-__device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
+__device__ __forceinline__ void xy64_full(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
                                             const cx<T>* __restrict__ tw64, int kz_first, int nplanes, int kz_second,
                                             cx<T>* R) {
   const int tid = threadIdx.x;
@@ -79,20 +118,20 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
       dft8<T, false>(v[c]);
       twiddle8<T, false>(v[c], w);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) R[xpos(c * 32 + y, k, a)] = v[c][k];
+      for (int k = 0; k < 8; ++k) R[gpos(c * 32 + y, k, a)] = v[c][k];
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[c][j] = R[xpos(c * 32 + y, a, j)];
+      for (int j = 0; j < 8; ++j) v[c][j] = R[gpos(c * 32 + y, a, j)];
       dft8<T, false>(v[c]);    // v[c][m] = X[kx = a + 8 m]
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int m = 0; m < 8; ++m) R[rpos<T>(c, y, a + 8 * m)] = v[c][m];
+      for (int m = 0; m < 8; ++m) R[rpos(c, y, a + 8 * m)] = v[c][m];
     __syncthreads();
   }
 
@@ -105,7 +144,7 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) in[h][c][b] = R[rpos<T>(c, a + 8 * b, kx)];
+      for (int b = 0; b < 4; ++b) in[h][c][b] = R[rpos(c, a + 8 * b, kx)];
   }
   __syncthreads();
   const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
@@ -124,13 +163,13 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
       dft8<T, false>(v[c]);
       twiddle8<T, false>(v[c], w);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) R[xpos(c * 32 + q, k, a)] = v[c][k];
+      for (int k = 0; k < 8; ++k) R[gpos(c * 32 + q, k, a)] = v[c][k];
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[c][j] = R[xpos(c * 32 + q, a, j)];
+      for (int j = 0; j < 8; ++j) v[c][j] = R[gpos(c * 32 + q, a, j)];
       dft8<T, false>(v[c]);    // v[c][m] = Y[ky = a + 8 m]
     }
     // Green product at (kx, ky), spectrum folded to the stored octant
@@ -156,13 +195,13 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
       dft8<T, true>(v[c]);
       twiddle8<T, true>(v[c], w);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) R[xpos(c * 32 + q, k, a)] = v[c][k];
+      for (int k = 0; k < 8; ++k) R[gpos(c * 32 + q, k, a)] = v[c][k];
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[c][j] = R[xpos(c * 32 + q, a, j)];
+      for (int j = 0; j < 8; ++j) v[c][j] = R[gpos(c * 32 + q, a, j)];
       dft8<T, true>(v[c]);     // v[c][b] = column value at y = a + 8 b
 #pragma unroll
       for (int b = 0; b < 4; ++b) out[h][c][b] = v[c][b];
@@ -175,7 +214,7 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) R[rpos<T>(c, a + 8 * b, kx)] = out[h][c][b];
+      for (int b = 0; b < 4; ++b) R[rpos(c, a + 8 * b, kx)] = out[h][c][b];
   }
   __syncthreads();
 
@@ -185,7 +224,7 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) v[c][m] = R[rpos<T>(c, y, a + 8 * m)];
+      for (int m = 0; m < 8; ++m) v[c][m] = R[rpos(c, y, a + 8 * m)];
       dft8<T, true>(v[c]);
       twiddle8<T, true>(v[c], w);
     }
@@ -193,12 +232,12 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) R[xpos(c * 32 + y, k, a)] = v[c][k];
+      for (int k = 0; k < 8; ++k) R[gpos(c * 32 + y, k, a)] = v[c][k];
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[c][j] = R[xpos(c * 32 + y, a, j)];
+      for (int j = 0; j < 8; ++j) v[c][j] = R[gpos(c * 32 + y, a, j)];
       dft8<T, true>(v[c]);     // v[c][b] = row value at x = a + 8 b
       if (y < n2) {
 #pragma unroll
@@ -213,37 +252,170 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
   }
 }
 
+template <typename T>
+__device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
+                                          const cx<T>* __restrict__ tw64, int kz_first, int nplanes, int kz_second,
+                                          cx<T>* R) {
+  const int tid = threadIdx.x;
+  const int a = tid & 7;
+  const int q = tid >> 3;                            // group: row y in A and C, column in B
+  const int n1 = g.n1, n2 = g.n2;
+  cx<T>* X = R + kRowVals + q * 64;                  // this group's exchange area
+  cx<T> w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w[k] = tw64[a * k];
+  const cx<T> zero{(T)0, (T)0};
+  for (int pi = 0; pi < nplanes; ++pi) {
+    const int kz = pi == 0 ? kz_first : kz_second;
+    cx<T>* P = U + (long)kz * 3 * n1 * n2;
+    const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
+    const T s3 = kz <= g.M3 / 2 ? (T)1 : (T)-1;
+    const cx<T>* G3 = goct + (long)k3 * g.H2 * g.H1 * 6;
+    const int y = q;
+    const bool row_ok = y < n2;
+    cx<T> in[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int x = a + 8 * b;
+        in[c][b] = (x < n1 && row_ok) ? P[(c * n2 + y) * n1 + x] : zero;
+      }
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      const bool first = h == 0;
+      // ---- A_h: forward x transform of row y, frequencies of half h to LDS
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cx<T> v[8];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[b] = in[c][b];
+#pragma unroll
+        for (int b = 4; b < 8; ++b) v[b] = zero;
+        fft64<T, false>(v, w, a, X);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const cx<T> lo = v[m], up = v[m + 4];
+          R[hpos(c, y, a + 8 * m)] = cx<T>{first ? lo.x : up.x, first ? lo.y : up.y};
+        }
+      }
+      __syncthreads();
+      // ---- B_h: column kx = 32 h + q: forward y transform, Green product, inverse, crop
+      {
+        const int kx = 32 * h + q;
+        cx<T> v[3][8];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) v[c][b] = R[hpos(c, a + 8 * b, q)];
+#pragma unroll
+          for (int b = 4; b < 8; ++b) v[c][b] = zero;
+          fft64<T, false>(v[c], w, a, X);  // v[c][m] = Y[ky = a + 8 m]
+        }
+        const int k1 = kx <= 32 ? kx : 64 - kx;
+        const T s1 = kx <= 32 ? (T)1 : (T)-1;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          // at most two frequencies' spectrum loads in flight (register pressure)
+          if (m == 2 || m == 4 || m == 6) __builtin_amdgcn_sched_barrier(0);
+          const int ky = a + 8 * m;
+          const int k2 = ky <= 32 ? ky : 64 - ky;
+          const T s2 = ky <= 32 ? (T)1 : (T)-1;
+          const cx<T>* Gp = G3 + ((long)k2 * g.H1 + k1) * 6;
+          const cx<T> gxx = Gp[0], gyy = Gp[3], gzz = Gp[5];
+          const cx<T> gxy = cscale(Gp[1], s1 * s2), gxz = cscale(Gp[2], s1 * s3), gyz = cscale(Gp[4], s2 * s3);
+          const cx<T> ux = v[0][m], uy = v[1][m], uz = v[2][m];
+          v[0][m] = cadd(cadd(cmul(gxx, ux), cmul(gxy, uy)), cmul(gxz, uz));
+          v[1][m] = cadd(cadd(cmul(gxy, ux), cmul(gyy, uy)), cmul(gyz, uz));
+          v[2][m] = cadd(cadd(cmul(gxz, ux), cmul(gyz, uy)), cmul(gzz, uz));
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          fft64<T, true>(v[c], w, a, X);   // v[c][b] = column value at y = a + 8 b
+#pragma unroll
+          for (int b = 0; b < 4; ++b) R[hpos(c, a + 8 * b, q)] = v[c][b];
+        }
+      }
+      __syncthreads();
+      // ---- C_h: inverse x transform of row y from the frequencies of half h.  The
+      // row's input is read again first (for A_1; unconditional, so that in[] is not
+      // carried across the column stage), then half 0 parks its partial result in
+      // the row's place and half 1 adds to it.
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int x = a + 8 * b;
+          in[c][b] = (x < n1 && row_ok) ? P[(c * n2 + y) * n1 + x] : zero;
+        }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cx<T> v[8];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const cx<T> t = R[hpos(c, y, a + 8 * m)];
+          v[m] = cx<T>{first ? t.x : (T)0, first ? t.y : (T)0};
+          v[m + 4] = cx<T>{first ? (T)0 : t.x, first ? (T)0 : t.y};
+        }
+        fft64<T, true>(v, w, a, X);        // v[b] = row value at x = a + 8 b
+        if (row_ok) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int x = a + 8 * b;
+            if (x < n1) {
+              cx<T>* o = P + (c * n2 + y) * n1 + x;
+              *o = first ? v[b] : cadd(*o, v[b]);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+
 // plane pair p: (0, M3/2) for p = 0, (p, M3 - p) otherwise
 __device__ __forceinline__ void pair_planes(int p, int M3, int* a, int* b) {
   *a = p == 0 ? 0 : p;
   *b = p == 0 ? M3 / 2 : M3 - p;
 }
 
-template <typename T>
+// V = 0: full-plane variant; V = 1: x-frequency halves
+template <typename T, int V>
+__device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
+                                            const cx<T>* __restrict__ tw64, int kz_first, int nplanes, int kz_second,
+                                            cx<T>* R) {
+  if constexpr (V == 0) xy64_full<T>(U, goct, g, tw64, kz_first, nplanes, kz_second, R);
+  else xy64_half<T>(U, goct, g, tw64, kz_first, nplanes, kz_second, R);
+}
+
+template <typename T, int V>
 __device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
                                           const cx<T>* __restrict__ tw64, int pair, cx<T>* R) {
   int a, b;
   pair_planes(pair, g.M3, &a, &b);
-  xy64_planes<T>(U, goct, g, tw64, a, g.M3 == 1 ? 1 : 2, b, R);
+  xy64_planes<T, V>(U, goct, g, tw64, a, g.M3 == 1 ? 1 : 2, b, R);
 }
 
 // One plane per workgroup.  The two planes of a pair read the same spectrum
 // slab; they go to workgroups b and b + 8 (same XCD under round-robin
 // dispatch, launched one after the other) so the second read hits L2.
-template <typename T>
-__global__ __launch_bounds__(256) void k_xy64(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, Geom g,
-                                              const cx<T>* __restrict__ tw64) {
+template <typename T, int V>
+__global__ __launch_bounds__(256, V == 1 ? 2 : 1) void k_xy64(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct,
+                                                              Geom g, const cx<T>* __restrict__ tw64) {
   extern __shared__ unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int base = (b / 16) * 16, r = b - base;
   int pa, pb;
   pair_planes(base / 2 + (r % 8), g.M3, &pa, &pb);
-  xy64_planes<T>(U, goct, g, tw64, r < 8 ? pa : pb, 1, 0, reinterpret_cast<cx<T>*>(smem_raw));
+  xy64_planes<T, V>(U, goct, g, tw64, r < 8 ? pa : pb, 1, 0, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_xy64_batch(const PassDesc* __restrict__ d, const int* __restrict__ prefix,
-                                                    int nsys, int total) {
+template <typename T, int V>
+__global__ __launch_bounds__(256, V == 1 ? 2 : 1) void k_xy64_batch(const PassDesc* __restrict__ d,
+                                                                    const int* __restrict__ prefix, int nsys,
+                                                                    int total) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* R = reinterpret_cast<cx<T>*>(smem_raw);
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
@@ -255,55 +427,75 @@ __global__ __launch_bounds__(256) void k_xy64_batch(const PassDesc* __restrict__
     }
     const PassDesc& D = d[lo];
     if (D.active && *D.active == 0) continue;
-    xy64_body<T>((cx<T>*)D.U, (const cx<T>*)D.goct, D.g, (const cx<T>*)D.twx, item - prefix[lo], R);
+    xy64_body<T, V>((cx<T>*)D.U, (const cx<T>*)D.goct, D.g, (const cx<T>*)D.twx, item - prefix[lo], R);
     __syncthreads();
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_xy64_batch_single(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct,
-                                                           Geom g, const cx<T>* __restrict__ tw64) {
+template <typename T, int V>
+__global__ __launch_bounds__(256, V == 1 ? 2 : 1) void k_xy64_batch_single(cx<T>* __restrict__ U,
+                                                                           const cx<T>* __restrict__ goct, Geom g,
+                                                                           const cx<T>* __restrict__ tw64) {
   extern __shared__ unsigned char smem_raw[];
-  xy64_body<T>(U, goct, g, tw64, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+  xy64_body<T, V>(U, goct, g, tw64, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 template <typename T>
+size_t xy64_lds(int V) {
+  return (size_t)(V == 1 ? kXyLdsVals : kFullLdsVals) * sizeof(cx<T>);
+}
+
+// Variant of the batched kernel: x-frequency halves in FP64 (register-bound
+// planes gain from two workgroups per CU), full plane in FP32.
+template <typename T>
+constexpr int kBatchVariant = sizeof(T) == 8 ? 1 : 0;
+
+template <typename T>
 hipError_t launch_xy64_batch(const PassDesc* d, const int* prefix, int nsys, int total, hipStream_t s) {
-  const size_t lds = (size_t)3 * 32 * 64 * sizeof(cx<T>);
-  hipLaunchKernelGGL((k_xy64_batch<T>), dim3(total < 4096 ? total : 4096), dim3(256), lds, s, d, prefix, nsys,
-                     total);
+  constexpr int V = kBatchVariant<T>;
+  hipLaunchKernelGGL((k_xy64_batch<T, V>), dim3(total < 4096 ? total : 4096), dim3(256), xy64_lds<T>(V), s, d,
+                     prefix, nsys, total);
   return hipGetLastError();
 }
 template hipError_t launch_xy64_batch<double>(const PassDesc*, const int*, int, int, hipStream_t);
 template hipError_t launch_xy64_batch<float>(const PassDesc*, const int*, int, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_xy64(const Geom& g, void* U, const void* goct, const void* tw1, hipStream_t s) {
-  const size_t lds = (size_t)3 * 32 * 64 * sizeof(cx<T>);
+hipError_t launch_xy64(const Geom& g, int V, void* U, const void* goct, const void* tw1, hipStream_t s) {
+  const size_t lds = xy64_lds<T>(V);
   if (g.M3 % 16 != 0) {   // short z circulant: one workgroup per plane pair
-    hipLaunchKernelGGL((k_xy64_batch_single<T>), dim3(g.M3 == 1 ? 1 : g.M3 / 2), dim3(256), lds, s, (cx<T>*)U,
-                       (const cx<T>*)goct, g, (const cx<T>*)tw1);
+    const dim3 grid(g.M3 == 1 ? 1 : g.M3 / 2);
+    if (V == 1)
+      hipLaunchKernelGGL((k_xy64_batch_single<T, 1>), grid, dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
+                         (const cx<T>*)tw1);
+    else
+      hipLaunchKernelGGL((k_xy64_batch_single<T, 0>), grid, dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
+                         (const cx<T>*)tw1);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_xy64<T>), dim3(g.M3), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
-                     (const cx<T>*)tw1);
+  if (V == 1)
+    hipLaunchKernelGGL((k_xy64<T, 1>), dim3(g.M3), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
+                       (const cx<T>*)tw1);
+  else
+    hipLaunchKernelGGL((k_xy64<T, 0>), dim3(g.M3), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
+                       (const cx<T>*)tw1);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t allow_lds_xy64() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_xy64<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)((size_t)3 * 32 * 64 * sizeof(cx<T>)));
-  if (e) return e;
-  e = hipFuncSetAttribute((const void*)k_xy64_batch_single<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)((size_t)3 * 32 * 64 * sizeof(cx<T>)));
-  if (e) return e;
-  return hipFuncSetAttribute((const void*)k_xy64_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)((size_t)3 * 32 * 64 * sizeof(cx<T>)));
+  const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)k_xy64<T, 0>, attr, (int)xy64_lds<T>(0)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_xy64<T, 1>, attr, (int)xy64_lds<T>(1)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_xy64_batch_single<T, 0>, attr, (int)xy64_lds<T>(0)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_xy64_batch_single<T, 1>, attr, (int)xy64_lds<T>(1)))) return e;
+  return hipFuncSetAttribute((const void*)k_xy64_batch<T, kBatchVariant<T>>, attr,
+                             (int)xy64_lds<T>(kBatchVariant<T>));
 }
 
-template hipError_t launch_xy64<double>(const Geom&, void*, const void*, const void*, hipStream_t);
-template hipError_t launch_xy64<float>(const Geom&, void*, const void*, const void*, hipStream_t);
+template hipError_t launch_xy64<double>(const Geom&, int, void*, const void*, const void*, hipStream_t);
+template hipError_t launch_xy64<float>(const Geom&, int, void*, const void*, const void*, hipStream_t);
 template hipError_t allow_lds_xy64<double>();
 template hipError_t allow_lds_xy64<float>();
 

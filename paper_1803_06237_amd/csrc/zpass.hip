@@ -179,29 +179,54 @@ struct ZShape {
   int A, B, P;
 };
 
+// Pencil counts P tried by the plan-time tuner, default first; each keeps the
+// workgroup (A P threads) within the kernels' 256 and its LDS (M3 (P + 1) values)
+// within 160 KiB.
 template <typename T>
-static bool zshape(int M3, ZShape<T>* s) {
+int z4_pencil_options(int M3, int* out, int cap) {
   const bool dbl = sizeof(T) == 8;
-  if (M3 == 512) *s = {16, 32, dbl ? 8 : 16};
-  else if (M3 == 1024) *s = {32, 32, dbl ? 4 : 8};
-  else if (M3 == 2048 && !dbl) *s = {32, 64, 4};
-  else return false;
+  int opts[4] = {0, 0, 0, 0}, n = 0;
+  if (M3 == 512) {                                   // A = 16
+    if (dbl) { opts[0] = 8; opts[1] = 4; opts[2] = 16; n = 3; }
+    else { opts[0] = 16; opts[1] = 8; n = 2; }
+  } else if (M3 == 1024) {                           // A = 32
+    if (dbl) { opts[0] = 4; opts[1] = 2; opts[2] = 8; n = 3; }
+    else { opts[0] = 8; opts[1] = 4; n = 2; }
+  } else if (M3 == 2048 && !dbl) {                   // A = 32
+    opts[0] = 4; opts[1] = 2; n = 2;
+  }
+  for (int i = 0; i < n && i < cap; ++i) out[i] = opts[i];
+  return n;
+}
+
+template <typename T>
+static bool zshape(int M3, ZShape<T>* s, int P = 0) {
+  int opts[4];
+  const int n = z4_pencil_options<T>(M3, opts, 4);
+  if (n == 0) return false;
+  bool ok = P == 0;
+  for (int i = 0; i < n; ++i) ok = ok || opts[i] == P;
+  if (!ok) return false;
+  const int p = P ? P : opts[0];
+  if (M3 == 512) *s = {16, 32, p};
+  else if (M3 == 1024) *s = {32, 32, p};
+  else *s = {32, 64, p};
   return true;
 }
 
 template <typename T>
-size_t z4_lds_bytes(int M3) {
+size_t z4_lds_bytes(int M3, int P) {
   ZShape<T> s;
-  if (!zshape<T>(M3, &s)) return 0;
+  if (!zshape<T>(M3, &s, P)) return 0;
   return (size_t)M3 * (s.P + 1) * sizeof(cx<T>);
 }
 
 template <typename T>
-hipError_t launch_z4(int which, const Geom& g, const void* x, void* y, const void* b, int mode, void* U,
+hipError_t launch_z4(int which, const Geom& g, int P, const void* x, void* y, const void* b, int mode, void* U,
                      const void* chi, const void* twz, hipStream_t st) {
   using C = cx<T>;
   ZShape<T> s;
-  if (!zshape<T>(g.M3, &s)) return hipErrorNotSupported;
+  if (!zshape<T>(g.M3, &s, P)) return hipErrorNotSupported;
   const int nb1 = (g.n1 + s.P - 1) / s.P;
   const dim3 grid(3 * g.n2 * nb1), block(s.A * s.P);
   const size_t lds = (size_t)g.M3 * (s.P + 1) * sizeof(C);
@@ -339,19 +364,21 @@ hipError_t allow_lds_z4() {
   return hipSuccess;
 }
 
-template hipError_t launch_z4<double>(int, const Geom&, const void*, void*, const void*, int, void*, const void*,
-                                      const void*, hipStream_t);
-template hipError_t launch_z4<float>(int, const Geom&, const void*, void*, const void*, int, void*, const void*,
-                                     const void*, hipStream_t);
+template hipError_t launch_z4<double>(int, const Geom&, int, const void*, void*, const void*, int, void*,
+                                      const void*, const void*, hipStream_t);
+template hipError_t launch_z4<float>(int, const Geom&, int, const void*, void*, const void*, int, void*,
+                                     const void*, const void*, hipStream_t);
+template int z4_pencil_options<double>(int, int*, int);
+template int z4_pencil_options<float>(int, int*, int);
 template hipError_t allow_lds_z4<double>();
 template hipError_t allow_lds_z4<float>();
-template size_t z4_lds_bytes<double>(int);
+template size_t z4_lds_bytes<double>(int, int);
 template bool z4_shape<double>(int, int*, int*, int*);
 template bool z4_shape<float>(int, int*, int*, int*);
 template hipError_t launch_z4_batch<double>(int, int, const PassDesc*, const int*, int, int, int, int, int, int, int,
                                             hipStream_t);
 template hipError_t launch_z4_batch<float>(int, int, const PassDesc*, const int*, int, int, int, int, int, int, int,
                                            hipStream_t);
-template size_t z4_lds_bytes<float>(int);
+template size_t z4_lds_bytes<float>(int, int);
 
 }  // namespace vie

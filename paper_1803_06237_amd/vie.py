@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvie.so")
 
 VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENUMERIC, VIE_ESTATE, VIE_ENOTIMPL = \
     0, -1, -2, -3, -4, -5, -6, -7
-VIE_FP64, VIE_WITH_FP32 = 0, 1
+VIE_FP64, VIE_WITH_FP32, VIE_NO_AUTOTUNE = 0, 1, 2
 
 _lib = None
 
@@ -92,6 +92,8 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(vp), ctypes.c_float, ctypes.POINTER(ctypes.c_double)]
         L.vie_set_preconditioner.argtypes = [vp, vp]
         L.vie_circulant_build.argtypes = [vp, ctypes.c_uint, ctypes.POINTER(CirculantInfo)]
+        L.vie_get_tune.argtypes = [vp, ctypes.c_int, ip, ip]
+        L.vie_set_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.vie_circulant_apply.argtypes = [vp, vp, vp]
         L.vie_nn_conv_test.argtypes = [ctypes.c_int, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                        ctypes.c_int, vp]
@@ -223,6 +225,16 @@ class Plan:
     def set_preconditioner(self, net):
         _check(lib().vie_set_preconditioner(self._h, net.handle if net is not None else None), self._h)
         self._net = net
+
+    def tune(self, precision: int = 0) -> dict:
+        """Launch shapes in use (vie_get_tune)."""
+        xv, zp = ctypes.c_int(), ctypes.c_int()
+        _check(lib().vie_get_tune(self._h, int(precision), ctypes.byref(xv), ctypes.byref(zp)), self._h)
+        return {"xy_variant": xv.value, "z_pencils": zp.value}
+
+    def set_tune(self, precision: int, xy_variant: int, z_pencils: int = 0):
+        """Force launch shapes (vie_set_tune)."""
+        _check(lib().vie_set_tune(self._h, int(precision), int(xy_variant), int(z_pencils)), self._h)
 
     def build_circulant(self, fp64: bool = False) -> dict:
         """Block-circulant preconditioner of the current contrast (vie_circulant_build)."""

@@ -73,4 +73,6 @@ def test_plan_rejects_bad_arguments_before_touching_the_device():
     assert L.vie_set_contrast(None, None) == vie.VIE_EINVAL
     assert L.vie_circulant_build(None, 0, None) == vie.VIE_EINVAL
     assert L.vie_circulant_apply(None, None, None) == vie.VIE_EINVAL
+    assert L.vie_get_tune(None, 0, None, None) == vie.VIE_EINVAL
+    assert L.vie_set_tune(None, 0, 0, 0) == vie.VIE_EINVAL
     L.vie_destroy(None)

@@ -199,3 +199,76 @@ def test_maximum_grid_runs():
         for a, ci in ((0, 1), (1, 3), (2, 4)):      # column b = 1: xy, yy, yz
             want = x[(a,) + tuple(o)] - chi[tuple(o)] * Nab[ci]
             assert abs(y[(a,) + tuple(o)] - want) < 1e-13
+
+
+def _sampled_expectation(wg, nnz, nout, seed):
+    """x with nnz random non-zeros and the oracle's outputs at nout sampled voxels."""
+    n = wg.n
+    rng = np.random.default_rng(seed)
+    kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+    chi = mv.contrast(wg.eps(), wg.eps_b)
+    x = np.zeros((3,) + n, complex)
+    src = np.stack([rng.integers(0, n[d], nnz) for d in range(3)], 1)
+    comp = rng.integers(0, 3, nnz)
+    vals = _cvec(rng, nnz)
+    for s, c, v in zip(src, comp, vals):
+        x[(c,) + tuple(s)] += v
+    core = np.argwhere(wg.core_mask())
+    outs = np.concatenate([core[rng.integers(0, len(core), nout // 2)],
+                           np.stack([rng.integers(0, n[d], nout - nout // 2) for d in range(3)], 1)])
+    Nab = green.galerkin_N((outs[:, None, :] - src[None, :, :]).reshape(-1, 3), kap).reshape(6, len(outs), nnz)
+    full = {}
+    for ci, (a, b) in enumerate(green.COMPONENTS):
+        full[(a, b)] = full[(b, a)] = Nab[ci]
+    want = np.empty((len(outs), 3), complex)
+    i = tuple(outs.T)
+    for a in range(3):
+        Nx = np.zeros(len(outs), complex)
+        for b in range(3):
+            Nx += (full[(a, b)] * np.where(comp == b, vals, 0)[None, :]).sum(axis=1)
+        want[:, a] = x[(a,) + i] - chi[i] * Nx
+    return x, outs, want
+
+
+TUNED_GRIDS = {
+    "32x32x512_M3_1024": lambda: inputs.strip_long(d=2),
+    "24x20x200_M3_512": lambda: inputs.Waveguide(n=(24, 20, 200), h=0.025, core_x=(4, 20), core_y=(6, 14),
+                                                 core_z=(0, 200), n_abs=30, d=2, sigma_max=10.0),
+}
+
+
+@pytest.mark.parametrize("grid", sorted(TUNED_GRIDS))
+def test_every_launch_shape_matches_the_oracle(grid):
+    """Each candidate the plan-time tuner can pick (xy pass variant x z-pass pencils per
+    workgroup, FP64 and FP32) gives the oracle's product on sampled outputs."""
+    vie = _dev()
+    wg = TUNED_GRIDS[grid]()
+    x, outs, want = _sampled_expectation(wg, nnz=20, nout=48, seed=7)
+    plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    plan.set_contrast(_t(wg.eps()))
+    print(grid, "tuned:", plan.tune(0), plan.tune(1))
+    M3 = 1 << int(np.ceil(np.log2(2 * wg.n[2] - 1)))
+    pencils = {0: {512: (8, 4, 16), 1024: (4, 2, 8)}[M3], 1: {512: (16, 8), 1024: (8, 4)}[M3]}
+    xt = _t(x)
+    xt32 = _t(x, torch.complex64)
+    i = tuple(outs.T)
+    for precision in (0, 1):
+        for xyv in (0, 1):
+            for zp in pencils[precision]:
+                plan.set_tune(precision, xyv, zp)
+                assert plan.tune(precision) == {"xy_variant": xyv, "z_pencils": zp}
+                if precision == 0:
+                    y = plan.matvec(xt).cpu().numpy()
+                else:
+                    y = plan.matvec_c64(xt32).cpu().numpy().astype(np.complex128)
+                got = np.stack([y[(a,) + i] for a in range(3)], 1)
+                # FP64 relative to the sampled outputs; FP32 rounding of the FFTs scales
+                # with the input, so relative to max |x| (the sampled outputs far from
+                # the sources are ~1e-3 of it)
+                scale = np.max(np.abs(want)) if precision == 0 else np.max(np.abs(x))
+                err = np.max(np.abs(got - want)) / scale
+                print(grid, precision, xyv, zp, f"{err:.2e}")
+                assert err < (1e-12 if precision == 0 else 5e-6)
+    with pytest.raises(vie.VieError) as ei:
+        plan.set_tune(0, 1, 3)
+    assert ei.value.code == vie.VIE_EINVAL
