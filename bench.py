@@ -274,6 +274,7 @@ def main():
         out["solve_to_1e-8"] = res
         from paper_1803_06237_amd import experiments
         out["iterations_vs_length"] = experiments.iterations_vs_length()
+        out["mixed_vs_fp64_observables"] = experiments.mixed_vs_fp64()
 
     if not args.no_family:
         from paper_1803_06237_amd import experiments

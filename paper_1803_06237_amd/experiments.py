@@ -13,6 +13,7 @@ the returned currents on the host.
 from __future__ import annotations
 
 import itertools
+import math
 import time
 from typing import Dict, List, Sequence
 
@@ -147,4 +148,47 @@ def iterations_vs_length(n3s: Sequence[int] = (128, 256, 512, 1024), d: int = 2,
         out["circulant_solve_seconds"].append(round(t_circ, 4))
         out["circulant_setup_seconds"].append(round(t_setup, 4))
         plan.close()
+    return out
+
+
+def mixed_vs_fp64(degrees: Sequence[int] = DEGREES, tol: float = 1e-8, ref_tol: float = 1e-10) -> dict:
+    """The mixed tier against FP64 on the 8 x 8 x 32 guide (h = 50 nm, 4 x 4 core, 8-voxel
+    absorbers, sigma_max = 2, z-dipole where the lossless core starts), per absorber degree:
+    relative L2 distance of the two solutions, and the reflection R of each against an FP64
+    reference with 64-voxel absorbers (8 x 8 x 144, same cross-section, same source plane
+    relative to the lossless part), R as in Section V-A over the lossless part."""
+    import torch
+    out = {"degrees": list(degrees), "rel_l2": [], "R_fp64": [], "R_mixed": [], "rel_dR": [],
+           "rel_res_fp64": [], "rel_res_mixed": [], "inner_iters": []}
+    for d in degrees:
+        wg = inputs.strip_small(d=d)
+        ref = inputs.Waveguide(n=(8, 8, 144), h=wg.h, core_x=wg.core_x, core_y=wg.core_y, core_z=(0, 144),
+                               n_abs=64, d=d, sigma_max=wg.sigma_max)
+        kb = wg.k0 * math.sqrt(wg.eps_b)
+        fields = {}
+        for name, g in (("ref", ref), ("short", wg)):
+            plan = vie.Plan(g.n, g.h, g.k0, g.eps_b, fp32=True)
+            plan.set_contrast(torch.from_numpy(g.eps()).cuda())
+            r0 = (g.h * 4, g.h * 4, g.h * g.n_abs)
+            e = inputs.dipole_field(g.n, g.h, r0, (0, 0, 1), kb)
+            b = plan.rhs(torch.from_numpy(e).cuda())
+            if name == "ref":
+                x, info = plan.solve(b, tol=ref_tol, restart=200, precision=0)
+                fields["ref"] = axis_field(g, x.cpu().numpy())
+            else:
+                x64, i64 = plan.solve(b, tol=tol, restart=50, precision=0)
+                x32, i32 = plan.solve(b, tol=tol, restart=50, precision=1, inner_restart=20, inner_tol=1e-4)
+                a64, a32 = x64.cpu().numpy(), x32.cpu().numpy()
+                out["rel_l2"].append(float(np.linalg.norm(a32 - a64) / np.linalg.norm(a64)))
+                out["rel_res_fp64"].append(i64["rel_res_true"])
+                out["rel_res_mixed"].append(i32["rel_res_true"])
+                out["inner_iters"].append(i32["inner_iters"])
+                fields["fp64"] = axis_field(g, a64)
+                fields["mixed"] = axis_field(g, a32)
+            plan.close()
+        Eref = fields["ref"]
+        R = {k: float(np.sum(np.abs(Eref - fields[k]) ** 2) / np.sum(np.abs(Eref) ** 2)) for k in ("fp64", "mixed")}
+        out["R_fp64"].append(R["fp64"])
+        out["R_mixed"].append(R["mixed"])
+        out["rel_dR"].append(abs(R["mixed"] - R["fp64"]) / R["fp64"])
     return out
