@@ -17,13 +17,15 @@
 //   8 x 8 exchanges between workgroup barriers: rows forward; columns forward,
 //   Green product and inverse in two halves of kx; rows inverse, crop, store.
 //  V = 1 (x-frequency halves): the 64 x-frequencies are processed in two halves
-//   so that the row-to-column hand-off needs 3 x 32 x 32 values of LDS, and each
+//   (|kx| <= 16 and |kx| >= 16 after folding, so each half reads its own part of
+//   the spectrum slab) so that the row-to-column hand-off needs 3 x 32 x 32
+//   values of LDS, and each
 //   group of 8 lanes exchanges through its own 64-value LDS area without
 //   workgroup barriers (80 KiB FP64 in all, two workgroups per CU):
 //   A_h: rows (x) forward for row y = group, all 3 components; the 32
 //        frequencies of half h go to LDS;
-//   B_h: columns (y) forward, Green product, columns inverse for column
-//        kx = 32 h + group, in place in LDS;
+//   B_h: columns (y) forward, Green product, columns inverse for one column
+//        of the half per group, in place in LDS;
 //   C_h: rows inverse from the 32 frequencies of half h (the rest taken as
 //        zero); half 0 parks its partial row in the plane's own storage (after
 //        reading the row input again for A_1) and half 1 adds to it.
@@ -46,6 +48,11 @@ __device__ __forceinline__ int hpos(int c, int y, int j) { return (c * 32 + y) *
 constexpr int kRowVals = 3 * 32 * 32;               // row/column hand-off of one half
 constexpr int kXyLdsVals = kRowVals + 32 * 64;      // + 32 groups x 64 exchange values
 constexpr int kFullLdsVals = 3 * 32 * 64;           // full-plane variant: rows of all 64 frequencies
+// x-frequency halves of the V = 1 variant, as the m of kx = a + 8 m (a = lane):
+// half 0 = m in {0, 1, 6, 7} (kx < 16 or kx >= 48, folded |kx| <= 16), half 1 =
+// m in {2, 3, 4, 5} (16 <= kx < 48, folded |kx| >= 16), so that the two halves
+// read disjoint parts of the folded spectrum slab.
+__constant__ constexpr int kHalf0[4] = {0, 1, 6, 7};
 
 // full-plane variant: element (c, y, kx) of the row buffer, and the 8 x 8 exchange
 // block of group gr (64 values) with element (i, j) rotated as in xpos
@@ -294,15 +301,16 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
         for (int b = 4; b < 8; ++b) v[b] = zero;
         fft64<T, false>(v, w, a, X);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const cx<T> lo = v[m], up = v[m + 4];
-          R[hpos(c, y, a + 8 * m)] = cx<T>{first ? lo.x : up.x, first ? lo.y : up.y};
+        for (int j = 0; j < 4; ++j) {
+          const cx<T> h0 = v[kHalf0[j]], h1 = v[j + 2];
+          R[hpos(c, y, a + 8 * j)] = cx<T>{first ? h0.x : h1.x, first ? h0.y : h1.y};
         }
       }
       __syncthreads();
-      // ---- B_h: column kx = 32 h + q: forward y transform, Green product, inverse, crop
+      // ---- B_h: LDS column q = a' + 8 j holds kx = a' + 8 m with m the j-th of the half
       {
-        const int kx = 32 * h + q;
+        const int jq = q >> 3;
+        const int kx = (q & 7) + 8 * (first ? (jq < 2 ? jq : jq + 4) : jq + 2);
         cx<T> v[3][8];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -352,10 +360,12 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
       for (int c = 0; c < 3; ++c) {
         cx<T> v[8];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const cx<T> t = R[hpos(c, y, a + 8 * m)];
-          v[m] = cx<T>{first ? t.x : (T)0, first ? t.y : (T)0};
-          v[m + 4] = cx<T>{first ? (T)0 : t.x, first ? (T)0 : t.y};
+        for (int j = 0; j < 4; ++j) {
+          const cx<T> t = R[hpos(c, y, a + 8 * j)];
+          const cx<T> in0{first ? t.x : (T)0, first ? t.y : (T)0};
+          const cx<T> in1{first ? (T)0 : t.x, first ? (T)0 : t.y};
+          v[kHalf0[j]] = in0;
+          v[j + 2] = in1;
         }
         fft64<T, true>(v, w, a, X);        // v[b] = row value at x = a + 8 b
         if (row_ok) {
