@@ -3,19 +3,25 @@
 Section V-D of the paper preconditions GMRES with the block-circulant matrix W
 closest to ``I - M_eps N`` in the Frobenius norm, circulant along one or more of
 the three Toeplitz levels (the conclusion names "one or more levels").  The
-reading taken here: circulant along the waveguide axis (the third level, n3
-slices), dense within a cross-section restricted to the support S of the
-contrast (the operator is the identity on every other voxel and stays in S when
-the right-hand side does).
+reading taken here: circulant along the waveguide axis (the third level),
+dense within a cross-section, and restricted to the support of the contrast in
+all three axes, since the operator is the identity on every other voxel:
 
-With blocks ``A_{i,j} = delta_ij I - D_i N_{i-j}`` (slices i, j; D_i the contrast
-of slice i on S, N_m the cross-section block of N at z-offset m), the
-Frobenius-nearest block circulant averages the blocks of every wrapped diagonal
-(i - j) mod n3 = k:
+* columns: the voxel columns S where chi is non-zero on some slice;
+* slices: a window of P consecutive slices starting at z0 that covers every
+  slice where chi is non-zero on S, with P the smallest length >= that extent
+  whose prime factors are 2, 3, 5 (P <= n3; otherwise P = n3), and z0 as small
+  a shift of the first such slice as keeps the window inside the grid.
 
-    W_k = delta_k0 I - (1/n3) [ (sum_{i >= k} D_i) N_k + (sum_{i < k} D_i) N_{k - n3} ]
+With blocks ``A_{i,j} = delta_ij I - D_i N_{i-j}`` (window slices i, j; D_i the
+contrast of slice z0 + i on S, N_m the cross-section block of N at z-offset m),
+the Frobenius-nearest block circulant averages the blocks of every wrapped
+diagonal (i - j) mod P = k:
 
-and is block-diagonalised by the DFT along the slices.
+    W_k = delta_k0 I - (1/P) [ (sum_{i >= k} D_i) N_k + (sum_{i < k} D_i) N_{k - P} ]
+
+and is block-diagonalised by the DFT along the window.  Every voxel outside
+S x window keeps the identity.
 """
 from __future__ import annotations
 
@@ -28,6 +34,32 @@ from .green import COMPONENTS, parity
 def support_columns(chi: np.ndarray) -> np.ndarray:
     """Cross-section voxels (i1, i2) where the contrast is non-zero on some slice, (|S|, 2)."""
     return np.argwhere(np.any(chi != 0, axis=2))
+
+
+def smooth_length(n: int) -> int:
+    """Smallest integer >= n whose prime factors are 2, 3 and 5."""
+    m = max(n, 1)
+    while True:
+        v = m
+        for p in (2, 3, 5):
+            while v % p == 0:
+                v //= p
+        if v == 1:
+            return m
+        m += 1
+
+
+def support_window(chi: np.ndarray) -> tuple:
+    """(z0, P): the slice window of the preconditioner (module docstring)."""
+    n3 = chi.shape[2]
+    on = np.nonzero(np.any(chi != 0, axis=(0, 1)))[0]
+    if len(on) == 0:
+        return 0, n3
+    first, last = int(on[0]), int(on[-1])
+    P = smooth_length(last - first + 1)
+    if P > n3:
+        return 0, n3
+    return min(first, n3 - P), P
 
 
 def _N_block(table: np.ndarray, S: np.ndarray, m3: int) -> np.ndarray:
@@ -52,13 +84,13 @@ def _N_block(table: np.ndarray, S: np.ndarray, m3: int) -> np.ndarray:
 
 
 def dense_A_on_support(table: np.ndarray, chi: np.ndarray, S: np.ndarray) -> np.ndarray:
-    """I - D N restricted to (S x slices) in slice-major order: block (i, j) of size 3|S|."""
-    n3 = chi.shape[2]
+    """I - D N restricted to S x window in slice-major order: block (i, j) of size 3|S|."""
+    z0, n3 = support_window(chi)
     s = len(S)
     m = 3 * s
     A = np.zeros((n3 * m, n3 * m), dtype=np.complex128)
     for i in range(n3):
-        Di = np.tile(chi[S[:, 0], S[:, 1], i], 3)
+        Di = np.tile(chi[S[:, 0], S[:, 1], z0 + i], 3)
         for j in range(n3):
             blk = -Di[:, None] * _N_block(table, S, i - j)
             if i == j:
@@ -68,11 +100,11 @@ def dense_A_on_support(table: np.ndarray, chi: np.ndarray, S: np.ndarray) -> np.
 
 
 def optimal_blocks(table: np.ndarray, chi: np.ndarray, S: np.ndarray) -> np.ndarray:
-    """W_k, k < n3, shape (n3, 3|S|, 3|S|) (the formula in the module docstring)."""
-    n3 = chi.shape[2]
+    """W_k, k < P, shape (P, 3|S|, 3|S|) (the formula in the module docstring)."""
+    z0, n3 = support_window(chi)
     s = len(S)
     m = 3 * s
-    D = np.stack([np.tile(chi[S[:, 0], S[:, 1], i], 3) for i in range(n3)])      # (n3, m)
+    D = np.stack([np.tile(chi[S[:, 0], S[:, 1], z0 + i], 3) for i in range(n3)])   # (P, m)
     W = np.zeros((n3, m, m), dtype=np.complex128)
     for k in range(n3):
         up = D[k:].sum(axis=0)
@@ -101,26 +133,28 @@ def spectrum_inverse(W: np.ndarray) -> np.ndarray:
     return np.linalg.inv(What)
 
 
-def apply(Winv_hat: np.ndarray, S: np.ndarray, r: np.ndarray) -> np.ndarray:
-    """z = W^{-1} r on S (slices along the last axis), identity elsewhere.  r: (3, n1, n2, n3)."""
+def apply(Winv_hat: np.ndarray, S: np.ndarray, r: np.ndarray, window: tuple) -> np.ndarray:
+    """z = W^{-1} r on S x window (window = support_window(chi)), identity elsewhere.
+    r: (3, n1, n2, n3)."""
+    z0, P = window
     z = r.copy()
     s = len(S)
-    R = np.concatenate([r[a][S[:, 0], S[:, 1], :] for a in range(3)], axis=0)   # (3|S|, n3)
+    R = np.concatenate([r[a][S[:, 0], S[:, 1], z0:z0 + P] for a in range(3)], axis=0)   # (3|S|, P)
     Rh = _fft.fft(R, axis=1)
     Zh = np.einsum("fij,jf->if", Winv_hat, Rh)
     Z = _fft.fft(Zh, axis=1, inverse=True)
     for a in range(3):
-        z[a][S[:, 0], S[:, 1], :] = Z[a * s:(a + 1) * s]
+        z[a][S[:, 0], S[:, 1], z0:z0 + P] = Z[a * s:(a + 1) * s]
     return z
 
 
 def frequency_block(table: np.ndarray, chi: np.ndarray, S: np.ndarray, f: int) -> np.ndarray:
-    """One DFT block What_f = sum_k W_k exp(-2 pi i f k / n3), accumulated one W_k at a
-    time (for full-size grids whose n3 blocks do not fit in memory together)."""
-    n3 = chi.shape[2]
+    """One DFT block What_f = sum_k W_k exp(-2 pi i f k / P), accumulated one W_k at a
+    time (for full-size grids whose P blocks do not fit in memory together)."""
+    z0, n3 = support_window(chi)
     s = len(S)
     m = 3 * s
-    D = np.stack([np.tile(chi[S[:, 0], S[:, 1], i], 3) for i in range(n3)])
+    D = np.stack([np.tile(chi[S[:, 0], S[:, 1], z0 + i], 3) for i in range(n3)])
     suffix = np.cumsum(D[::-1], axis=0)[::-1]            # suffix[k] = sum_{i >= k} D_i
     total = suffix[0]
     out = np.eye(m, dtype=np.complex128)

@@ -25,11 +25,13 @@ def _case(n=(3, 3, 7), cols=((0, 0), (1, 1), (2, 1), (1, 2)), z_varying=True):
     return table, chi
 
 
-def _support_perm(n, S):
-    """Rows of the (3, n1, n2, n3) flattening in the slice-major support order (i3, a, p)."""
+def _support_perm(n, S, window=None):
+    """Rows of the (3, n1, n2, n3) flattening in the slice-major support order (i3, a, p),
+    i3 over the window (z0, P) (default: all slices)."""
     n1, n2, n3 = n
+    z0, P = window if window is not None else (0, n3)
     idx = []
-    for i3 in range(n3):
+    for i3 in range(z0, z0 + P):
         for a in range(3):
             for (i1, i2) in S:
                 idx.append(((a * n1 + i1) * n2 + i2) * n3 + i3)
@@ -101,7 +103,7 @@ def test_fft_apply_solves_the_block_circulant():
     W = circ.optimal_blocks(table, chi, S)
     Winv = circ.spectrum_inverse(W)
     r = RNG.standard_normal((3,) + n) + 1j * RNG.standard_normal((3,) + n)
-    z = circ.apply(Winv, S, r)
+    z = circ.apply(Winv, S, r, circ.support_window(chi))
     perm = _support_perm(n, S)
     zs = np.linalg.solve(circ.block_circulant_dense(W), r.ravel()[perm])
     assert np.allclose(z.ravel()[perm], zs, atol=1e-12, rtol=0)
@@ -136,7 +138,8 @@ def test_preconditioner_cuts_iterations_and_keeps_the_solution():
         S = circ.support_columns(chi)
         Winv = circ.spectrum_inverse(circ.optimal_blocks(table, chi, S))
         b = mv.rhs_from_field(wg.eps(), wg.eps_b, inputs.gaussian_rhs(wg.n, 1), wg.h).ravel()
-        pc = lambda v: circ.apply(Winv, S, v.reshape((3,) + wg.n)).ravel()
+        win = circ.support_window(chi)
+        pc = lambda v: circ.apply(Winv, S, v.reshape((3,) + wg.n), win).ravel()
         x0, i0 = solve.gmres(op, b, tol=1e-8, restart=400)
         x1, i1 = solve.fgmres(op, b, tol=1e-8, restart=400, precond=pc)
         assert i0.converged and i1.converged
@@ -154,3 +157,67 @@ def test_single_frequency_block_matches_the_fft_of_all_blocks():
     What = np.fft.fft(W, axis=0)                  # library DFT, independent of the oracle's FFT
     for f in (0, 1, 4):
         assert np.allclose(circ.frequency_block(table, chi, S, f), What[f], atol=1e-13, rtol=0)
+
+
+def test_smooth_lengths_and_windows():
+    assert [circ.smooth_length(n) for n in (1, 7, 8, 59, 97, 472, 625, 832)] == [1, 8, 8, 60, 100, 480, 625, 864]
+    chi = np.zeros((2, 2, 12), dtype=np.complex128)
+    chi[0, 1, 3:9] = 1.5
+    assert circ.support_window(chi) == (3, 6)
+    chi = np.zeros((2, 2, 10), dtype=np.complex128)
+    chi[1, 0, 3:10] = 1.0                     # extent 7 -> P = 8, shifted to fit: z0 = 2
+    assert circ.support_window(chi) == (2, 8)
+    chi = np.zeros((2, 2, 7), dtype=np.complex128)
+    chi[0, 0, :] = 1.0                        # extent 7 -> 8 > n3: the whole grid
+    assert circ.support_window(chi) == (0, 7)
+    assert circ.support_window(np.zeros((2, 2, 5))) == (0, 5)
+
+
+def test_window_blocks_satisfy_normal_equations_and_apply_is_identity_outside():
+    """Contrast on slices 3..8 of 12 (window (3, 6)): the blocks are the Frobenius fit of
+    the dense operator restricted to S x window, and W^{-1} leaves other voxels alone."""
+    n = (3, 2, 12)
+    table = green.green_table(n, KAPPA)
+    chi = np.zeros(n, dtype=np.complex128)
+    chi[0, 0, 3:9] = 2.0 + 0.3j * np.arange(6)
+    chi[1, 1, 4:9] = 1.5
+    S = circ.support_columns(chi)
+    win = circ.support_window(chi)
+    assert win == (3, 6)
+    P, m = win[1], 3 * len(S)
+    perm = _support_perm(n, S, win)
+    As = mv.dense_A(table, chi)[np.ix_(perm, perm)]
+    W = circ.optimal_blocks(table, chi, S)
+    assert W.shape == (P, m, m)
+    for k in range(P):
+        acc = sum(As[i * m:(i + 1) * m, ((i - k) % P) * m:(((i - k) % P) + 1) * m] for i in range(P))
+        assert np.allclose(acc / P, W[k], atol=1e-14, rtol=0)
+    r = RNG.standard_normal((3,) + n) + 1j * RNG.standard_normal((3,) + n)
+    z = circ.apply(circ.spectrum_inverse(W), S, r, win)
+    outside = np.ones(3 * np.prod(n), dtype=bool)
+    outside[perm] = False
+    assert np.array_equal(z.ravel()[outside], r.ravel()[outside])
+    zs = np.linalg.solve(circ.block_circulant_dense(W), r.ravel()[perm])
+    assert np.allclose(z.ravel()[perm], zs, atol=1e-12, rtol=0)
+
+
+def test_background_slices_do_not_dilute_the_preconditioner():
+    """A guide whose core stops short of both grid ends converges as fast as the same
+    core filling the grid (the window drops the background slices)."""
+    its = []
+    for n3, core_z in ((40, (0, 40)), (52, (6, 46))):
+        wg = inputs.Waveguide(n=(6, 6, n3), h=0.05, core_x=(1, 5), core_y=(2, 4), core_z=core_z, n_abs=8,
+                              d=2, sigma_max=2.0)
+        kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+        table = green.green_table(wg.n, kap)
+        chi = mv.contrast(wg.eps(), wg.eps_b)
+        op = mv.Operator(table, chi)
+        S = circ.support_columns(chi)
+        win = circ.support_window(chi)
+        Winv = circ.spectrum_inverse(circ.optimal_blocks(table, chi, S))
+        b = mv.rhs_from_field(wg.eps(), wg.eps_b, inputs.gaussian_rhs(wg.n, 2), wg.h).ravel()
+        pc = lambda v: circ.apply(Winv, S, v.reshape((3,) + wg.n), win).ravel()
+        x, info = solve.fgmres(op, b, tol=1e-8, restart=400, precond=pc)
+        assert info.converged
+        its.append(info.iters)
+    assert its[1] <= its[0] + 2, its
