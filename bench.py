@@ -286,6 +286,15 @@ def main():
             "unknowns_total": fam["unknowns"], "max_rel_res_fp64": fam["max_rel_res"],
             "reflection_slopes": fam["slopes"], "predicted_slopes": {str(d): -2 * (d + 1) for d in range(4)},
             "reflection": fam["reflection"]}
+        famc = experiments.run_family(precision=3, restart=30)
+        out["batched_family_circulant"] = {
+            "workload": "the same 64 systems, FP64 FGMRES preconditioned by each plan's block circulant",
+            "solve_seconds": round(famc["solve_seconds"], 3),
+            "preconditioner_seconds": round(famc["preconditioner_seconds"], 3),
+            "max_rel_res_fp64": famc["max_rel_res"], "max_outer_iters": max(famc["outer_iters"]),
+            "reflection_slopes": famc["slopes"],
+            "speedup_vs_mixed_incl_setup": round(fam["solve_seconds"] /
+                                                 (famc["solve_seconds"] + famc["preconditioner_seconds"]), 3)}
 
     if not args.no_learned:
         out["learned_preconditioner"] = learned_comparison()

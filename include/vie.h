@@ -170,8 +170,11 @@ int vie_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol,
  * and a system that reaches tol is masked on the device for the rest of its
  * restart cycle.  opts->precision 0: GMRES(restart); 1: FP64 flexible
  * GMRES(restart) preconditioned by inner_restart FP32 GMRES steps (plans built
- * with VIE_WITH_FP32).  With opts->use_graph one restart cycle is captured as a
- * HIP graph and replayed.  rhs[s], x[s]: device, 3N_s values each, x[s] out
+ * with VIE_WITH_FP32); 3: FP64 flexible GMRES(restart) preconditioned by each
+ * plan's block circulant (vie_circulant_build on every plan first; systems of
+ * one plan share it).  With opts->use_graph one restart cycle is captured as a
+ * HIP graph and replayed (precisions 0 and 1; precision 3 chooses the systems to
+ * precondition on the host each cycle and runs eagerly).  rhs[s], x[s]: device, 3N_s values each, x[s] out
  * (in with use_x0).  infos: host array of count entries or NULL.  Runs on a
  * stream of its own after synchronising the first plan's stream; returns
  * synchronised.  Returns VIE_OK when every system converged, else the first
@@ -187,20 +190,24 @@ int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* rhs, vie_c12
  * I - M_eps N in the Frobenius norm, after Chan and Olkin's preconditioners for
  * Toeplitz-block matrices; the paper's conclusion allows a circulant
  * approximation on one or more of the three Toeplitz levels).  This version
- * takes the circulant along the third axis (the long guide axis, n3 slices)
- * and keeps each cross-section block dense on the support S of the contrast
- * (the voxel columns (i1, i2) where chi is non-zero on some slice; m = 3|S|):
+ * takes the circulant along the third axis (the long guide axis) and keeps
+ * each cross-section block dense, on the support of the contrast: the voxel
+ * columns S where chi is non-zero on some slice (m = 3|S|) and a window of P
+ * slices from z0 that covers every slice where chi is non-zero on S (P the
+ * smallest length >= that extent with prime factors 2, 3, 5, at most n3;
+ * z0 the first such slice, moved down if the window would leave the grid):
  *
- *   W_k = delta_k0 I - (1/n3) [ U_k N_k + (U_0 - U_k) N_{k - n3} ],
- *   U_k = diag over S of sum_{i3 >= k} chi(i1, i2, i3),
+ *   W_k = delta_k0 I - (1/P) [ U_k N_k + (U_0 - U_k) N_{k - P} ],
+ *   U_k = diag over S of sum_{i >= k} chi(i1, i2, z0 + i),
  *
- * with N_k the m x m block of N between slices k apart.  Voxels outside S keep
- * the identity.  The DFT along the slices turns W into n3 dense m x m blocks,
+ * with N_k the m x m block of N between slices k apart.  Voxels outside S x
+ * window keep the identity.  The DFT along the window turns W into P dense
+ * m x m blocks,
  * which are inverted once (FP64 Gauss-Jordan with partial pivoting on the
  * device); the inverses are kept in FP32 (flags 0) or FP64 (VIE_CIRC_FP64).
  *
  * vie_circulant_build: for the plan's current contrast (set_contrast first; a
- *   later set_contrast releases it).  Limits: m <= 2048, and 2 n3 m^2 * 16 bytes
+ *   later set_contrast releases it).  Limits: m <= 2048, and 2 P m^2 * 16 bytes
  *   of device memory during set-up (VIE_ENOMEM otherwise).  VIE_ENUMERIC if a
  *   frequency block is singular.  info (host, may be NULL) receives the sizes,
  *   the device bytes of the kept inverses and the set-up time.  Synchronises.
@@ -212,7 +219,8 @@ enum { VIE_CIRC_FP32 = 0, VIE_CIRC_FP64 = 1 };
 typedef struct {
   int support_columns;   /* |S| */
   int block_size;        /* m = 3 |S| */
-  int blocks;            /* n3 (0 when S is empty: W = I) */
+  int blocks;            /* P, the window length (0 when S is empty: W = I) */
+  int first_slice;       /* z0 */
   int fp64;              /* 1: inverse blocks kept in FP64 */
   size_t bytes;          /* device bytes of the inverse blocks */
   double seconds;        /* set-up wall time */

@@ -488,6 +488,9 @@ struct vie_batch_s {
   BatchLevel<float> inner;
   PassSet p64, p32;
   bool mixed;
+  bool circ_tier = false;         // FP64 FGMRES preconditioned by each plan's block circulant
+  std::vector<Circ*> circ;        // per system (systems of one plan share it)
+  std::vector<int> on;            // host copy of the cycle flags
   std::vector<void*> allocs;
   hipGraphExec_t graph = nullptr;
   std::string err;
@@ -726,8 +729,17 @@ hipError_t enqueue_cycle(vie_batch_s* B, BatchLevel<T>& L, PassSet& PS, int) {
   hipError_t e;
   hipLaunchKernelGGL(k_b_init, dim3((L.nsys + 63) / 64), dim3(64), 0, s, L.d, L.nsys, L.m);
   for (int j = 0; j < L.m; ++j) {
-    if (L.flex) {
+    if (L.flex && B->mixed) {
       if ((e = enqueue_inner(B, j))) return e;
+    } else if (L.flex && B->circ_tier) {
+      // Z_j = W^{-1} V_j for the systems active in this cycle, one after the other
+      // on the batch stream (systems that share a plan share its work buffers)
+      for (int i = 0; i < L.nsys; ++i) {
+        if (!B->on[i]) continue;
+        const KDesc& D = L.h[i];
+        if ((e = circ_apply(B->circ[i], (const double2*)D.V + (long)j * D.n, (double2*)D.Z + (long)j * D.n, s)))
+          return e;
+      }
     }
     if ((e = batch_matvec<T>(B, PS, L, false, j))) return e;
     const int g = grid_for(L.ctotal);
@@ -762,7 +774,11 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
   vie_batch_s B;
   B.nsys = count;
   B.sp.resize(count);
+  if (o.precision < 0 || o.precision > 3 || o.precision == 2) return VIE_EINVAL;
   B.mixed = o.precision == 1;
+  B.circ_tier = o.precision == 3;
+  if (B.circ_tier) o.use_graph = 0;   // the active set is chosen on the host per cycle
+  B.circ.assign(count, nullptr);
   std::vector<long> n(count);
   for (int s = 0; s < count; ++s) {
     SysPlan& P = B.sp[s];
@@ -774,6 +790,7 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
     if (rc) return rc;
     if (!hc) return VIE_ESTATE;
     if (B.mixed && !P.goct32) return VIE_ESTATE;
+    if (B.circ_tier && !(B.circ[s] = plan_circ(plans[s]))) return VIE_ESTATE;
     if (s == 0) user_stream = st;
     n[s] = 3 * P.g.N;
   }
@@ -825,7 +842,7 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
     }
   }
   BTRY(hipHostMalloc(&hflags, sizeof(int) * count * 4 + sizeof(double) * count * 4, hipHostMallocDefault));
-  BTRY(build_level<double>(B.outer, n, o.restart, B.mixed, tol, bptr, xptr, act, nullptr));
+  BTRY(build_level<double>(B.outer, n, o.restart, B.mixed || B.circ_tier, tol, bptr, xptr, act, nullptr));
   if (B.mixed) {
     std::vector<const void*> ib(count);
     std::vector<void*> ix(count);
@@ -881,6 +898,7 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
       nact += on[i];
     }
     if (nact == 0 || status == VIE_ENUMERIC) break;
+    B.on = on;
     BTRY(hipMemcpyAsync(act, on.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
     // V_0 = r / beta for the active systems
     hipLaunchKernelGGL((k_b_scale<double>), dim3(grid_for(O.ctotal)), dim3(kT), 0, s, O.d, O.d_cpre, count, O.ctotal,

@@ -1,16 +1,18 @@
 // Block-circulant preconditioner of I - M_eps N along the guide axis
 // (Section V-D; Chan and Olkin's construction for Toeplitz-block matrices).
 //
-// Restricted to the cross-section support S of the contrast (|S| voxel
-// columns, m = 3|S| unknowns per slice), the operator has blocks
-// A_{ij} = delta_ij I - D_i N_{i-j} between slices i and j.  The block
+// Restricted to the support of the contrast -- the voxel columns S where chi
+// is non-zero on some slice (m = 3|S| unknowns per slice) and a window of P
+// slices from z0 covering every slice where it is non-zero (P the smallest
+// 2,3,5-smooth length >= that extent, at most n3) -- the operator has blocks
+// A_{ij} = delta_ij I - D_i N_{i-j} between window slices i and j.  The block
 // circulant nearest in the Frobenius norm averages each wrapped diagonal:
 //
-//   W_k = delta_k0 I - (1/n3) [ U_k N_k + (U_0 - U_k) N_{k-n3} ],
-//   U_k = diag(sum_{i >= k} chi(p, i))  (suffix sums of the contrast),
+//   W_k = delta_k0 I - (1/P) [ U_k N_k + (U_0 - U_k) N_{k-P} ],
+//   U_k = diag(sum_{i >= k} chi(p, z0 + i))  (suffix sums of the contrast),
 //
-// and the DFT along the slices block-diagonalises it: W^ f = sum_k W_k w^{fk},
-// w = exp(-2 pi i / n3).  Every other voxel keeps the identity.
+// and the DFT along the window block-diagonalises it: W^ f = sum_k W_k w^{fk},
+// w = exp(-2 pi i / P).  Every other voxel keeps the identity.
 //
 // Set-up (FP64): the blocks W_k as n3-long sequences per matrix entry, a
 // mixed-radix Stockham FFT of every sequence, then a batched blocked
@@ -24,6 +26,7 @@
 // written straight back; voxels outside S are copied.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -48,6 +51,15 @@ struct Radices {
   int r[kMaxRadices];
 };
 
+int smooth_length(int n) {
+  for (int m = n < 1 ? 1 : n;; ++m) {
+    int v = m;
+    for (int p : {2, 3, 5})
+      while (v % p == 0) v /= p;
+    if (v == 1) return m;
+  }
+}
+
 Radices factor(int n) {
   Radices rd{};
   rd.n = n;
@@ -71,14 +83,14 @@ __device__ __forceinline__ int comp_index(int a, int b) {
   return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
 }
 
-// ---- W_k, stored as Wt[e][k] with e = col * m + row ------------------------
+// ---- W_k, stored as Wt[e][k] with e = col * m + row (k < P; table offsets < n3) ----
 __global__ __launch_bounds__(kThreads) void k_circ_blocks(double2* __restrict__ Wt, const double2* __restrict__ table,
                                                           const int2* __restrict__ S, const double2* __restrict__ ucum,
-                                                          int s, int n1, int n2, int n3, long total) {
+                                                          int s, int n1, int n2, int n3, int P, long total) {
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int k = (int)(idx % n3);
-  const long e = idx / n3;
+  const int k = (int)(idx % P);
+  const long e = idx / P;
   const int m = 3 * s;
   const int row = (int)(e % m), col = (int)(e / m);
   const int a = row / s, p = row % s, b = col / s, q = col % s;
@@ -88,14 +100,14 @@ __global__ __launch_bounds__(kThreads) void k_circ_blocks(double2* __restrict__ 
   if (d1 < 0 && ((a == 0) != (b == 0))) sg = -sg;   // parity of N^{ab} along axis 1
   if (d2 < 0 && ((a == 1) != (b == 1))) sg = -sg;   // along axis 2
   const long base = (((long)comp_index(a, b) * n1 + abs(d1)) * n2 + abs(d2)) * n3;
-  const double2 up = ucum[(long)p * (n3 + 1) + k];
+  const double2 up = ucum[(long)p * (P + 1) + k];
   double2 acc = cmul(up, table[base + k]);
   if (k > 0) {
-    const double2 tot = ucum[(long)p * (n3 + 1)];
-    const double s3 = ((a == 2) != (b == 2)) ? -1.0 : 1.0;   // offset k - n3 < 0 along axis 3
-    acc = cadd(acc, cscale(cmul(csub(tot, up), table[base + n3 - k]), s3));
+    const double2 tot = ucum[(long)p * (P + 1)];
+    const double s3 = ((a == 2) != (b == 2)) ? -1.0 : 1.0;   // offset k - P < 0 along axis 3
+    acc = cadd(acc, cscale(cmul(csub(tot, up), table[base + P - k]), s3));
   }
-  double2 w = cscale(acc, -sg / n3);
+  double2 w = cscale(acc, -sg / P);
   if (k == 0 && row == col) w.x += 1.0;
   Wt[idx] = w;
 }
@@ -104,6 +116,8 @@ __global__ __launch_bounds__(kThreads) void k_circ_blocks(double2* __restrict__ 
 // Stage with radix R after Ns = product of earlier radices: output q of task
 // j < n/R is sum_r x[j + r n/R] w^{r ((j mod Ns) n/(Ns R) + q n/R)}, written to
 // (j / Ns) Ns R + (j mod Ns) + q Ns.  Natural order after the last stage.
+// Window slices t < P of a support row start at z0 of a voxel column; the
+// transform rows are [seq][P].
 template <typename T>
 struct IoVoxelIn {   // FP64 voxel vector (through the support map) -> rows[seq][t]
   const double2* r;
@@ -111,13 +125,13 @@ struct IoVoxelIn {   // FP64 voxel vector (through the support map) -> rows[seq]
   const int* col;
   int s;
   long n12;
-  int n3;
+  int n3, z0, P;
   __device__ cx<T> load(long seq, int t) const {
     const int a = (int)(seq / s), p = (int)(seq % s);
-    const double2 v = r[((long)a * n12 + col[p]) * n3 + t];
+    const double2 v = r[((long)a * n12 + col[p]) * n3 + z0 + t];
     return cx<T>{(T)v.x, (T)v.y};
   }
-  __device__ void store(long seq, int t, cx<T> v) const { rows[seq * n3 + t] = v; }
+  __device__ void store(long seq, int t, cx<T> v) const { rows[seq * P + t] = v; }
 };
 
 template <typename T>
@@ -127,41 +141,43 @@ struct IoVoxelOut {  // rows[seq][t] -> FP64 voxel vector (through the support m
   const int* col;
   int s;
   long n12;
-  int n3;
-  __device__ cx<T> load(long seq, int t) const { return rows[seq * n3 + t]; }
+  int n3, z0, P;
+  __device__ cx<T> load(long seq, int t) const { return rows[seq * P + t]; }
   __device__ void store(long seq, int t, cx<T> v) const {
     const int a = (int)(seq / s), p = (int)(seq % s);
-    z[((long)a * n12 + col[p]) * n3 + t] = double2{(double)v.x, (double)v.y};
+    z[((long)a * n12 + col[p]) * n3 + z0 + t] = double2{(double)v.x, (double)v.y};
   }
 };
 
 template <typename T>
-struct IoRowsIn {    // FP64 support-compressed vector rows[seq][t] -> rows of T
+struct IoRowsIn {    // FP64 support-compressed vector (rows of n3 slices) -> rows of T
   const double2* r;
   cx<T>* rows;
-  int n3;
+  int n3, z0, P;
   __device__ cx<T> load(long seq, int t) const {
-    const double2 v = r[seq * n3 + t];
+    const double2 v = r[seq * n3 + z0 + t];
     return cx<T>{(T)v.x, (T)v.y};
   }
-  __device__ void store(long seq, int t, cx<T> v) const { rows[seq * n3 + t] = v; }
+  __device__ void store(long seq, int t, cx<T> v) const { rows[seq * P + t] = v; }
 };
 
 template <typename T>
 struct IoRowsOut {   // rows of T -> FP64 support-compressed vector
   const cx<T>* rows;
   double2* z;
-  int n3;
-  __device__ cx<T> load(long seq, int t) const { return rows[seq * n3 + t]; }
-  __device__ void store(long seq, int t, cx<T> v) const { z[seq * n3 + t] = double2{(double)v.x, (double)v.y}; }
+  int n3, z0, P;
+  __device__ cx<T> load(long seq, int t) const { return rows[seq * P + t]; }
+  __device__ void store(long seq, int t, cx<T> v) const {
+    z[seq * n3 + z0 + t] = double2{(double)v.x, (double)v.y};
+  }
 };
 
 struct IoBlocks {    // Wt[e][k] -> What[f][e]
   const double2* Wt;
   double2* Wh;
   long m2;
-  int n3;
-  __device__ double2 load(long seq, int t) const { return Wt[seq * n3 + t]; }
+  int P;
+  __device__ double2 load(long seq, int t) const { return Wt[seq * P + t]; }
   __device__ void store(long seq, int t, double2 v) const { Wh[(long)t * m2 + seq] = v; }
 };
 
@@ -441,12 +457,13 @@ hipError_t launch_update(double2* A, int m, int j, const int* piv, int n3, hipSt
 
 struct Circ {
   int s = 0, m = 0, n1 = 0, n2 = 0, n3 = 0;
+  int z0 = 0, P = 0;           // slice window of the circulant
   bool fp64 = false;
   int* col = nullptr;          // voxel column i1 * n2 + i2 of each support column
-  double2* tw = nullptr;       // exp(-2 pi i t / n3)
-  double2* inv64 = nullptr;    // n3 blocks, column-major m x m
+  double2* tw = nullptr;       // exp(-2 pi i t / P)
+  double2* inv64 = nullptr;    // P blocks, column-major m x m
   float2* inv32 = nullptr;
-  void* xhat = nullptr;        // m x n3 rows of the apply precision
+  void* xhat = nullptr;        // m x P rows of the apply precision
   void* yhat = nullptr;
   Radices rd{};
   CircInfo info{};
@@ -514,29 +531,49 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
     return finish(VIE_OK, "");
   }
   if (m > 2048) return finish(VIE_EINVAL, "contrast support wider than 682 voxel columns");
+  // slice window: every slice where chi is non-zero on S, grown to a 2,3,5-smooth length
+  int first = n3, last = -1;
+  for (int p = 0; p < c->s; ++p) {
+    const double2* z = chi.data() + (long)cols[p] * n3;
+    for (int k = 0; k < n3; ++k)
+      if (z[k].x != 0.0 || z[k].y != 0.0) {
+        first = std::min(first, k);
+        last = std::max(last, k);
+      }
+  }
+  int P = smooth_length(last - first + 1);
+  int z0 = std::min(first, n3 - P);
+  if (P > n3) {
+    P = n3;
+    z0 = 0;
+  }
+  c->z0 = z0;
+  c->P = P;
+  c->info.z0 = z0;
+  c->info.P = P;
   const long m2 = (long)m * m;
-  const size_t blk = sizeof(double2) * (size_t)n3 * m2;
+  const size_t blk = sizeof(double2) * (size_t)P * m2;
   size_t free_b = 0, total_b = 0;
   CTRY(hipMemGetInfo(&free_b, &total_b));
   const size_t need = 2 * blk + (fp64 ? 0 : blk / 2);
   if (need > free_b / 10 * 9) return finish(VIE_ENOMEM, "preconditioner blocks exceed free device memory");
-  c->rd = factor(n3);
-  // suffix sums of the contrast per support column: U_k, k = 0..n3
-  std::vector<double2> ucum((size_t)c->s * (n3 + 1));
+  c->rd = factor(P);
+  // suffix sums of the contrast over the window per support column: U_k, k = 0..P
+  std::vector<double2> ucum((size_t)c->s * (P + 1));
   for (int p = 0; p < c->s; ++p) {
-    const double2* z = chi.data() + (long)cols[p] * n3;
+    const double2* z = chi.data() + (long)cols[p] * n3 + z0;
     double ax = 0, ay = 0;
-    double2* u = ucum.data() + (size_t)p * (n3 + 1);
-    u[n3] = double2{0, 0};
-    for (int k = n3 - 1; k >= 0; --k) {
+    double2* u = ucum.data() + (size_t)p * (P + 1);
+    u[P] = double2{0, 0};
+    for (int k = P - 1; k >= 0; --k) {
       ax += z[k].x;
       ay += z[k].y;
       u[k] = double2{ax, ay};
     }
   }
-  std::vector<double2> tw(n3);
-  for (int t = 0; t < n3; ++t) {
-    const long double a = -2.0L * 3.14159265358979323846264338327950288L * t / n3;
+  std::vector<double2> tw(P);
+  for (int t = 0; t < P; ++t) {
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * t / P;
     tw[t] = double2{(double)std::cos(a), (double)std::sin(a)};
   }
   int2* S_d = nullptr;
@@ -547,7 +584,7 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
   int* piv = nullptr;
   int* bad = nullptr;
   CTRY(hipMalloc(&c->col, sizeof(int) * c->s));
-  CTRY(hipMalloc(&c->tw, sizeof(double2) * n3));
+  CTRY(hipMalloc(&c->tw, sizeof(double2) * P));
   CTRY(hipMalloc(&S_d, sizeof(int2) * c->s));
   tmp.push_back(S_d);
   CTRY(hipMalloc(&ucum_d, sizeof(double2) * ucum.size()));
@@ -557,27 +594,27 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
   CTRY(hipMalloc(&Wt, blk));
   tmp.push_back(Wt);
   CTRY(hipMemcpyAsync(c->col, cols.data(), sizeof(int) * c->s, hipMemcpyHostToDevice, s));
-  CTRY(hipMemcpyAsync(c->tw, tw.data(), sizeof(double2) * n3, hipMemcpyHostToDevice, s));
+  CTRY(hipMemcpyAsync(c->tw, tw.data(), sizeof(double2) * P, hipMemcpyHostToDevice, s));
   CTRY(hipMemcpyAsync(S_d, S.data(), sizeof(int2) * c->s, hipMemcpyHostToDevice, s));
   CTRY(hipMemcpyAsync(ucum_d, ucum.data(), sizeof(double2) * ucum.size(), hipMemcpyHostToDevice, s));
   CTRY(hipMemcpyAsync(table_d, table, sizeof(double2) * 6 * g.N, hipMemcpyHostToDevice, s));
-  const long total = (long)n3 * m2;
+  const long total = (long)P * m2;
   hipLaunchKernelGGL(k_circ_blocks, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, Wt,
-                     table_d, S_d, ucum_d, c->s, g.n1, g.n2, n3, total);
+                     table_d, S_d, ucum_d, c->s, g.n1, g.n2, n3, P, total);
   CTRY(hipGetLastError());
   CTRY(hipMalloc(&Wh, blk));
   tmp.push_back(Wh);
   const size_t wh_slot = tmp.size() - 1;
   CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, false, IoBlocks>,
-                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(3 * (size_t)n3 * sizeof(double2))));
-  CTRY(launch_fft<double, false>(c->rd, c->tw, IoBlocks{Wt, Wh, m2, n3}, m2, 1.0, s));
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(3 * (size_t)P * sizeof(double2))));
+  CTRY(launch_fft<double, false>(c->rd, c->tw, IoBlocks{Wt, Wh, m2, P}, m2, 1.0, s));
   CTRY(hipStreamSynchronize(s));
   CTRY(hipFree(Wt));
   tmp[3] = nullptr;
   CTRY(hipFree(table_d));
   tmp[2] = nullptr;
   // Gauss-Jordan on every frequency block
-  CTRY(hipMalloc(&piv, sizeof(int) * (size_t)n3 * m));
+  CTRY(hipMalloc(&piv, sizeof(int) * (size_t)P * m));
   tmp.push_back(piv);
   CTRY(hipMalloc(&bad, sizeof(int)));
   tmp.push_back(bad);
@@ -586,13 +623,13 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
   const size_t panel_lds = sizeof(double2) * (size_t)m * nb;
   CTRY(hipFuncSetAttribute((const void*)k_gj_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)panel_lds));
   for (int j = 0; j < m; j += nb) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(n3), dim3(kThreads), panel_lds, s, Wh, m, j, nb, piv, bad);
+    hipLaunchKernelGGL(k_gj_panel, dim3(P), dim3(kThreads), panel_lds, s, Wh, m, j, nb, piv, bad);
     CTRY(hipGetLastError());
-    if (nb == 16) CTRY(launch_update<16>(Wh, m, j, piv, n3, s));
-    else if (nb == 8) CTRY(launch_update<8>(Wh, m, j, piv, n3, s));
-    else CTRY(launch_update<4>(Wh, m, j, piv, n3, s));
+    if (nb == 16) CTRY(launch_update<16>(Wh, m, j, piv, P, s));
+    else if (nb == 8) CTRY(launch_update<8>(Wh, m, j, piv, P, s));
+    else CTRY(launch_update<4>(Wh, m, j, piv, P, s));
   }
-  hipLaunchKernelGGL(k_gj_unscramble, dim3((m + kThreads - 1) / kThreads, n3), dim3(kThreads), 0, s, Wh, m, piv);
+  hipLaunchKernelGGL(k_gj_unscramble, dim3((m + kThreads - 1) / kThreads, P), dim3(kThreads), 0, s, Wh, m, piv);
   CTRY(hipGetLastError());
   int bad_h = 0;
   CTRY(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -603,15 +640,15 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
     c->inv64 = Wh;
     tmp[wh_slot] = nullptr;
   } else {
-    CTRY(hipMalloc(&c->inv32, sizeof(float2) * (size_t)n3 * m2));
+    CTRY(hipMalloc(&c->inv32, sizeof(float2) * (size_t)P * m2));
     hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, Wh,
                        c->inv32, total);
     CTRY(hipGetLastError());
     CTRY(hipStreamSynchronize(s));
   }
-  CTRY(hipMalloc(&c->xhat, es * (size_t)m * n3));
-  CTRY(hipMalloc(&c->yhat, es * (size_t)m * n3));
-  const int lds_need = (int)(3 * (size_t)n3 * es);
+  CTRY(hipMalloc(&c->xhat, es * (size_t)m * P));
+  CTRY(hipMalloc(&c->yhat, es * (size_t)m * P));
+  const int lds_need = (int)(3 * (size_t)P * es);
   const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
   if (fp64) {
     CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, false, IoVoxelIn<double>>, attr, lds_need));
@@ -624,7 +661,7 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
     CTRY(hipFuncSetAttribute((const void*)k_circ_fft<float, false, IoRowsIn<float>>, attr, lds_need));
     CTRY(hipFuncSetAttribute((const void*)k_circ_fft<float, true, IoRowsOut<float>>, attr, lds_need));
   }
-  c->info.bytes = (fp64 ? sizeof(double2) : sizeof(float2)) * (size_t)n3 * m2;
+  c->info.bytes = (fp64 ? sizeof(double2) : sizeof(float2)) * (size_t)P * m2;
   c->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = c->info;
   return finish(VIE_OK, "");
@@ -639,10 +676,10 @@ hipError_t apply_t(Circ* c, const cx<T>* inv, const IN& in, const OUT& out, hipS
   auto* yh = reinterpret_cast<cx<T>*>(c->yhat);
   hipError_t e = launch_fft<T, false>(c->rd, c->tw, in, c->m, 1.0, s);
   if (e) return e;
-  hipLaunchKernelGGL(k_circ_gemv<T>, dim3((c->m + kGemvRows - 1) / kGemvRows, c->n3), dim3(kThreads), 0, s, inv, xh,
-                     yh, c->m, c->n3);
+  hipLaunchKernelGGL(k_circ_gemv<T>, dim3((c->m + kGemvRows - 1) / kGemvRows, c->P), dim3(kThreads), 0, s, inv, xh,
+                     yh, c->m, c->P);
   if ((e = hipGetLastError())) return e;
-  return launch_fft<T, true>(c->rd, c->tw, out, c->m, 1.0 / c->n3, s);
+  return launch_fft<T, true>(c->rd, c->tw, out, c->m, 1.0 / c->P, s);
 }
 
 template <typename T>
@@ -650,15 +687,15 @@ hipError_t apply_voxels(Circ* c, const cx<T>* inv, const double2* r, double2* z,
   const long n12 = (long)c->n1 * c->n2;
   auto* xh = reinterpret_cast<cx<T>*>(c->xhat);
   auto* yh = reinterpret_cast<cx<T>*>(c->yhat);
-  return apply_t<T>(c, inv, IoVoxelIn<T>{r, xh, c->col, c->s, n12, c->n3},
-                    IoVoxelOut<T>{yh, z, c->col, c->s, n12, c->n3}, s);
+  return apply_t<T>(c, inv, IoVoxelIn<T>{r, xh, c->col, c->s, n12, c->n3, c->z0, c->P},
+                    IoVoxelOut<T>{yh, z, c->col, c->s, n12, c->n3, c->z0, c->P}, s);
 }
 
 template <typename T>
 hipError_t apply_rows(Circ* c, const cx<T>* inv, const double2* r, double2* z, hipStream_t s) {
   auto* xh = reinterpret_cast<cx<T>*>(c->xhat);
   auto* yh = reinterpret_cast<cx<T>*>(c->yhat);
-  return apply_t<T>(c, inv, IoRowsIn<T>{r, xh, c->n3}, IoRowsOut<T>{yh, z, c->n3}, s);
+  return apply_t<T>(c, inv, IoRowsIn<T>{r, xh, c->n3, c->z0, c->P}, IoRowsOut<T>{yh, z, c->n3, c->z0, c->P}, s);
 }
 }  // namespace
 
@@ -671,6 +708,10 @@ hipError_t circ_apply(Circ* c, const double2* r, double2* z, hipStream_t s) {
 
 hipError_t circ_apply_rows(Circ* c, const double2* r, double2* z, hipStream_t s) {
   if (c->s == 0) return hipSuccess;
+  if (c->P < c->n3) {   // slices outside the window keep the identity
+    const hipError_t e = hipMemcpyAsync(z, r, sizeof(double2) * 3 * (size_t)c->s * c->n3, hipMemcpyDeviceToDevice, s);
+    if (e) return e;
+  }
   return c->fp64 ? apply_rows<double>(c, c->inv64, r, z, s) : apply_rows<float>(c, c->inv32, r, z, s);
 }
 

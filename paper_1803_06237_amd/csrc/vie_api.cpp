@@ -496,6 +496,8 @@ int vie::plan_export(vie_plan_t p, Geom* g, Tune* t64, Tune* t32, void** U64, vo
   return VIE_OK;
 }
 
+vie::Circ* vie::plan_circ(vie_plan_t p) { return p ? p->circ : nullptr; }
+
 size_t vie::lds_budget(int device) {
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
@@ -993,7 +995,8 @@ int vie_circulant_build(vie_plan_t p, unsigned flags, vie_circulant_info* info) 
   if (info) {
     info->support_columns = ci.s;
     info->block_size = ci.m;
-    info->blocks = ci.s ? p->g.n3 : 0;
+    info->blocks = ci.s ? ci.P : 0;
+    info->first_slice = ci.z0;
     info->fp64 = ci.fp64;
     info->bytes = ci.bytes;
     info->seconds = ci.seconds;

@@ -100,6 +100,7 @@ struct CircInfo {
   int fp64;       // 1: inverse blocks kept in FP64
   size_t bytes;   // device bytes of the inverse blocks
   double seconds; // set-up wall time
+  int z0, P;      // slice window of the circulant
 };
 struct Circ;
 // Builds W^{-1} for the contrast chi64 (device, FP64) with the host Toeplitz table.
@@ -124,5 +125,7 @@ namespace vie {
 int plan_export(vie_plan_t p, Geom* g, Tune* t64, Tune* t32, void** U64, void** U32, void** goct64, void** goct32,
                 void** chi64, void** chi32, const void** tw64, const void** tw32, hipStream_t* stream,
                 int* has_contrast);
+// The plan's block-circulant preconditioner, or null when none is built.
+Circ* plan_circ(vie_plan_t p);
 
 }  // namespace vie

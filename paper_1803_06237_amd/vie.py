@@ -46,7 +46,8 @@ class SolveInfo(ctypes.Structure):
 
 class CirculantInfo(ctypes.Structure):
     _fields_ = [("support_columns", ctypes.c_int), ("block_size", ctypes.c_int), ("blocks", ctypes.c_int),
-                ("fp64", ctypes.c_int), ("bytes", ctypes.c_size_t), ("seconds", ctypes.c_double)]
+                ("first_slice", ctypes.c_int), ("fp64", ctypes.c_int), ("bytes", ctypes.c_size_t),
+                ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

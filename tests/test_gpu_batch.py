@@ -138,3 +138,25 @@ def test_long_guides_family_batch():
         r = p.residual(x, b)
         rel = (torch.linalg.norm(r) / torch.linalg.norm(b)).item()
         assert rel <= 1e-8 and abs(rel - info["rel_res_true"]) < 1e-12
+
+
+def test_batch_circulant_tier(systems):
+    """precision 3: each system's FGMRES preconditioned by its plan's block circulant;
+    solutions judged by the oracle, fewer iterations than plain GMRES."""
+    vie = _dev()
+    plans = [s[2] for s in systems]
+    for p in plans:
+        p.build_circulant()
+    bs = [torch.from_numpy(s[3]).cuda() for s in systems]
+    x0, i0, c0 = vie.solve_batch(plans, bs, tol=1e-8, restart=30, precision=0)
+    xs, infos, code = vie.solve_batch(plans, bs, tol=1e-8, restart=30, precision=3)
+    assert code == vie.VIE_OK, infos
+    for (wg, op, plan, b), x, info, info0 in zip(systems, xs, infos, i0):
+        rr = _rel(op, b, x.cpu().numpy())
+        print(wg.n, info["iters"], "vs plain", info0["iters"], rr)
+        assert info["status"] == 0 and rr <= 1.01e-8
+        assert info["iters"] < info0["iters"]
+    plans[0].set_contrast(torch.from_numpy(systems[0][0].eps()).cuda())       # releases its preconditioner
+    with pytest.raises(vie.VieError) as ei:
+        vie.solve_batch(plans, bs, tol=1e-8, restart=30, precision=3)
+    assert ei.value.code == vie.VIE_ESTATE

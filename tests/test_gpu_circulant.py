@@ -52,6 +52,11 @@ CASES = [
     ("ragged_7x5x129", lambda: _ragged_eps((7, 5, 129), 3)),
     ("ragged_9x4x20", lambda: _ragged_eps((9, 4, 20), 4)),
     ("one_slice_5x5x1", lambda: _guide((5, 5, 1), (1, 4), (2, 3), 0).eps()),
+    # core shorter than the grid: slice window (5, 40), and (8, 40) shifted to fit the end
+    ("gap_6x6x48", lambda: inputs.Waveguide(n=(6, 6, 48), h=0.05, core_x=(1, 5), core_y=(2, 4), core_z=(5, 43),
+                                            n_abs=6, d=2, sigma_max=2.0).eps()),
+    ("gap_end_6x5x48", lambda: inputs.Waveguide(n=(6, 5, 48), h=0.05, core_x=(2, 5), core_y=(1, 4),
+                                                core_z=(10, 47), n_abs=5, d=1, sigma_max=3.0).eps()),
 ]
 
 
@@ -61,7 +66,7 @@ def _oracle_apply(eps, h, r):
     chi = mv.contrast(eps, inputs.EPS_B)
     S = circ.support_columns(chi)
     Winv = circ.spectrum_inverse(circ.optimal_blocks(table, chi, S))
-    return circ.apply(Winv, S, r)
+    return circ.apply(Winv, S, r, circ.support_window(chi))
 
 
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
@@ -80,12 +85,17 @@ def test_apply_matches_oracle(name, make, fp64):
     zo = _oracle_apply(eps, h, r)
     err = np.max(np.abs(z - zo)) / np.max(np.abs(zo))
     print(name, info, "max rel err", err)
-    assert info["block_size"] == 3 * info["support_columns"] and info["blocks"] == n[2]
-    assert err <= (1e-11 if fp64 else 2e-5)
-    # outside the support the preconditioner is the identity, bit for bit
     chi = mv.contrast(eps, inputs.EPS_B)
+    z0, P = circ.support_window(chi)
+    assert info["block_size"] == 3 * info["support_columns"]
+    assert (info["first_slice"], info["blocks"]) == (z0, P)
+    assert err <= (1e-11 if fp64 else 2e-5)
+    # outside the support columns and outside the slice window the preconditioner is
+    # the identity, bit for bit
     outside = ~np.any(chi != 0, axis=2)
     assert np.array_equal(z[:, outside, :], r[:, outside, :])
+    assert np.array_equal(z[:, :, :, :z0], r[:, :, :, :z0])
+    assert np.array_equal(z[:, :, :, z0 + P:], r[:, :, :, z0 + P:])
 
 
 def test_no_contrast_is_the_identity():
@@ -171,6 +181,7 @@ def test_full_size_single_frequencies(long_guide, long_guide_blocks, fp64):
     print(info)
     s, n3 = len(S), wg.n[2]
     assert info["support_columns"] == s == 180
+    assert circ.support_window(mv.contrast(wg.eps(), wg.eps_b)) == (0, n3) == (info["first_slice"], info["blocks"])
     rng = np.random.default_rng(2)
     for f in FREQS:
         v = rng.standard_normal(3 * s) + 1j * rng.standard_normal(3 * s)
