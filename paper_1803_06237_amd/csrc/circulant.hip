@@ -298,17 +298,22 @@ __global__ __launch_bounds__(kThreads) void k_gj_panel(double2* __restrict__ A, 
     double2 d = P[jj * m + k];
     const double dd = d.x * d.x + d.y * d.y;
     const double2 ck = dd > 0.0 ? double2{d.x / dd, -d.y / dd} : double2{1.0, 0.0};
-    // rows r owned by this thread; pivot-row values read before the barrier
+    // rows r = threadIdx.x + t * kThreads owned by this thread (t compile-time, so
+    // the cache stays in registers); pivot-column values read before the barrier
     constexpr int kMaxRows = 2048 / kThreads;
     double2 fr[kMaxRows];
-    int nr = 0;
-    for (int r = threadIdx.x; r < m; r += blockDim.x) fr[nr++] = P[jj * m + r];
+#pragma unroll
+    for (int t = 0; t < kMaxRows; ++t) {
+      const int r = threadIdx.x + t * kThreads;
+      fr[t] = r < m ? P[jj * m + r] : double2{0.0, 0.0};
+    }
     __syncthreads();
     for (int c = 0; c < w; ++c) {
       const double2 rk = c == jj ? ck : cmul(P[c * m + k], ck);
-      int t = 0;
-      for (int r = threadIdx.x; r < m; r += blockDim.x, ++t) {
-        if (r == k) continue;
+#pragma unroll
+      for (int t = 0; t < kMaxRows; ++t) {
+        const int r = threadIdx.x + t * kThreads;
+        if (r >= m || r == k) continue;
         const double2 fv = fr[t];
         if (c == jj)
           P[c * m + r] = double2{-(fv.x * ck.x - fv.y * ck.y), -(fv.x * ck.y + fv.y * ck.x)};
@@ -327,22 +332,23 @@ __global__ __launch_bounds__(kThreads) void k_gj_panel(double2* __restrict__ A, 
   for (int i = threadIdx.x; i < w * m; i += blockDim.x) Af[(long)j * m + i] = P[i];
 }
 
-// Columns outside the panel, kGemvRows at a time: apply the panel's row swaps,
-// then A[:, c] = (rows of the panel zeroed) + T[:, panel] * A[panel rows, c].
+// Columns c in [cb, ce) outside the panel [j, j + w), 64 per workgroup: apply the
+// panel's row swaps, then A[:, c] = (rows of the panel zeroed) + T[:, panel] *
+// A[panel rows, c], with T the panel's in-place Gauss-Jordan columns.
 template <int NB>
 __global__ __launch_bounds__(kThreads) void k_gj_update(double2* __restrict__ A, int m, int j,
-                                                        const int* __restrict__ piv) {
+                                                        const int* __restrict__ piv, int cb, int ce) {
   __shared__ double2 B[NB][64];
   __shared__ int s_piv[NB];
   const long f = blockIdx.y;
   double2* Af = A + f * (long)m * m;
   const int w = min(NB, m - j);
-  const int c0 = blockIdx.x * 64;
+  const int c0 = cb + blockIdx.x * 64;
   if (threadIdx.x < w) s_piv[threadIdx.x] = piv[f * m + j + threadIdx.x];
   __syncthreads();
   if (threadIdx.x < 64) {
     const int c = c0 + threadIdx.x;
-    const bool own = c < m && (c < j || c >= j + w);
+    const bool own = c < ce && (c < j || c >= j + w);
     if (own) {
       double2* col = Af + (long)c * m;
       for (int jj = 0; jj < w; ++jj) {
@@ -359,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_gj_update(double2* __restrict__ A,
     }
   }
   __syncthreads();
-  const int ncol = min(64, m - c0);
+  const int ncol = min(64, ce - c0);
   for (int r = threadIdx.x; r < m; r += blockDim.x) {
     double2 tr[NB];
 #pragma unroll
@@ -448,9 +454,19 @@ hipError_t launch_fft(const Radices& rd, const double2* tw, const IO& io, long c
 }
 
 template <int NB>
-hipError_t launch_update(double2* A, int m, int j, const int* piv, int n3, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_update<NB>, dim3((m + 63) / 64, n3), dim3(kThreads), 0, s, A, m, j, piv);
+hipError_t launch_update(double2* A, int m, int j, const int* piv, int cb, int ce, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_update<NB>, dim3((ce - cb + 63) / 64, nblk), dim3(kThreads), 0, s, A, m, j, piv, cb, ce);
   return hipGetLastError();
+}
+
+hipError_t launch_update_w(int nbw, double2* A, int m, int j, const int* piv, int cb, int ce, int nblk,
+                           hipStream_t s) {
+  switch (nbw) {
+    case 32: return launch_update<32>(A, m, j, piv, cb, ce, nblk, s);
+    case 16: return launch_update<16>(A, m, j, piv, cb, ce, nblk, s);
+    case 8: return launch_update<8>(A, m, j, piv, cb, ce, nblk, s);
+    default: return launch_update<4>(A, m, j, piv, cb, ce, nblk, s);
+  }
 }
 
 }  // namespace
@@ -622,12 +638,18 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
   const int nb = m <= 600 ? 16 : (m <= 1200 ? 8 : 4);
   const size_t panel_lds = sizeof(double2) * (size_t)m * nb;
   CTRY(hipFuncSetAttribute((const void*)k_gj_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)panel_lds));
-  for (int j = 0; j < m; j += nb) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(P), dim3(kThreads), panel_lds, s, Wh, m, j, nb, piv, bad);
-    CTRY(hipGetLastError());
-    if (nb == 16) CTRY(launch_update<16>(Wh, m, j, piv, P, s));
-    else if (nb == 8) CTRY(launch_update<8>(Wh, m, j, piv, P, s));
-    else CTRY(launch_update<4>(Wh, m, j, piv, P, s));
+  // two-level panels: 2 nb columns at a time; each nb-column sub-panel is factored in
+  // LDS and applied to the other columns of the outer panel, then the outer panel's
+  // composite transformation goes to the rest of the matrix in one rank-2nb pass
+  const int nb2 = 2 * nb;
+  for (int J = 0; J < m; J += nb2) {
+    const int wJ = std::min(nb2, m - J);
+    for (int j = J; j < J + wJ; j += nb) {
+      hipLaunchKernelGGL(k_gj_panel, dim3(P), dim3(kThreads), panel_lds, s, Wh, m, j, nb, piv, bad);
+      CTRY(hipGetLastError());
+      if (wJ > nb) CTRY(launch_update_w(nb, Wh, m, j, piv, J, J + wJ, P, s));
+    }
+    CTRY(launch_update_w(nb2, Wh, m, J, piv, 0, m, P, s));
   }
   hipLaunchKernelGGL(k_gj_unscramble, dim3((m + kThreads - 1) / kThreads, P), dim3(kThreads), 0, s, Wh, m, piv);
   CTRY(hipGetLastError());
