@@ -249,8 +249,8 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
   if (!e) e = hipMalloc(&y, bytes);
   if (!e) e = hipMemsetAsync(x, 0, bytes, s);
   if (!e && t->z4) {
-    int opts[4];
-    const int n = z4_pencil_options<T>(g.M3, opts, 4);
+    int opts[8];
+    const int n = z4_pencil_options<T>(g.M3, opts, 8);
     float best = INFINITY;
     int bestp = 0;
     for (int i = 0; i < n && !e; ++i) {
@@ -951,9 +951,9 @@ int vie_get_tune(vie_plan_t p, int precision, int* xy_variant, int* z_pencils) {
   if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
   if (precision != 0 && precision != 1) return fail(p, VIE_EINVAL, "precision must be 0 or 1");
   const Tune& t = precision == 0 ? p->t64 : p->t32;
-  int opts[4];
-  const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 4)
-                               : z4_pencil_options<float>(p->g.M3, opts, 4);
+  int opts[8];
+  const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 8)
+                               : z4_pencil_options<float>(p->g.M3, opts, 8);
   if (xy_variant) *xy_variant = (p->g.M1 == 64 && p->g.M2 == 64) ? t.xyv : -1;
   if (z_pencils) *z_pencils = t.z4 && n ? (t.zp ? t.zp : opts[0]) : 0;
   return VIE_OK;
@@ -963,9 +963,9 @@ int vie_set_tune(vie_plan_t p, int precision, int xy_variant, int z_pencils) {
   if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
   if (precision != 0 && precision != 1) return fail(p, VIE_EINVAL, "precision must be 0 or 1");
   if (xy_variant != 0 && xy_variant != 1) return fail(p, VIE_EINVAL, "xy_variant must be 0 or 1");
-  int opts[4];
-  const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 4)
-                               : z4_pencil_options<float>(p->g.M3, opts, 4);
+  int opts[8];
+  const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 8)
+                               : z4_pencil_options<float>(p->g.M3, opts, 8);
   Tune& t = precision == 0 ? p->t64 : p->t32;
   if (z_pencils != 0) {
     bool ok = false;

@@ -185,13 +185,13 @@ struct ZShape {
 template <typename T>
 int z4_pencil_options(int M3, int* out, int cap) {
   const bool dbl = sizeof(T) == 8;
-  int opts[4] = {0, 0, 0, 0}, n = 0;
+  int opts[6] = {0, 0, 0, 0, 0, 0}, n = 0;
   if (M3 == 512) {                                   // A = 16
-    if (dbl) { opts[0] = 8; opts[1] = 4; opts[2] = 16; n = 3; }
-    else { opts[0] = 16; opts[1] = 8; n = 2; }
+    if (dbl) { opts[0] = 8; opts[1] = 4; opts[2] = 16; opts[3] = 2; n = 4; }
+    else { opts[0] = 16; opts[1] = 8; opts[2] = 4; opts[3] = 2; n = 4; }
   } else if (M3 == 1024) {                           // A = 32
     if (dbl) { opts[0] = 4; opts[1] = 2; opts[2] = 8; n = 3; }
-    else { opts[0] = 8; opts[1] = 4; n = 2; }
+    else { opts[0] = 8; opts[1] = 4; opts[2] = 2; n = 3; }
   } else if (M3 == 2048 && !dbl) {                   // A = 32
     opts[0] = 4; opts[1] = 2; n = 2;
   }
@@ -201,8 +201,8 @@ int z4_pencil_options(int M3, int* out, int cap) {
 
 template <typename T>
 static bool zshape(int M3, ZShape<T>* s, int P = 0) {
-  int opts[4];
-  const int n = z4_pencil_options<T>(M3, opts, 4);
+  int opts[8];
+  const int n = z4_pencil_options<T>(M3, opts, 8);
   if (n == 0) return false;
   bool ok = P == 0;
   for (int i = 0; i < n; ++i) ok = ok || opts[i] == P;

@@ -248,7 +248,7 @@ def test_every_launch_shape_matches_the_oracle(grid):
     plan.set_contrast(_t(wg.eps()))
     print(grid, "tuned:", plan.tune(0), plan.tune(1))
     M3 = 1 << int(np.ceil(np.log2(2 * wg.n[2] - 1)))
-    pencils = {0: {512: (8, 4, 16), 1024: (4, 2, 8)}[M3], 1: {512: (16, 8), 1024: (8, 4)}[M3]}
+    pencils = {0: {512: (8, 4, 16, 2), 1024: (4, 2, 8)}[M3], 1: {512: (16, 8, 4, 2), 1024: (8, 4, 2)}[M3]}
     xt = _t(x)
     xt32 = _t(x, torch.complex64)
     i = tuple(outs.T)
