@@ -324,8 +324,6 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
         const T s1 = kx <= 32 ? (T)1 : (T)-1;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-          // at most two frequencies' spectrum loads in flight (register pressure)
-          if (m == 2 || m == 4 || m == 6) __builtin_amdgcn_sched_barrier(0);
           const int ky = a + 8 * m;
           const int k2 = ky <= 32 ? ky : 64 - ky;
           const T s2 = ky <= 32 ? (T)1 : (T)-1;
@@ -349,6 +347,7 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
       // row's input is read again first (for A_1; unconditional, so that in[] is not
       // carried across the column stage), then half 0 parks its partial result in
       // the row's place and half 1 adds to it.
+      // (in half 1 the same loads bring the parked partial rows, all 12 at once)
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -372,10 +371,7 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int x = a + 8 * b;
-            if (x < n1) {
-              cx<T>* o = P + (c * n2 + y) * n1 + x;
-              *o = first ? v[b] : cadd(*o, v[b]);
-            }
+            if (x < n1) P[(c * n2 + y) * n1 + x] = first ? v[b] : cadd(in[c][b], v[b]);
           }
         }
       }

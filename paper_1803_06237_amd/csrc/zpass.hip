@@ -89,9 +89,23 @@ __device__ __forceinline__ void zfwd4_body(const cx<T>* __restrict__ x, cx<T>* _
   __syncthreads();
   const long plane = 3L * g.n1 * g.n2;
   cx<T>* dst = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;
-  for (int t = threadIdx.x; t < np * M; t += blockDim.x) {
-    const int pp = t % np, kz = t / np;
-    dst[kz * plane + pp] = S[kz * ld + pp];
+  if (np == P) {
+    // full block: thread t owns pencil t % P at planes t / P + A k, k < B; eight
+    // values in flight per batch, no divisions
+    const int pp = threadIdx.x % P, kz0 = threadIdx.x / P;
+#pragma unroll
+    for (int k0 = 0; k0 < B; k0 += 8) {
+      cx<T> tmp[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) tmp[k] = S[(kz0 + A * (k0 + k)) * ld + pp];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) dst[(long)(kz0 + A * (k0 + k)) * plane + pp] = tmp[k];
+    }
+  } else {
+    for (int t = threadIdx.x; t < np * M; t += blockDim.x) {
+      const int pp = t % np, kz = t / np;
+      dst[kz * plane + pp] = S[kz * ld + pp];
+    }
   }
   __syncthreads();
 }
@@ -120,9 +134,23 @@ __device__ __forceinline__ void zinv4_body(const cx<T>* __restrict__ U, const cx
   const int ld = P + 1;
   const long plane = 3L * g.n1 * g.n2;
   const cx<T>* src = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;
-  for (int t = threadIdx.x; t < np * M; t += blockDim.x) {
-    const int pp = t % np, kz = t / np;
-    S[kz * ld + pp] = src[kz * plane + pp];
+  if (np == P) {
+    // full block: thread t owns pencil t % P at planes t / P + A k, k < B; eight
+    // loads in flight per batch (one at a time would expose every latency), no divisions
+    const int pp = threadIdx.x % P, kz0 = threadIdx.x / P;
+#pragma unroll
+    for (int k0 = 0; k0 < B; k0 += 8) {
+      cx<T> tmp[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) tmp[k] = src[(long)(kz0 + A * (k0 + k)) * plane + pp];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) S[(kz0 + A * (k0 + k)) * ld + pp] = tmp[k];
+    }
+  } else {
+    for (int t = threadIdx.x; t < np * M; t += blockDim.x) {
+      const int pp = t % np, kz = t / np;
+      S[kz * ld + pp] = src[kz * plane + pp];
+    }
   }
   __syncthreads();
   cx<T> v[B];
