@@ -19,6 +19,17 @@ template <> struct cplx_of<double> { using type = double2; };
 template <> struct cplx_of<float> { using type = float2; };
 template <typename T> using cx = typename cplx_of<T>::type;
 
+// Pointer into global memory.  Device functions that batched kernels share take
+// their arrays in this form: a pointer read from device memory (a batch
+// descriptor) has no address space, so accesses through it would compile to flat
+// loads and stores, which the compiler must also order against LDS traffic.
+// (The host pass only type-checks device code, without address spaces.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename P> using gptr = __attribute__((address_space(1))) P*;
+#else
+template <typename P> using gptr = P*;
+#endif
+
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
 template <typename V> __device__ __forceinline__ V cmul(V a, V b) {

@@ -13,6 +13,12 @@
 // kz-plane-major intermediate U[kz][c][i2][i1] is written and read in runs of P
 // elements through an LDS staging array [kz][P + 1] (padded against bank
 // conflicts); the z-contiguous vectors x, y, chi are accessed directly.
+//
+// In FP64 the exchange moves the real parts, then the imaginary parts, and the
+// staging array holds one half of the kz range at a time.  That halves the LDS
+// of a pencil (8 KiB at M3 = 1024), so a CU holds twice as many pencils: at
+// 32 x 32 x 512 every pencil of a pass is resident at once instead of in one
+// and a half rounds of workgroups.
 #include <hip/hip_runtime.h>
 
 #include "dft_reg.hpp"
@@ -37,11 +43,71 @@ __device__ __forceinline__ int xcd_pair(int b, int nblocks) {
   const int r = b - base;
   return base + 2 * (r % 8) + r / 8;
 }
+
+// FP64 pencils exchange real and imaginary parts separately and stage half of
+// the kz range at a time
+template <typename T>
+constexpr bool z4_split() {
+  return sizeof(T) == 8;
+}
+
+// Thread a of pencil p hands v[k1] to the owner of frequency k1; afterwards
+// w[t A + j] holds frequency a + A t of thread j (t < B / A).  S must be free on
+// entry; the caller synchronises before reusing it.
+template <typename T, int A, int B>
+__device__ __forceinline__ void z4_exchange(const cx<T>* v, cx<T>* w, cx<T>* S, int p, int a, bool on) {
+  constexpr int M = A * B;
+  if constexpr (z4_split<T>()) {
+    T* Sd = reinterpret_cast<T*>(S);
+    if (on) {
+#pragma unroll
+      for (int k1 = 0; k1 < B; ++k1) Sd[xslot<A>(p, M, k1, a)] = v[k1].x;
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int t = 0; t < B / A; ++t)
+#pragma unroll
+        for (int j = 0; j < A; ++j) w[t * A + j].x = Sd[xslot<A>(p, M, a + A * t, j)];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int k1 = 0; k1 < B; ++k1) Sd[xslot<A>(p, M, k1, a)] = v[k1].y;
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int t = 0; t < B / A; ++t)
+#pragma unroll
+        for (int j = 0; j < A; ++j) w[t * A + j].y = Sd[xslot<A>(p, M, a + A * t, j)];
+    }
+  } else {
+    if (on) {
+#pragma unroll
+      for (int k1 = 0; k1 < B; ++k1) S[xslot<A>(p, M, k1, a)] = v[k1];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int t = 0; t < B / A; ++t)
+#pragma unroll
+        for (int j = 0; j < A; ++j) w[t * A + j] = S[xslot<A>(p, M, a + A * t, j)];
+    }
+  }
+}
 }  // namespace
 
+// LDS of a workgroup of P pencils of length M
+template <typename T>
+size_t z4_lds_for(int M, int P) {
+  return (size_t)(z4_split<T>() ? M / 2 : M) * (P + 1) * sizeof(cx<T>);
+}
+
 template <typename T, int A, int B>
-__device__ __forceinline__ void zfwd4_body(const cx<T>* __restrict__ x, cx<T>* __restrict__ U, const Geom& g,
-                                           int P, const cx<T>* __restrict__ tw, int blk, cx<T>* S) {
+__device__ __forceinline__ void zfwd4_body(gptr<const cx<T>> __restrict__ x, gptr<cx<T>> __restrict__ U,
+                                           const Geom& g, int P, gptr<const cx<T>> __restrict__ tw, int blk,
+                                           cx<T>* S, int tid) {
   constexpr int M = A * B;
   const int nb1 = (g.n1 + P - 1) / P;
   const int ib1 = blk % nb1;
@@ -50,78 +116,77 @@ __device__ __forceinline__ void zfwd4_body(const cx<T>* __restrict__ x, cx<T>* _
   const int c = blk / g.n2;
   const int i1_0 = ib1 * P;
   const int np = min(P, g.n1 - i1_0);
-  const int p = threadIdx.x / A, a = threadIdx.x % A;
+  const int p = tid / A, a = tid % A;
   const int ld = P + 1;
   cx<T> v[B];
   if (p < np) {
-    const cx<T>* src = x + (((long)c * g.n1 + i1_0 + p) * g.n2 + i2) * g.n3;
+    gptr<const cx<T>> src = x + (((long)c * g.n1 + i1_0 + p) * g.n2 + i2) * g.n3;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int n = a + A * b;
-      v[b] = (b < B / 2 && n < g.n3) ? src[n] : cx<T>{(T)0, (T)0};   // n >= M/2 >= n3 is padding
+      v[b] = cx<T>{(T)0, (T)0};
+      if (b < B / 2 && n < g.n3) v[b] = src[n];   // n >= M/2 >= n3 is padding
     }
     dft_reg<T, false, B>(v);
 #pragma unroll
     for (int k1 = 1; k1 < B; ++k1) v[k1] = cmul(v[k1], tw[a * k1]);
-#pragma unroll
-    for (int k1 = 0; k1 < B; ++k1) S[xslot<A>(p, M, k1, a)] = v[k1];
   }
-  __syncthreads();
+  cx<T> w[B];
+  z4_exchange<T, A, B>(v, w, S, p, a, p < np);
   if (p < np) {
 #pragma unroll
-    for (int t = 0; t < B / A; ++t) {
-      const int k1 = a + A * t;
-      cx<T> z[A];
-#pragma unroll
-      for (int j = 0; j < A; ++j) z[j] = S[xslot<A>(p, M, k1, j)];
-      dft_reg<T, false, A>(z);
-#pragma unroll
-      for (int k2 = 0; k2 < A; ++k2) v[t * A + k2] = z[k2];
-    }
+    for (int t = 0; t < B / A; ++t) dft_reg<T, false, A>(w + t * A);
   }
   __syncthreads();
-  if (p < np) {
-#pragma unroll
-    for (int t = 0; t < B / A; ++t)
-#pragma unroll
-      for (int k2 = 0; k2 < A; ++k2) S[(a + A * t + B * k2) * ld + p] = v[t * A + k2];
-  }
-  __syncthreads();
+  // w[t A + k2] is X[kz] at kz = a + A t + B k2; staged H kz-ranges of M / H
+  constexpr int H = z4_split<T>() ? 2 : 1;
   const long plane = 3L * g.n1 * g.n2;
-  cx<T>* dst = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;
-  if (np == P) {
-    // full block: thread t owns pencil t % P at planes t / P + A k, k < B; eight
-    // values in flight per batch, no divisions
-    const int pp = threadIdx.x % P, kz0 = threadIdx.x / P;
+  gptr<cx<T>> dst = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;
 #pragma unroll
-    for (int k0 = 0; k0 < B; k0 += 8) {
-      cx<T> tmp[8];
+  for (int h = 0; h < H; ++h) {
+    if (p < np) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) tmp[k] = S[(kz0 + A * (k0 + k)) * ld + pp];
+      for (int t = 0; t < B / A; ++t)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) dst[(long)(kz0 + A * (k0 + k)) * plane + pp] = tmp[k];
+        for (int k2 = 0; k2 < A / H; ++k2) S[(a + A * t + B * k2) * ld + p] = w[t * A + h * (A / H) + k2];
     }
-  } else {
-    for (int t = threadIdx.x; t < np * M; t += blockDim.x) {
-      const int pp = t % np, kz = t / np;
-      dst[kz * plane + pp] = S[kz * ld + pp];
+    __syncthreads();
+    gptr<cx<T>> dh = dst + (long)h * (M / H) * plane;
+    if (np == P) {
+      // full block: thread t owns pencil t % P at planes t / P + A k, k < B / H;
+      // eight values in flight per batch, no divisions
+      const int pp = tid % P, kz0 = tid / P;
+#pragma unroll
+      for (int k0 = 0; k0 < B / H; k0 += 8) {
+        cx<T> tmp[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tmp[k] = S[(kz0 + A * (k0 + k)) * ld + pp];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dh[(long)(kz0 + A * (k0 + k)) * plane + pp] = tmp[k];
+      }
+    } else {
+      for (int t = tid; t < np * (M / H); t += blockDim.x) {
+        const int pp = t % np, kz = t / np;
+        dh[kz * plane + pp] = S[kz * ld + pp];
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 template <typename T, int A, int B>
 __global__ __launch_bounds__(256) void k_zfwd4(const cx<T>* __restrict__ x, cx<T>* __restrict__ U, Geom g,
                                                 int P, const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
-  zfwd4_body<T, A, B>(x, U, g, P, tw, xcd_pair(blockIdx.x, gridDim.x), reinterpret_cast<cx<T>*>(smem_raw));
+  zfwd4_body<T, A, B>((gptr<const cx<T>>)x, (gptr<cx<T>>)U, g, P, (gptr<const cx<T>>)tw,
+                      xcd_pair(blockIdx.x, gridDim.x), reinterpret_cast<cx<T>*>(smem_raw), threadIdx.x);
 }
 
 template <typename T, int A, int B, int MODE>
-__device__ __forceinline__ void zinv4_body(const cx<T>* __restrict__ U, const cx<T>* __restrict__ x,
-                                           cx<T>* __restrict__ y, const cx<T>* __restrict__ bvec,
-                                           const cx<T>* __restrict__ chi, const Geom& g, int P,
-                                           const cx<T>* __restrict__ tw, int blk, cx<T>* S) {
+__device__ __forceinline__ void zinv4_body(gptr<const cx<T>> __restrict__ U, gptr<const cx<T>> __restrict__ x,
+                                           gptr<cx<T>> __restrict__ y, gptr<const cx<T>> __restrict__ bvec,
+                                           gptr<const cx<T>> __restrict__ chi, const Geom& g, int P,
+                                           gptr<const cx<T>> __restrict__ tw, int blk, cx<T>* S, int tid) {
   constexpr int M = A * B;
   const int nb1 = (g.n1 + P - 1) / P;
   const int ib1 = blk % nb1;
@@ -130,57 +195,67 @@ __device__ __forceinline__ void zinv4_body(const cx<T>* __restrict__ U, const cx
   const int c = blk / g.n2;
   const int i1_0 = ib1 * P;
   const int np = min(P, g.n1 - i1_0);
-  const int p = threadIdx.x / A, a = threadIdx.x % A;
+  const int p = tid / A, a = tid % A;
   const int ld = P + 1;
   const long plane = 3L * g.n1 * g.n2;
-  const cx<T>* src = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;
-  if (np == P) {
-    // full block: thread t owns pencil t % P at planes t / P + A k, k < B; eight
-    // loads in flight per batch (one at a time would expose every latency), no divisions
-    const int pp = threadIdx.x % P, kz0 = threadIdx.x / P;
-#pragma unroll
-    for (int k0 = 0; k0 < B; k0 += 8) {
-      cx<T> tmp[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) tmp[k] = src[(long)(kz0 + A * (k0 + k)) * plane + pp];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) S[(kz0 + A * (k0 + k)) * ld + pp] = tmp[k];
-    }
-  } else {
-    for (int t = threadIdx.x; t < np * M; t += blockDim.x) {
-      const int pp = t % np, kz = t / np;
-      S[kz * ld + pp] = src[kz * plane + pp];
-    }
-  }
-  __syncthreads();
+  gptr<const cx<T>> src = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;
+  // staged H kz-ranges of M / H; range h holds v[b] for b in [h B / H, (h + 1) B / H)
+  constexpr int H = z4_split<T>() ? 2 : 1;
   cx<T> v[B];
-  if (p < np) {
 #pragma unroll
-    for (int b = 0; b < B; ++b) v[b] = S[(a + A * b) * ld + p];
+  for (int h = 0; h < H; ++h) {
+    gptr<const cx<T>> sh = src + (long)h * (M / H) * plane;
+    if (np == P) {
+      // full block: thread t owns pencil t % P at planes t / P + A k, k < B / H;
+      // eight loads in flight per batch (one at a time would expose every
+      // latency), no divisions
+      const int pp = tid % P, kz0 = tid / P;
+#pragma unroll
+      for (int k0 = 0; k0 < B / H; k0 += 8) {
+        cx<T> tmp[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tmp[k] = sh[(long)(kz0 + A * (k0 + k)) * plane + pp];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) S[(kz0 + A * (k0 + k)) * ld + pp] = tmp[k];
+      }
+    } else {
+      for (int t = tid; t < np * (M / H); t += blockDim.x) {
+        const int pp = t % np, kz = t / np;
+        S[kz * ld + pp] = sh[kz * plane + pp];
+      }
+    }
+    __syncthreads();
+    if (p < np) {
+#pragma unroll
+      for (int b = 0; b < B / H; ++b) v[h * (B / H) + b] = S[(a + A * b) * ld + p];
+    }
+    __syncthreads();
+  }
+  if (p < np) {
     dft_reg<T, true, B>(v);
 #pragma unroll
     for (int k1 = 1; k1 < B; ++k1) v[k1] = cmulc(v[k1], tw[a * k1]);
   }
-  __syncthreads();
-  if (p < np) {
-#pragma unroll
-    for (int k1 = 0; k1 < B; ++k1) S[xslot<A>(p, M, k1, a)] = v[k1];
-  }
-  __syncthreads();
+  cx<T> w[B];
+  z4_exchange<T, A, B>(v, w, S, p, a, p < np);
   if (p < np) {
     const long vox = ((long)(i1_0 + p) * g.n2 + i2) * g.n3;
     const long off = (long)c * g.N + vox;
 #pragma unroll
     for (int t = 0; t < B / A; ++t) {
       const int k1 = a + A * t;
-      cx<T> z[A];
-#pragma unroll
-      for (int j = 0; j < A; ++j) z[j] = S[xslot<A>(p, M, k1, j)];
+      cx<T>* z = w + t * A;
       dft_reg<T, true, A>(z);
+      // Pin the kept outputs in registers here.  Otherwise the compiler sinks
+      // their arithmetic into the conditional stores below, which keeps the
+      // transform's intermediates live across all of them (280 instead of 168
+      // VGPRs in FP64 at A = 32: one wave per SIMD instead of three).
 #pragma unroll
-      for (int k2 = 0; k2 < A; ++k2) {
+      for (int k2 = 0; k2 < A / 2; ++k2) asm volatile("" : "+v"(z[k2].x), "+v"(z[k2].y));
+#pragma unroll
+      for (int k2 = 0; k2 < A / 2; ++k2) {
         const int n = k1 + B * k2;
-        if (k2 < A / 2 && n < g.n3) {   // n >= M/2 >= n3 is cropped
+        if (n < g.n3) {   // n >= M/2 >= n3 is cropped
           const cx<T> r = csub(x[off + n], cmul(chi[vox + n], z[k2]));
           y[off + n] = MODE == 0 ? r : csub(bvec[off + n], r);
         }
@@ -196,8 +271,9 @@ __global__ __launch_bounds__(256) void k_zinv4(const cx<T>* __restrict__ U, cons
                                                 const cx<T>* __restrict__ chi, Geom g, int P,
                                                 const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
-  zinv4_body<T, A, B, MODE>(U, x, y, bvec, chi, g, P, tw, xcd_pair(blockIdx.x, gridDim.x),
-                            reinterpret_cast<cx<T>*>(smem_raw));
+  zinv4_body<T, A, B, MODE>((gptr<const cx<T>>)U, (gptr<const cx<T>>)x, (gptr<cx<T>>)y, (gptr<const cx<T>>)bvec,
+                            (gptr<const cx<T>>)chi, g, P, (gptr<const cx<T>>)tw, xcd_pair(blockIdx.x, gridDim.x),
+                            reinterpret_cast<cx<T>*>(smem_raw), threadIdx.x);
 }
 
 // Launch: returns hipErrorNotSupported when (M3, precision) has no four-step
@@ -208,7 +284,7 @@ struct ZShape {
 };
 
 // Pencil counts P tried by the plan-time tuner, default first; each keeps the
-// workgroup (A P threads) within the kernels' 256 and its LDS (M3 (P + 1) values)
+// workgroup (A P threads) within the kernels' 256 and its LDS (z4_lds_for)
 // within 160 KiB.
 template <typename T>
 int z4_pencil_options(int M3, int* out, int cap) {
@@ -246,7 +322,7 @@ template <typename T>
 size_t z4_lds_bytes(int M3, int P) {
   ZShape<T> s;
   if (!zshape<T>(M3, &s, P)) return 0;
-  return (size_t)M3 * (s.P + 1) * sizeof(cx<T>);
+  return z4_lds_for<T>(M3, s.P);
 }
 
 template <typename T>
@@ -257,7 +333,7 @@ hipError_t launch_z4(int which, const Geom& g, int P, const void* x, void* y, co
   if (!zshape<T>(g.M3, &s, P)) return hipErrorNotSupported;
   const int nb1 = (g.n1 + s.P - 1) / s.P;
   const dim3 grid(3 * g.n2 * nb1), block(s.A * s.P);
-  const size_t lds = (size_t)g.M3 * (s.P + 1) * sizeof(C);
+  const size_t lds = z4_lds_for<T>(g.M3, s.P);
 #define VIE_Z4(AA, BB)                                                                                        \
   if (s.A == AA && s.B == BB) {                                                                               \
     if (which == 0)                                                                                           \
@@ -277,6 +353,16 @@ hipError_t launch_z4(int which, const Geom& g, int P, const void* x, void* y, co
   }
 #undef VIE_Z4
   return hipErrorNotSupported;
+}
+
+// The thread index as a value the compiler cannot see through.  The persistent
+// kernels take it once per item: otherwise every thread-dependent LDS and
+// twiddle address of the body is hoisted out of the item loop and held in
+// registers across it (about a hundred VGPRs).
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 __device__ __forceinline__ int find_sys(const int* prefix, int nsys, int item) {
@@ -300,8 +386,8 @@ __global__ __launch_bounds__(256) void k_zfwd4_batch(const PassDesc* __restrict_
     const int s = find_sys(prefix, nsys, item);
     const PassDesc& D = d[s];
     if (D.active && *D.active == 0) continue;
-    zfwd4_body<T, A, B>((const cx<T>*)D.xb + (long)jx * D.xs, (cx<T>*)D.U, D.g, D.P, (const cx<T>*)D.twz,
-                        item - prefix[s], S);
+    zfwd4_body<T, A, B>((gptr<const cx<T>>)(const cx<T>*)D.xb + (long)jx * D.xs, (gptr<cx<T>>)(cx<T>*)D.U, D.g, D.P,
+                        (gptr<const cx<T>>)(const cx<T>*)D.twz, item - prefix[s], S, opaque_tid());
   }
 }
 
@@ -314,9 +400,10 @@ __global__ __launch_bounds__(256) void k_zinv4_batch(const PassDesc* __restrict_
     const int s = find_sys(prefix, nsys, item);
     const PassDesc& D = d[s];
     if (D.active && *D.active == 0) continue;
-    zinv4_body<T, A, B, MODE>((const cx<T>*)D.U, (const cx<T>*)D.xb + (long)jx * D.xs,
-                              (cx<T>*)D.yb + (long)jy * D.ys, (const cx<T>*)D.b, (const cx<T>*)D.chi, D.g, D.P,
-                              (const cx<T>*)D.twz, item - prefix[s], S);
+    zinv4_body<T, A, B, MODE>((gptr<const cx<T>>)(const cx<T>*)D.U, (gptr<const cx<T>>)(const cx<T>*)D.xb + (long)jx * D.xs,
+                              (gptr<cx<T>>)(cx<T>*)D.yb + (long)jy * D.ys, (gptr<const cx<T>>)(const cx<T>*)D.b,
+                              (gptr<const cx<T>>)(const cx<T>*)D.chi, D.g, D.P, (gptr<const cx<T>>)(const cx<T>*)D.twz,
+                              item - prefix[s], S, opaque_tid());
   }
 }
 
@@ -333,7 +420,7 @@ bool z4_shape(int M3, int* A, int* B, int* P) {
 template <typename T>
 hipError_t launch_z4_batch(int which, int mode, const PassDesc* d, const int* prefix, int nsys, int total, int A,
                            int B, int P, int jx, int jy, hipStream_t st) {
-  const size_t lds = (size_t)A * B * (P + 1) * sizeof(cx<T>);
+  const size_t lds = z4_lds_for<T>(A * B, P);
   const dim3 grid(total < 4096 ? total : 4096), block(A * P);
 #define VIE_Z4B(AA, BB)                                                                                      \
   if (A == AA && B == BB) {                                                                                  \
