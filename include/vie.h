@@ -235,7 +235,8 @@ int vie_circulant_apply(vie_plan_t plan, const vie_c128* r, vie_c128* z);
  * untimed and five timed launches each, HIP events) and keeps the fastest:
  * pencils per workgroup of the four-step z passes (forward and inverse timed
  * together) and, for 64 x 64 circulant cross-sections, the xy pass variant
- * (0: full plane in LDS; 1: x-frequency halves, two workgroups per CU).  Choices
+ * (0: full plane in LDS; 1: x-frequency halves, two workgroups per CU; 2: full
+ * plane with 512 threads and private exchange areas, one workgroup per CU).  Choices
  * are cached per (device, grid, precision) for the life of the process.
  * vie_get_tune: the current choice for precision 0 (FP64) or 1 (FP32):
  *   *xy_variant (-1 when the grid does not use the 64 x 64 kernel),

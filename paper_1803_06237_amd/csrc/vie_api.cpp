@@ -270,7 +270,7 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
   if (!e && g.M1 == 64 && g.M2 == 64) {
     float best = INFINITY;
     int bestv = t->xyv;
-    for (int v = 0; v < 2 && !e; ++v) {
+    for (int v = 0; v < 3 && !e; ++v) {
       Tune c = *t;
       c.xyv = v;
       float ms = 0;
@@ -962,7 +962,7 @@ int vie_get_tune(vie_plan_t p, int precision, int* xy_variant, int* z_pencils) {
 int vie_set_tune(vie_plan_t p, int precision, int xy_variant, int z_pencils) {
   if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
   if (precision != 0 && precision != 1) return fail(p, VIE_EINVAL, "precision must be 0 or 1");
-  if (xy_variant != 0 && xy_variant != 1) return fail(p, VIE_EINVAL, "xy_variant must be 0 or 1");
+  if (xy_variant < 0 || xy_variant > 2) return fail(p, VIE_EINVAL, "xy_variant must be 0, 1 or 2");
   int opts[8];
   const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 8)
                                : z4_pencil_options<float>(p->g.M3, opts, 8);

@@ -26,7 +26,7 @@ struct Tune {
   int cc;        // column chunk in the xy pass
   int xythreads; // threads per workgroup in the xy pass
   int z4;        // 1: z passes use the register four-step kernels
-  int xyv;       // 64 x 64 xy pass variant: 0 full plane, 1 x-frequency halves
+  int xyv;       // 64 x 64 xy pass variant: 0 full plane, 1 x-frequency halves, 2 wide
   int zp;        // pencils per workgroup in the four-step z passes (0: the default for M3)
 };
 

@@ -29,11 +29,24 @@
 //   C_h: rows inverse from the 32 frequencies of half h (the rest taken as
 //        zero); half 0 parks its partial row in the plane's own storage (after
 //        reading the row input again for A_1) and half 1 adds to it.
+//  V = 2 (wide): 512 threads (64 groups, two waves per SIMD) and the whole
+//   160 KiB of LDS in FP64: the rows of all 64 x-frequencies of the three
+//   components (96 KiB) plus a private 64-value exchange area per group, so no
+//   row transform is done twice and no partial row leaves the CU:
+//   A: the 96 forward row transforms (32 rows x 3 components) over the 64
+//      groups (groups g < 32 take components 0 and 2 of row g, the others
+//      component 1 of row g - 32);
+//   B: one column (kx = g) per group: forward, Green product, inverse;
+//   C: the 96 inverse row transforms as in A, crop, store.
 // Planes kz and M3 - kz use the same slab of the folded Green spectrum: the
 // single-system kernel puts them on workgroups b and b + 8 (same XCD), the
 // batched kernel transforms the pair in one workgroup.
-// LDS element (c, y, j) sits at (c*32 + y)*32 + (j ^ (y & 7)) so that the column
-// reads of the 8 lanes of a group (consecutive y) hit distinct banks.
+// LDS layouts avoid bank conflicts.  The LDS serves a wave in passes of 256 bytes
+// (16 lanes of 16-byte values in FP64, 32 lanes of 8-byte values in FP32), so
+// the 2 or 4 lane groups of a pass must use disjoint banks as well as the 8
+// lanes of a group: hand-off element (c, y, j) sits in row (c, y) at column
+// j ^ (y & 7) ^ 8 (y & 3), and the exchange area of group q stores its row i in
+// slot i ^ (q & 3), rotated by i.
 #include <hip/hip_runtime.h>
 
 #include "fft_device.hpp"
@@ -43,11 +56,14 @@ namespace vie {
 
 namespace {
 
-__device__ __forceinline__ int hpos(int c, int y, int j) { return (c * 32 + y) * 32 + (j ^ (y & 7)); }
+__device__ __forceinline__ int hpos(int c, int y, int j) {
+  return (c * 32 + y) * 32 + (j ^ (y & 7) ^ ((y & 3) << 3));
+}
 
 constexpr int kRowVals = 3 * 32 * 32;               // row/column hand-off of one half
 constexpr int kXyLdsVals = kRowVals + 32 * 64;      // + 32 groups x 64 exchange values
 constexpr int kFullLdsVals = 3 * 32 * 64;           // full-plane variant: rows of all 64 frequencies
+constexpr int kWideLdsVals = kFullLdsVals + 64 * 64; // wide variant: + 64 groups x 64 exchange values
 // x-frequency halves of the V = 1 variant, as the m of kx = a + 8 m (a = lane):
 // half 0 = m in {0, 1, 6, 7} (kx < 16 or kx >= 48, folded |kx| <= 16), half 1 =
 // m in {2, 3, 4, 5} (16 <= kx < 48, folded |kx| >= 16), so that the two halves
@@ -56,8 +72,10 @@ __constant__ constexpr int kHalf0[4] = {0, 1, 6, 7};
 
 // full-plane variant: element (c, y, kx) of the row buffer, and the 8 x 8 exchange
 // block of group gr (64 values) with element (i, j) rotated as in xpos
-__device__ __forceinline__ int rpos(int c, int y, int kx) { return (c * 32 + y) * 64 + (kx ^ (y & 7)); }
-__device__ __forceinline__ int gpos(int gr, int i, int j) { return gr * 64 + i * 8 + ((i + j) & 7); }
+__device__ __forceinline__ int rpos(int c, int y, int kx) {
+  return (c * 32 + y) * 64 + (kx ^ (y & 7) ^ ((y & 3) << 3));
+}
+__device__ __forceinline__ int gpos(int gr, int i, int j) { return gr * 64 + (i ^ (gr & 3)) * 8 + ((i + j) & 7); }
 
 template <typename T, bool INV>
 __device__ __forceinline__ void twiddle8(cx<T>* v, const cx<T>* w) {
@@ -65,29 +83,30 @@ __device__ __forceinline__ void twiddle8(cx<T>* v, const cx<T>* w) {
   for (int k = 1; k < 8; ++k) v[k] = INV ? cmulc(v[k], w[k]) : cmul(v[k], w[k]);
 }
 
-// Exchange area of one group of 8 lanes (64 values): element (i, j) stored rotated
-// so that 8 lanes reading row i with j = 0..7 touch distinct banks.
-__device__ __forceinline__ int xpos(int i, int j) { return i * 8 + ((i + j) & 7); }
+// Exchange area of one group of 8 lanes (64 values): element (i, j) stored in
+// slot i ^ f (f = group & 3) and rotated by i, so that the lanes of a group and
+// the groups of an LDS pass touch distinct banks.
+__device__ __forceinline__ int xpos(int i, int j, int f) { return (i ^ f) * 8 + ((i + j) & 7); }
 
 // 8 x 8 transpose across the 8 lanes of a group through the group's own 64-value
 // LDS area X: lane a's v[k] becomes lane k's v[a].  The area belongs to one wave,
 // whose LDS accesses complete in program order, so no workgroup barrier is needed.
 template <typename T>
-__device__ __forceinline__ void transpose8(cx<T>* v, int a, cx<T>* X) {
+__device__ __forceinline__ void transpose8(cx<T>* v, int a, cx<T>* X, int f) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) X[xpos(k, a)] = v[k];
+  for (int k = 0; k < 8; ++k) X[xpos(k, a, f)] = v[k];
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = X[xpos(a, j)];
+  for (int j = 0; j < 8; ++j) v[j] = X[xpos(a, j, f)];
   __builtin_amdgcn_wave_barrier();
 }
 
 // 64-point transform of the group: in, lane a holds x[a + 8 b]; out, lane a holds X[a + 8 m]
 template <typename T, bool INV>
-__device__ __forceinline__ void fft64(cx<T>* v, const cx<T>* w, int a, cx<T>* X) {
+__device__ __forceinline__ void fft64(cx<T>* v, const cx<T>* w, int a, cx<T>* X, int f) {
   dft8<T, INV>(v);
   twiddle8<T, INV>(v, w);
-  transpose8<T>(v, a, X);
+  transpose8<T>(v, a, X, f);
   dft8<T, INV>(v);
 }
 
@@ -268,6 +287,7 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
   const int q = tid >> 3;                            // group: row y in A and C, column in B
   const int n1 = g.n1, n2 = g.n2;
   cx<T>* X = R + kRowVals + q * 64;                  // this group's exchange area
+  const int f = q & 3;
   cx<T> w[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) w[k] = tw64[a * k];
@@ -299,7 +319,7 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
         for (int b = 0; b < 4; ++b) v[b] = in[c][b];
 #pragma unroll
         for (int b = 4; b < 8; ++b) v[b] = zero;
-        fft64<T, false>(v, w, a, X);
+        fft64<T, false>(v, w, a, X, f);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const cx<T> h0 = v[kHalf0[j]], h1 = v[j + 2];
@@ -318,7 +338,7 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
           for (int b = 0; b < 4; ++b) v[c][b] = R[hpos(c, a + 8 * b, q)];
 #pragma unroll
           for (int b = 4; b < 8; ++b) v[c][b] = zero;
-          fft64<T, false>(v[c], w, a, X);  // v[c][m] = Y[ky = a + 8 m]
+          fft64<T, false>(v[c], w, a, X, f);  // v[c][m] = Y[ky = a + 8 m]
         }
         const int k1 = kx <= 32 ? kx : 64 - kx;
         const T s1 = kx <= 32 ? (T)1 : (T)-1;
@@ -337,7 +357,7 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          fft64<T, true>(v[c], w, a, X);   // v[c][b] = column value at y = a + 8 b
+          fft64<T, true>(v[c], w, a, X, f);   // v[c][b] = column value at y = a + 8 b
 #pragma unroll
           for (int b = 0; b < 4; ++b) R[hpos(c, a + 8 * b, q)] = v[c][b];
         }
@@ -366,7 +386,7 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
           v[kHalf0[j]] = in0;
           v[j + 2] = in1;
         }
-        fft64<T, true>(v, w, a, X);        // v[b] = row value at x = a + 8 b
+        fft64<T, true>(v, w, a, X, f);        // v[b] = row value at x = a + 8 b
         if (row_ok) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
@@ -381,20 +401,122 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
 }
 
 
+template <typename T>
+__device__ __forceinline__ void xy64_wide(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
+                                          const cx<T>* __restrict__ tw64, int kz_first, int nplanes, int kz_second,
+                                          cx<T>* R) {
+  const int tid = threadIdx.x;
+  const int a = tid & 7;
+  const int q = tid >> 3;                            // 0..63
+  const int f = q & 3;
+  const int n1 = g.n1, n2 = g.n2;
+  cx<T>* X = R + kFullLdsVals + q * 64;              // this group's exchange area
+  cx<T> w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w[k] = tw64[a * k];
+  const cx<T> zero{(T)0, (T)0};
+  for (int pi = 0; pi < nplanes; ++pi) {
+    const int kz = pi == 0 ? kz_first : kz_second;
+    cx<T>* P = U + (long)kz * 3 * n1 * n2;
+    // ---- A: forward x transforms; row task ft = q + 64 t (t = 0, 1) is
+    // (component ft / 32, row ft % 32) while ft < 96
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int ft = q + 64 * t;
+      if (ft < 96) {
+        const int c = ft >> 5, y = ft & 31;
+        cx<T> v[8];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int x = a + 8 * b;
+          v[b] = (x < n1 && y < n2) ? P[(c * n2 + y) * n1 + x] : zero;
+        }
+#pragma unroll
+        for (int b = 4; b < 8; ++b) v[b] = zero;
+        fft64<T, false>(v, w, a, X, f);           // v[m] = X[kx = a + 8 m]
+#pragma unroll
+        for (int m = 0; m < 8; ++m) R[rpos(c, y, a + 8 * m)] = v[m];
+      }
+    }
+    __syncthreads();
+    // ---- B: column kx = q of all three components
+    {
+      const int kx = q;
+      const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
+      const T s3 = kz <= g.M3 / 2 ? (T)1 : (T)-1;
+      const cx<T>* G3 = goct + (long)k3 * g.H2 * g.H1 * 6;
+      cx<T> v[3][8];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[c][b] = R[rpos(c, a + 8 * b, kx)];
+#pragma unroll
+        for (int b = 4; b < 8; ++b) v[c][b] = zero;
+        fft64<T, false>(v[c], w, a, X, f);        // v[c][m] = Y[ky = a + 8 m]
+      }
+      const int k1 = kx <= 32 ? kx : 64 - kx;
+      const T s1 = kx <= 32 ? (T)1 : (T)-1;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int ky = a + 8 * m;
+        const int k2 = ky <= 32 ? ky : 64 - ky;
+        const T s2 = ky <= 32 ? (T)1 : (T)-1;
+        const cx<T>* Gp = G3 + ((long)k2 * g.H1 + k1) * 6;
+        const cx<T> gxx = Gp[0], gyy = Gp[3], gzz = Gp[5];
+        const cx<T> gxy = cscale(Gp[1], s1 * s2), gxz = cscale(Gp[2], s1 * s3), gyz = cscale(Gp[4], s2 * s3);
+        const cx<T> ux = v[0][m], uy = v[1][m], uz = v[2][m];
+        v[0][m] = cadd(cadd(cmul(gxx, ux), cmul(gxy, uy)), cmul(gxz, uz));
+        v[1][m] = cadd(cadd(cmul(gxy, ux), cmul(gyy, uy)), cmul(gyz, uz));
+        v[2][m] = cadd(cadd(cmul(gxz, ux), cmul(gyz, uy)), cmul(gzz, uz));
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        fft64<T, true>(v[c], w, a, X, f);         // v[c][b] = column value at y = a + 8 b
+#pragma unroll
+        for (int b = 0; b < 4; ++b) R[rpos(c, a + 8 * b, kx)] = v[c][b];
+      }
+    }
+    __syncthreads();
+    // ---- C: inverse x transforms of the row tasks of A, crop, store
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int ft = q + 64 * t;
+      if (ft < 96 && (ft & 31) < n2) {
+        const int c = ft >> 5, y = ft & 31;
+        cx<T> v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = R[rpos(c, y, a + 8 * m)];
+        fft64<T, true>(v, w, a, X, f);            // v[b] = row value at x = a + 8 b
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int x = a + 8 * b;
+          if (x < n1) P[(c * n2 + y) * n1 + x] = v[b];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // plane pair p: (0, M3/2) for p = 0, (p, M3 - p) otherwise
 __device__ __forceinline__ void pair_planes(int p, int M3, int* a, int* b) {
   *a = p == 0 ? 0 : p;
   *b = p == 0 ? M3 / 2 : M3 - p;
 }
 
-// V = 0: full-plane variant; V = 1: x-frequency halves
+// V = 0: full-plane variant; V = 1: x-frequency halves; V = 2: wide
 template <typename T, int V>
 __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
                                             const cx<T>* __restrict__ tw64, int kz_first, int nplanes, int kz_second,
                                             cx<T>* R) {
   if constexpr (V == 0) xy64_full<T>(U, goct, g, tw64, kz_first, nplanes, kz_second, R);
-  else xy64_half<T>(U, goct, g, tw64, kz_first, nplanes, kz_second, R);
+  else if constexpr (V == 1) xy64_half<T>(U, goct, g, tw64, kz_first, nplanes, kz_second, R);
+  else xy64_wide<T>(U, goct, g, tw64, kz_first, nplanes, kz_second, R);
 }
+
+// threads per workgroup and occupancy hint of each variant
+template <int V> constexpr int kXyThreads = V == 2 ? 512 : 256;
+template <int V> constexpr int kXyWaves = V == 1 ? 2 : 1;
 
 template <typename T, int V>
 __device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
@@ -408,8 +530,9 @@ __device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __
 // slab; they go to workgroups b and b + 8 (same XCD under round-robin
 // dispatch, launched one after the other) so the second read hits L2.
 template <typename T, int V>
-__global__ __launch_bounds__(256, V == 1 ? 2 : 1) void k_xy64(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct,
-                                                              Geom g, const cx<T>* __restrict__ tw64) {
+__global__ __launch_bounds__(kXyThreads<V>, kXyWaves<V>) void k_xy64(cx<T>* __restrict__ U,
+                                                                    const cx<T>* __restrict__ goct, Geom g,
+                                                                    const cx<T>* __restrict__ tw64) {
   extern __shared__ unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int base = (b / 16) * 16, r = b - base;
@@ -439,16 +562,17 @@ __global__ __launch_bounds__(256, V == 1 ? 2 : 1) void k_xy64_batch(const PassDe
 }
 
 template <typename T, int V>
-__global__ __launch_bounds__(256, V == 1 ? 2 : 1) void k_xy64_batch_single(cx<T>* __restrict__ U,
-                                                                           const cx<T>* __restrict__ goct, Geom g,
-                                                                           const cx<T>* __restrict__ tw64) {
+__global__ __launch_bounds__(kXyThreads<V>, kXyWaves<V>) void k_xy64_batch_single(cx<T>* __restrict__ U,
+                                                                                 const cx<T>* __restrict__ goct,
+                                                                                 Geom g,
+                                                                                 const cx<T>* __restrict__ tw64) {
   extern __shared__ unsigned char smem_raw[];
   xy64_body<T, V>(U, goct, g, tw64, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 template <typename T>
 size_t xy64_lds(int V) {
-  return (size_t)(V == 1 ? kXyLdsVals : kFullLdsVals) * sizeof(cx<T>);
+  return (size_t)(V == 1 ? kXyLdsVals : V == 2 ? kWideLdsVals : kFullLdsVals) * sizeof(cx<T>);
 }
 
 // Variant of the batched kernel: x-frequency halves in FP64 (register-bound
@@ -469,23 +593,32 @@ template hipError_t launch_xy64_batch<float>(const PassDesc*, const int*, int, i
 template <typename T>
 hipError_t launch_xy64(const Geom& g, int V, void* U, const void* goct, const void* tw1, hipStream_t s) {
   const size_t lds = xy64_lds<T>(V);
+  const dim3 block(V == 2 ? kXyThreads<2> : kXyThreads<0>);
   if (g.M3 % 16 != 0) {   // short z circulant: one workgroup per plane pair
     const dim3 grid(g.M3 == 1 ? 1 : g.M3 / 2);
-    if (V == 1)
-      hipLaunchKernelGGL((k_xy64_batch_single<T, 1>), grid, dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
-                         (const cx<T>*)tw1);
-    else
-      hipLaunchKernelGGL((k_xy64_batch_single<T, 0>), grid, dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
-                         (const cx<T>*)tw1);
-    return hipGetLastError();
+#define VIE_XYS(VV)                                                                                           \
+  if (V == VV) {                                                                                              \
+    hipLaunchKernelGGL((k_xy64_batch_single<T, VV>), grid, block, lds, s, (cx<T>*)U, (const cx<T>*)goct, g,   \
+                       (const cx<T>*)tw1);                                                                    \
+    return hipGetLastError();                                                                                 \
   }
-  if (V == 1)
-    hipLaunchKernelGGL((k_xy64<T, 1>), dim3(g.M3), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
-                       (const cx<T>*)tw1);
-  else
-    hipLaunchKernelGGL((k_xy64<T, 0>), dim3(g.M3), dim3(256), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
-                       (const cx<T>*)tw1);
-  return hipGetLastError();
+    VIE_XYS(0)
+    VIE_XYS(1)
+    VIE_XYS(2)
+#undef VIE_XYS
+    return hipErrorInvalidValue;
+  }
+#define VIE_XY(VV)                                                                                            \
+  if (V == VV) {                                                                                              \
+    hipLaunchKernelGGL((k_xy64<T, VV>), dim3(g.M3), block, lds, s, (cx<T>*)U, (const cx<T>*)goct, g,          \
+                       (const cx<T>*)tw1);                                                                    \
+    return hipGetLastError();                                                                                 \
+  }
+  VIE_XY(0)
+  VIE_XY(1)
+  VIE_XY(2)
+#undef VIE_XY
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -496,6 +629,8 @@ hipError_t allow_lds_xy64() {
   if ((e = hipFuncSetAttribute((const void*)k_xy64<T, 1>, attr, (int)xy64_lds<T>(1)))) return e;
   if ((e = hipFuncSetAttribute((const void*)k_xy64_batch_single<T, 0>, attr, (int)xy64_lds<T>(0)))) return e;
   if ((e = hipFuncSetAttribute((const void*)k_xy64_batch_single<T, 1>, attr, (int)xy64_lds<T>(1)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_xy64<T, 2>, attr, (int)xy64_lds<T>(2)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_xy64_batch_single<T, 2>, attr, (int)xy64_lds<T>(2)))) return e;
   return hipFuncSetAttribute((const void*)k_xy64_batch<T, kBatchVariant<T>>, attr,
                              (int)xy64_lds<T>(kBatchVariant<T>));
 }

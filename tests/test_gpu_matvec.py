@@ -33,10 +33,11 @@ H, K0, EPSB = 0.05, inputs.K0, inputs.EPS_B
 
 # grids spanning several tiles and ragged tails (pencils per workgroup, column
 # chunks, every z-transform shape: circulant lengths 512, 1024, 2048 along z and
-# the 64 x 64 cross-section kernel via (17, 32, 6); non-power-of-two n in every
+# the 64 x 64 cross-section kernel via (17, 32, 6) and, with a z circulant of 8
+# (one workgroup per plane pair), (20, 18, 3); non-power-of-two n in every
 # axis), plus the degenerate single voxel
 GRIDS = [(8, 8, 32), (5, 7, 37), (3, 32, 20), (12, 20, 24), (2, 3, 4), (1, 1, 1), (1, 1, 9), (32, 1, 3),
-         (3, 5, 200), (7, 1, 129), (2, 3, 300), (2, 2, 600), (17, 32, 6)]
+         (3, 5, 200), (7, 1, 129), (2, 3, 300), (2, 2, 600), (17, 32, 6), (20, 18, 3)]
 
 
 @pytest.fixture(scope="module", params=GRIDS, ids=lambda g: "x".join(map(str, g)))
@@ -230,6 +231,34 @@ def _sampled_expectation(wg, nnz, nout, seed):
     return x, outs, want
 
 
+@pytest.mark.parametrize("n", [(17, 32, 6), (20, 18, 3)], ids=lambda g: "x".join(map(str, g)))
+def test_every_xy_variant_matches_the_oracle(n):
+    """Each 64 x 64 xy-pass variant, FP64 and FP32, gives the oracle's whole product
+    (both launch paths: one plane per workgroup, and one plane pair per workgroup)."""
+    vie = _dev()
+    rng = np.random.default_rng(3 + sum(n))
+    kap = mv.kappa_of(H, K0, EPSB)
+    spec = mv.spectrum(green.green_table(n, kap))
+    eps = EPSB + 10 * rng.random(n) + 1j * rng.random(n)
+    eps[rng.random(n) < 0.3] = EPSB
+    chi = mv.contrast(eps, EPSB)
+    plan = vie.Plan(n, H, K0, EPSB, fp32=True)
+    plan.set_contrast(_t(eps))
+    x = _cvec(rng, (3,) + n)
+    want = mv.matvec_fft(spec, chi, x)
+    for precision in (0, 1):
+        for xyv in (0, 1, 2):
+            plan.set_tune(precision, xyv, 0)
+            assert plan.tune(precision)["xy_variant"] == xyv
+            if precision == 0:
+                y = plan.matvec(_t(x)).cpu().numpy()
+            else:
+                y = plan.matvec_c64(_t(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+            err = np.max(np.abs(y - want)) / np.max(np.abs(want))
+            print(n, precision, xyv, f"{err:.2e}")
+            assert err < (1e-12 if precision == 0 else 5e-6)
+
+
 TUNED_GRIDS = {
     "32x32x512_M3_1024": lambda: inputs.strip_long(d=2),
     "24x20x200_M3_512": lambda: inputs.Waveguide(n=(24, 20, 200), h=0.025, core_x=(4, 20), core_y=(6, 14),
@@ -253,7 +282,7 @@ def test_every_launch_shape_matches_the_oracle(grid):
     xt32 = _t(x, torch.complex64)
     i = tuple(outs.T)
     for precision in (0, 1):
-        for xyv in (0, 1):
+        for xyv in (0, 1, 2):
             for zp in pencils[precision]:
                 plan.set_tune(precision, xyv, zp)
                 assert plan.tune(precision) == {"xy_variant": xyv, "z_pencils": zp}
