@@ -30,6 +30,16 @@ template <typename P> using gptr = __attribute__((address_space(1))) P*;
 template <typename P> using gptr = P*;
 #endif
 
+// The thread index as a value the compiler cannot see through.  Persistent
+// kernels take it once per work item: otherwise every thread-dependent LDS and
+// global address of the body is hoisted out of the item loop and held in
+// registers across it (about a hundred VGPRs).
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
 template <typename V> __device__ __forceinline__ V cmul(V a, V b) {

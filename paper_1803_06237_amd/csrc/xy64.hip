@@ -401,23 +401,62 @@ __device__ __forceinline__ void xy64_half(cx<T>* __restrict__ U, const cx<T>* __
 }
 
 
+// Inputs of the two row tasks of group q for plane P (zero outside the grid),
+// from clamped, always valid addresses: no branches, one memory latency.
+template <typename T>
+__device__ __forceinline__ void wide_load_rows(const cx<T>* P, int q, int a, int n1, int n2, cx<T> (&in)[2][4]) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int ft = q + 64 * t < 96 ? q + 64 * t : q;
+    const int c = ft >> 5, y = ft & 31;
+    const int yc = y < n2 ? y : n2 - 1;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int x = a + 8 * b;
+      const cx<T> v = P[(c * n2 + yc) * n1 + (x < n1 ? x : n1 - 1)];
+      const bool ok = x < n1 && y < n2;
+      in[t][b] = cx<T>{ok ? v.x : (T)0, ok ? v.y : (T)0};
+    }
+  }
+}
+
+// Green values of column kx (folded index k1) at ky = a + 8 m: the six entries
+// of the folded octant
+template <typename T>
+__device__ __forceinline__ void wide_load_green(const cx<T>* G3, const Geom& g, int k1, int a, int m, cx<T>* out) {
+  const int ky = a + 8 * m;
+  const int k2 = ky <= 32 ? ky : 64 - ky;
+  const cx<T>* Gp = G3 + ((long)k2 * g.H1 + k1) * 6;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) out[e] = Gp[e];
+}
+
 template <typename T>
 __device__ __forceinline__ void xy64_wide(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
                                           const cx<T>* __restrict__ tw64, int kz_first, int nplanes, int kz_second,
                                           cx<T>* R) {
-  const int tid = threadIdx.x;
-  const int a = tid & 7;
-  const int q = tid >> 3;                            // 0..63
-  const int f = q & 3;
   const int n1 = g.n1, n2 = g.n2;
-  cx<T>* X = R + kFullLdsVals + q * 64;              // this group's exchange area
   cx<T> w[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = tw64[a * k];
+  for (int k = 0; k < 8; ++k) w[k] = tw64[(threadIdx.x & 7) * k];
   const cx<T> zero{(T)0, (T)0};
   for (int pi = 0; pi < nplanes; ++pi) {
+    // thread indices taken afresh per plane (see opaque_tid)
+    const int tid = nplanes > 1 ? opaque_tid() : (int)threadIdx.x;
+    const int a = tid & 7;
+    const int q = tid >> 3;                          // 0..63
+    const int f = q & 3;
+    cx<T>* X = R + kFullLdsVals + q * 64;            // this group's exchange area
+    const int kx = q;                                // column of stage B
+    const int k1 = kx <= 32 ? kx : 64 - kx;
+    const T s1 = kx <= 32 ? (T)1 : (T)-1;
     const int kz = pi == 0 ? kz_first : kz_second;
     cx<T>* P = U + (long)kz * 3 * n1 * n2;
+    const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
+    const T s3 = kz <= g.M3 / 2 ? (T)1 : (T)-1;
+    const cx<T>* G3 = goct + (long)k3 * g.H2 * g.H1 * 6;
+    cx<T> in[2][4];
+    wide_load_rows<T>(P, q, a, n1, n2, in);
     // ---- A: forward x transforms; row task ft = q + 64 t (t = 0, 1) is
     // (component ft / 32, row ft % 32) while ft < 96
 #pragma unroll
@@ -427,10 +466,7 @@ __device__ __forceinline__ void xy64_wide(cx<T>* __restrict__ U, const cx<T>* __
         const int c = ft >> 5, y = ft & 31;
         cx<T> v[8];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int x = a + 8 * b;
-          v[b] = (x < n1 && y < n2) ? P[(c * n2 + y) * n1 + x] : zero;
-        }
+        for (int b = 0; b < 4; ++b) v[b] = in[t][b];
 #pragma unroll
         for (int b = 4; b < 8; ++b) v[b] = zero;
         fft64<T, false>(v, w, a, X, f);           // v[m] = X[kx = a + 8 m]
@@ -439,12 +475,14 @@ __device__ __forceinline__ void xy64_wide(cx<T>* __restrict__ U, const cx<T>* __
       }
     }
     __syncthreads();
-    // ---- B: column kx = q of all three components
+    // ---- B: column kx = q of all three components.  The Green values of ky =
+    // a + 8 m come through a ring of two batches: the first two are loaded
+    // before the forward transforms, batch m + 2 as batch m is used.
     {
-      const int kx = q;
-      const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
-      const T s3 = kz <= g.M3 / 2 ? (T)1 : (T)-1;
-      const cx<T>* G3 = goct + (long)k3 * g.H2 * g.H1 * 6;
+      constexpr int kRing = 2;
+      cx<T> G[kRing][6];
+#pragma unroll
+      for (int m = 0; m < kRing; ++m) wide_load_green<T>(G3, g, k1, a, m, G[m]);
       cx<T> v[3][8];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -454,20 +492,18 @@ __device__ __forceinline__ void xy64_wide(cx<T>* __restrict__ U, const cx<T>* __
         for (int b = 4; b < 8; ++b) v[c][b] = zero;
         fft64<T, false>(v[c], w, a, X, f);        // v[c][m] = Y[ky = a + 8 m]
       }
-      const int k1 = kx <= 32 ? kx : 64 - kx;
-      const T s1 = kx <= 32 ? (T)1 : (T)-1;
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int ky = a + 8 * m;
-        const int k2 = ky <= 32 ? ky : 64 - ky;
         const T s2 = ky <= 32 ? (T)1 : (T)-1;
-        const cx<T>* Gp = G3 + ((long)k2 * g.H1 + k1) * 6;
-        const cx<T> gxx = Gp[0], gyy = Gp[3], gzz = Gp[5];
-        const cx<T> gxy = cscale(Gp[1], s1 * s2), gxz = cscale(Gp[2], s1 * s3), gyz = cscale(Gp[4], s2 * s3);
+        cx<T>* Gm = G[m % kRing];
+        const cx<T> gxx = Gm[0], gyy = Gm[3], gzz = Gm[5];
+        const cx<T> gxy = cscale(Gm[1], s1 * s2), gxz = cscale(Gm[2], s1 * s3), gyz = cscale(Gm[4], s2 * s3);
         const cx<T> ux = v[0][m], uy = v[1][m], uz = v[2][m];
         v[0][m] = cadd(cadd(cmul(gxx, ux), cmul(gxy, uy)), cmul(gxz, uz));
         v[1][m] = cadd(cadd(cmul(gxy, ux), cmul(gyy, uy)), cmul(gyz, uz));
         v[2][m] = cadd(cadd(cmul(gxz, ux), cmul(gyz, uy)), cmul(gzz, uz));
+        if (m + kRing < 8) wide_load_green<T>(G3, g, k1, a, m + kRing, Gm);
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {

@@ -355,16 +355,6 @@ hipError_t launch_z4(int which, const Geom& g, int P, const void* x, void* y, co
   return hipErrorNotSupported;
 }
 
-// The thread index as a value the compiler cannot see through.  The persistent
-// kernels take it once per item: otherwise every thread-dependent LDS and
-// twiddle address of the body is hoisted out of the item loop and held in
-// registers across it (about a hundred VGPRs).
-__device__ __forceinline__ int opaque_tid() {
-  int t = threadIdx.x;
-  asm volatile("" : "+v"(t));
-  return t;
-}
-
 __device__ __forceinline__ int find_sys(const int* prefix, int nsys, int item) {
   int lo = 0, hi = nsys - 1;
   while (lo < hi) {
