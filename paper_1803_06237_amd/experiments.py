@@ -200,3 +200,172 @@ def mixed_vs_fp64(degrees: Sequence[int] = DEGREES, tol: float = 1e-8, ref_tol: 
         out["R_mixed"].append(R["mixed"])
         out["rel_dR"].append(abs(R["mixed"] - R["fp64"]) / R["fp64"])
     return out
+
+
+# ---------------------------------------------------------------------------
+# The strip study of Section V-A on the paper's own geometry (Section II-A).
+# ---------------------------------------------------------------------------
+
+STRIP_LENGTHS = tuple(round(0.45 * k, 2) for k in range(1, 22))    # 450 .. 9450 nm in steps of 450 nm
+LAMBDA_SI = inputs.LAMBDA0 / math.sqrt(inputs.EPS_SI)                # wavelength in the core, um
+# Absorber length (silicon wavelengths) for R = 1e-8 with electric currents only, as the
+# paper's table of Section V-A gives it (d = 0 and some d = 1 entries are extrapolations there)
+PAPER_LENGTH_FOR_1E8 = {1e-25: {0: 13000.0, 1: 49.0, 2: 9.5, 3: 7.2}, 1e-10: {0: 4500.0, 1: 32.0, 2: 7.1, 3: 6.2}}
+
+
+def strip_axis_field(wg: inputs.Waveguide, w: np.ndarray) -> np.ndarray:
+    """E over the lossless part of the strip's centre line (Section V-A measures on
+    y = 250 nm, z = 100 nm, a corner shared by four voxel columns): the mean of those four
+    columns, E = J / (eps_r - 1) with J = w h^{-3/2} (constants dropped).  Shape (3, length)."""
+    i1, i2 = wg.n[0] // 2, wg.n[1] // 2
+    lo, hi = wg.lossless_range()
+    eps_r = wg.eps_core / wg.eps_b
+    J = sum(w[:, a, b, lo:hi] for a in (i1 - 1, i1) for b in (i2 - 1, i2)) / 4.0
+    return J / (wg.h ** 1.5 * (eps_r - 1.0))
+
+
+def length_for_reflection(lengths: Sequence[float], R: Sequence[float], target: float = 1e-8):
+    """Absorber length at which R(L) first falls to target: linear interpolation of log R
+    against log L between the bracketing points; beyond the last point, the straight line
+    through the last two points is extended (as the paper extrapolates some of its entries).
+    None when R never decreases toward target."""
+    L = np.log(np.asarray(lengths, dtype=float))
+    y = np.log(np.maximum(np.asarray(R, dtype=float), 1e-300))
+    t = math.log(target)
+    for i in range(len(L)):
+        if y[i] <= t:
+            if i == 0:
+                return float(lengths[0])
+            f = (t - y[i - 1]) / (y[i] - y[i - 1])
+            return float(math.exp(L[i - 1] + f * (L[i] - L[i - 1])))
+    if len(L) >= 2 and y[-1] < y[-2]:
+        slope = (y[-1] - y[-2]) / (L[-1] - L[-2])
+        return float(math.exp(L[-1] + (t - y[-1]) / slope))
+    return None
+
+
+def analyse_reflection(lengths: Sequence[float], R: Sequence[float], d: int, r_rt: float, l_ref: float,
+                       lam: float = LAMBDA_SI, target: float = 1e-8) -> dict:
+    """Post-processing of one R(L) curve of Section V-A.  Points within a factor 2 of the
+    reference length are left out (E(L) approaches the reference there, which steepens
+    R artificially), as are points below ten times the floor max(R_rt, 1e-11) (the
+    stagnation the paper describes).  From L >= 2 silicon wavelengths on, the log-log
+    slope is fitted (predicted -2(d+1), Section IV-C).  The length giving R = target is
+    interpolated where the kept curve crosses it, otherwise extrapolated from its last
+    point with the fitted slope and, for comparison, with the predicted one (the paper
+    extrapolates some of its entries).  Lengths are returned in silicon wavelengths."""
+    L = np.asarray(lengths, dtype=float)
+    R = np.asarray(R, dtype=float)
+    keep = L <= l_ref / 2 + 1e-9
+    Lk, Rk = L[keep], R[keep]
+    fit = (Lk >= 2 * lam) & (Rk > 10 * max(r_rt, 1e-11))
+    slope = float(np.polyfit(np.log(Lk[fit]), np.log(Rk[fit]), 1)[0]) if fit.sum() >= 2 else None
+    out = {"slope": slope, "predicted_slope": -2 * (d + 1), "fit_points": int(fit.sum())}
+    crossed = np.nonzero(Rk <= target)[0]
+    if len(crossed):
+        i = crossed[0] + 1
+        out["length_lambda"] = length_for_reflection(Lk[:i], Rk[:i], target) / lam
+        out["method"] = "interpolated"
+        return out
+
+    def extrapolate(s):
+        if s is None or s >= 0:
+            return None
+        return float(Lk[-1] * math.exp((math.log(target) - math.log(Rk[-1])) / s)) / lam
+
+    out["length_lambda"] = extrapolate(slope)
+    out["length_lambda_predicted_slope"] = extrapolate(-2.0 * (d + 1))
+    out["method"] = "extrapolated"
+    return out
+
+
+def strip_reflection_study(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: Sequence[int] = DEGREES,
+                           lengths: Sequence[float] = STRIP_LENGTHS, precision: int = 1, tol: float = 1e-8,
+                           restart: int = 50, inner_restart: int = 20, inner_tol: float = 1e-3,
+                           strip_len: int = inputs.STRIP_LEN, progress=None) -> dict:
+    """Section V-A on the strip of Section II-A: for each round-trip reflection and profile
+    degree, the guide with every absorber length is solved in one vie_solve_batch call
+    (complex-source dipole, electric currents only); R(L) against the longest absorber on
+    the centre line, the fitted log-log slope (predicted -2(d+1), Section IV-C) and the
+    length that gives R = 1e-8 in silicon wavelengths (the paper's table).  The grid
+    depends on L only, so one plan per length serves every (R_rt, d) with its own
+    contrast.  progress, if given, is called with each finished run."""
+    import torch
+
+    def guide(L, d, r_rt):
+        wg = inputs.strip_paper(L, d, r_rt)
+        if strip_len != inputs.STRIP_LEN:
+            wg = inputs.Waveguide(n=(wg.n[0], wg.n[1], strip_len + wg.n_abs), h=wg.h, core_x=wg.core_x,
+                                  core_y=wg.core_y, core_z=(0, strip_len + wg.n_abs), n_abs=wg.n_abs, d=d,
+                                  sigma_max=wg.sigma_max, ends="right")
+        return wg
+
+    Lref = max(lengths)
+    out = {"lengths_um": list(lengths), "lambda_si_um": LAMBDA_SI, "strip_voxels": strip_len, "runs": {}}
+    t0 = time.perf_counter()
+    plans = {}
+    for L in lengths:
+        wg = guide(L, 0, r_rts[0])
+        plans[L] = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    out["plan_seconds"] = round(time.perf_counter() - t0, 3)
+    try:
+        for r_rt in r_rts:
+            for d in degrees:
+                t0 = time.perf_counter()
+                wgs, bs = [], []
+                for L in lengths:
+                    wg = guide(L, d, r_rt)
+                    plans[L].set_contrast(torch.from_numpy(wg.eps()).cuda())
+                    bs.append(plans[L].rhs(torch.from_numpy(inputs.strip_paper_source(wg)).cuda()))
+                    wgs.append(wg)
+                torch.cuda.synchronize()
+                setup_s = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                xs, infos, code = vie.solve_batch([plans[L] for L in lengths], bs, tol=tol, restart=restart,
+                                                  precision=precision, inner_restart=inner_restart,
+                                                  inner_tol=inner_tol)
+                torch.cuda.synchronize()
+                solve_s = time.perf_counter() - t0
+                fields = {L: strip_axis_field(wg, x.cpu().numpy()) for L, wg, x in zip(lengths, wgs, xs)}
+                ref = fields[Lref]
+                Ls = [L for L in lengths if L != Lref]
+                R = [float(np.sum(np.abs(ref - fields[L]) ** 2) / np.sum(np.abs(ref) ** 2)) for L in Ls]
+                run = {"r_rt": r_rt, "d": d, "status": code, "setup_seconds": round(setup_s, 3),
+                       "solve_seconds": round(solve_s, 3), "unknowns": sum(3 * wg.N for wg in wgs),
+                       "max_rel_res": max(i["rel_res_true"] for i in infos),
+                       "outer_iters": [i["iters"] for i in infos], "inner_iters": [i["inner_iters"] for i in infos],
+                       "R": R, "paper_length_for_1e-8_lambda": PAPER_LENGTH_FOR_1E8.get(r_rt, {}).get(d)}
+                run.update(analyse_reflection(Ls, R, d, r_rt, Lref))
+                out["runs"][f"{r_rt:g}/{d}"] = run
+                if progress is not None:
+                    progress(run)
+                del xs, bs
+    finally:
+        for p in plans.values():
+            p.close()
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="experiments of the paper run on the GPU path")
+    ap.add_argument("which", choices=["strip"], help="strip: the reflection study of Section V-A")
+    ap.add_argument("--out", default=None, help="write the JSON result here")
+    ap.add_argument("--quick", action="store_true", help="every other absorber length")
+    a = ap.parse_args()
+    lengths = STRIP_LENGTHS[::2] if a.quick else STRIP_LENGTHS
+    if lengths[-1] != STRIP_LENGTHS[-1]:
+        lengths = tuple(lengths) + (STRIP_LENGTHS[-1],)
+
+    def show(r):
+        def fmt(v):
+            return None if v is None else round(v, 2)
+        print(f"{r['r_rt']:g}/{r['d']}", "slope", fmt(r["slope"]), "pred", r["predicted_slope"],
+              "L(1e-8)/lambda", fmt(r["length_lambda"]), r["method"], "paper", r["paper_length_for_1e-8_lambda"],
+              "solve s", r["solve_seconds"], "max res", f"{r['max_rel_res']:.1e}", flush=True)
+
+    res = strip_reflection_study(lengths=lengths, progress=show)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(json.dumps(res, indent=1))

@@ -66,6 +66,13 @@ class Waveguide:
     # optional sidewall roughness: per-z integer offsets of the two x-sidewalls
     rough_lo: Optional[np.ndarray] = None
     rough_hi: Optional[np.ndarray] = None
+    # which ends of the core carry an absorber: "both", or "right" (high-z end
+    # only, as for the directional source of Section V-A)
+    ends: str = "both"
+
+    def __post_init__(self):
+        if self.ends not in ("both", "right"):
+            raise ValueError("ends must be 'both' or 'right'")
 
     @property
     def N(self) -> int:
@@ -78,8 +85,9 @@ class Waveguide:
         z0, z1 = self.core_z
         L = self.n_abs
         if L > 0:
-            for k in range(z0, z0 + L):          # left absorber: inner interface at z0+L
-                u[k] = (z0 + L - k - 0.5) / L
+            if self.ends == "both":
+                for k in range(z0, z0 + L):      # left absorber: inner interface at z0+L
+                    u[k] = (z0 + L - k - 0.5) / L
             for k in range(z1 - L, z1):          # right absorber: inner interface at z1-L
                 u[k] = (k - (z1 - L) + 0.5) / L
         return u
@@ -89,9 +97,15 @@ class Waveguide:
         m = np.zeros(n3, dtype=bool)
         z0, z1 = self.core_z
         if self.n_abs > 0:
-            m[z0:z0 + self.n_abs] = True
+            if self.ends == "both":
+                m[z0:z0 + self.n_abs] = True
             m[z1 - self.n_abs:z1] = True
         return m
+
+    def lossless_range(self) -> Tuple[int, int]:
+        """z index range [lo, hi) of the core outside the absorbers."""
+        z0, z1 = self.core_z
+        return (z0 + (self.n_abs if self.ends == "both" else 0), z1 - self.n_abs)
 
     def core_mask(self) -> np.ndarray:
         n1, n2, n3 = self.n
@@ -145,6 +159,41 @@ def dipole_field(n: Sequence[int], h: float, r0: Sequence[float], p: Sequence[co
     r = np.sqrt(X * X + Y * Y + Z * Z)
     if np.any(r == 0):
         raise ValueError("dipole coincides with a voxel centre")
+    nx, ny, nz = X / r, Y / r, Z / r
+    p = np.asarray(p, dtype=np.complex128)
+    ndp = nx * p[0] + ny * p[1] + nz * p[2]
+    ph = np.exp(1j * k * r)
+    far = k * k / r
+    near = 1.0 / r ** 3 - 1j * k / r ** 2
+    out = np.empty((3, n1, n2, n3), dtype=np.complex128)
+    for a, na in enumerate((nx, ny, nz)):
+        out[a] = ph * (far * (p[a] - na * ndp) + near * (3.0 * na * ndp - p[a]))
+    return out
+
+
+def complex_source_dipole_field(n: Sequence[int], h: float, r0: Sequence[float], p: Sequence[complex],
+                                k: float, shift: Sequence[float]) -> np.ndarray:
+    """Field of a dipole p at the complex location r0 + i*shift, at voxel centres.
+
+    The dipole field above continued analytically to a complex source point
+    (Section II: the source is moved off the real axis so that it radiates a
+    beam).  With ``d = r - r0 - i*shift`` the distance is ``R = sqrt(d.d)`` on the
+    principal branch (Re R >= 0), ``n = d/R``, and the textbook expression is
+    evaluated with these complex values.  For ``exp(-i omega t)`` a shift of +b
+    along an axis makes a beam travelling in the +axis direction (the paper's
+    -j*b for ``exp(+j omega t)``).  Away from the disc |rho| <= |shift| in the
+    plane through r0 normal to the shift (where R is 0 on the rim and changes
+    branch inside) the field solves the same Maxwell equations as a real dipole.
+    Returns shape (3, n1, n2, n3) complex128.
+    """
+    n1, n2, n3 = n
+    c = [h * (np.arange(nn) + 0.5) for nn in (n1, n2, n3)]
+    s = np.asarray(shift, dtype=float)
+    X, Y, Z = np.meshgrid(c[0] - r0[0] - 1j * s[0], c[1] - r0[1] - 1j * s[1], c[2] - r0[2] - 1j * s[2],
+                          indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)              # principal branch, Re >= 0
+    if np.any(np.abs(r) < 1e-12 * h):
+        raise ValueError("a voxel centre lies on the complex source's branch rim")
     nx, ny, nz = X / r, Y / r, Z / r
     p = np.asarray(p, dtype=np.complex128)
     ndp = nx * p[0] + ny * p[1] + nz * p[2]
@@ -247,3 +296,29 @@ def rough_strip(seed: int, n3: int = 256, n_abs: int = 40, d: int = 2,
     hi[absz] = 0
     wg.rough_lo, wg.rough_hi = lo, hi
     return wg
+
+
+H_PAPER = 0.05 / 3.0                 # 50/3 nm voxels (Section II-A)
+STRIP_LEN = 810                      # 13.5 um lossless strip in voxels (Section II-A)
+
+
+def strip_paper(length_um: float, d: int, r_rt: float = 1e-10) -> Waveguide:
+    """The strip of Section II-A: a 500 x 200 nm silicon core 13.5 um long in silica,
+    voxels of 50/3 nm (30 x 12 across, 810 along), with one absorber of length
+    length_um appended at the far end (Section V-A).  The grid is the core itself."""
+    n_abs = int(round(length_um / H_PAPER))
+    n3 = STRIP_LEN + n_abs
+    sig = sigma_max_for(r_rt, d, n_abs * H_PAPER)
+    return Waveguide(n=(30, 12, n3), h=H_PAPER, core_x=(0, 30), core_y=(0, 12), core_z=(0, n3), n_abs=n_abs,
+                     d=d, sigma_max=sig, ends="right")
+
+
+def strip_paper_source(wg: Waveguide) -> np.ndarray:
+    """Incident field of Section II: a dipole across the strip's width (the dominant TE
+    mode's polarisation) on the centre line, a quarter silicon wavelength from the
+    near end, at the complex location shifted by one silicon wavelength along the
+    guide (a beam travelling away from the near end)."""
+    lam_si = LAMBDA0 / math.sqrt(wg.eps_core)
+    r0 = (0.5 * wg.n[0] * wg.h, 0.5 * wg.n[1] * wg.h, wg.core_z[0] * wg.h + lam_si / 4.0)
+    kb = wg.k0 * math.sqrt(wg.eps_b)
+    return complex_source_dipole_field(wg.n, wg.h, r0, (1, 0, 0), kb, (0.0, 0.0, lam_si))
