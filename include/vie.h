@@ -300,6 +300,48 @@ int vie_nn_conv_test(int mode, const int dims[3], int taps, int cin, int cout, c
                      float* out, int relu, void* hip_stream);
 const char* vie_net_last_error(vie_net_t net);
 
+/*
+ * JM-VIE: electric and magnetic currents (Section III, the coupled system
+ * (I - M T)(J, M) = C M (E_inc, H_inc) with T = [[N, -c_e K], [c_m K, N]],
+ * K = curl S; Section IV-B, an absorber that also carries magnetic loss).
+ * Magnetic unknowns are in impedance units (w_m = eta w~_m) and the time
+ * dependence is exp(-i omega t), which makes the operator
+ *   y_e = x_e - M_eps (N x_e + i kappa K x_m),
+ *   y_m = x_m - M_mu  (-i kappa K x_e + N x_m),
+ * kappa = k_b h, M_mu = (mu_r - 1)/mu_r, K the Galerkin table of curl S at unit
+ * voxel edge.  Vectors hold 6N values: electric [3][n1][n2][n3], then magnetic.
+ * The right-hand side is the caller's, e.g. h^{3/2} (M_eps e_inc, M_mu eta h_inc)
+ * with eta h_inc = curl e_inc / (i k_b).
+ *
+ * vie_curl_table -- host-only, FP64: K^{ab}(m) for 0 <= m_d < grid[d], out
+ *   [3][n1][n2][n3] for the components xy, xz, yz (K^{ba} = -K^{ab}, K^{aa} = 0);
+ *   negating m_d multiplies K^{ab} by -1 exactly when d is neither a nor b.
+ * vie_jm_enable -- builds the spectrum of K and the JM buffers (about 6 M1 M2 M3
+ *   complex values per precision) and sets mu_r = 1 everywhere.  Idempotent.
+ *   VIE_EINVAL when M1 M2 > 4096.  Synchronises.
+ * vie_jm_set_permeability -- mu_r: device, N relative permeabilities (copied).
+ *   VIE_EINVAL for a zero or non-finite entry.  Synchronises.
+ * vie_jm_rhs -- b = h^{3/2} (M_eps e_inc, M_mu etah_inc): e_inc and etah_inc
+ *   device, 3N values each (fields at the voxel centres, eta h_inc in the units
+ *   of e_inc); b device, 6N values.  Async.
+ * vie_jm_matvec / vie_jm_matvec_c64 -- y = (I - M T~) x in FP64 / FP32 (the
+ *   latter needs VIE_WITH_FP32); device, 6N values each, no overlap.  Async.
+ * vie_jm_residual -- r = b - (I - M T~) x, FP64.  Async.
+ * vie_jm_solve -- GMRES(restart) (precision 0) or FP32-inner / FP64-outer
+ *   flexible GMRES (precision 1) on the 6N unknowns; x in/out (use_x0), tol on
+ *   the true FP64 residual relative to ||b||, info as for vie_solve.
+ * All take VIE_ESTATE before vie_jm_enable and vie_set_contrast.
+ */
+int vie_curl_table(const int grid[3], double kappa, vie_c128* out, int nthreads);
+int vie_jm_enable(vie_plan_t plan);
+int vie_jm_set_permeability(vie_plan_t plan, const vie_c128* mu_r);
+int vie_jm_rhs(vie_plan_t plan, const vie_c128* e_inc, const vie_c128* etah_inc, vie_c128* b);
+int vie_jm_matvec(vie_plan_t plan, const vie_c128* x, vie_c128* y);
+int vie_jm_matvec_c64(vie_plan_t plan, const vie_c64* x, vie_c64* y);
+int vie_jm_residual(vie_plan_t plan, const vie_c128* x, const vie_c128* b, vie_c128* r);
+int vie_jm_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts* opts,
+                 vie_solve_info* info);
+
 /* Message for the last failing call on this plan (plan = NULL: on this thread). */
 const char* vie_last_error(vie_plan_t plan);
 

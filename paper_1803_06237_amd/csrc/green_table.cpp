@@ -280,7 +280,67 @@ cd face_orthogonal(int a, int b, const long m[3], double kappa) {
   return acc;
 }
 
+// Q_k(m) of the curl table: a signed unit step along k (+1 on [m_k, m_k+1],
+// -1 on [m_k-1, m_k]) and the tent along the two other axes
+cd curl_q(int k, const long m[3], double kappa) {
+  const int p0 = (k + 1) % 3, p1 = (k + 2) % 3;
+  cd acc = 0;
+  for (int sk = 0; sk < 2; ++sk)
+    for (int s0 = 0; s0 < 2; ++s0)
+      for (int s1 = 0; s1 < 2; ++s1) {
+        long lo[3];
+        Lin w[3];
+        lo[k] = sk == 0 ? m[k] : m[k] - 1;
+        w[k] = Lin{sk == 0 ? 1.0 : -1.0, 0.0};
+        tent(m[p0], s0, &lo[p0], &w[p0]);
+        tent(m[p1], s1, &lo[p1], &w[p1]);
+        acc += box3(lo, w, kappa);
+      }
+  return acc;
+}
+
+template <typename F>
+void run_threads(int nthreads, long count, F&& body) {
+  std::atomic<long> next{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nthreads; ++t)
+    th.emplace_back([&] {
+      for (;;) {
+        long i = next.fetch_add(1);
+        if (i >= count) break;
+        body(i);
+      }
+    });
+  for (auto& t : th) t.join();
+}
+
 }  // namespace
+
+// Galerkin table of K = curl S (the magnetic-electric coupling of the JM-VIE,
+// Section III): with Phi_j = int_{V_j} G and the divergence theorem on the
+// testing voxel, K^{ab}(m) = eps_{akb} Q_k(m) (h = 1, k the axis other than a
+// and b), Q_k(m) = int G(d) [1_{[m_k,m_k+1]} - 1_{[m_k-1,m_k]}](d_k)
+// prod_{l != k} (1 - |d_l - m_l|) dd.  Output out[3][n1][n2][n3] for the
+// components (0,1), (0,2), (1,2): -Q_2, +Q_1, -Q_0.  K^{ba} = -K^{ab}; Q_k is odd
+// in m_k and even in the other offsets.
+int curl_table(const int n[3], double kappa, std::complex<double>* out, int nthreads) {
+  const long n1 = n[0], n2 = n[1], n3 = n[2];
+  const long N = n1 * n2 * n3;
+  (void)rules();
+  if (nthreads <= 0) nthreads = (int)std::max(1u, std::thread::hardware_concurrency());
+  run_threads(nthreads, n1 * n2, [&](long row) {
+    long m[3];
+    m[0] = row / n2;
+    m[1] = row % n2;
+    for (m[2] = 0; m[2] < n3; ++m[2]) {
+      const long idx = (m[0] * n2 + m[1]) * n3 + m[2];
+      out[0 * N + idx] = -curl_q(2, m, kappa);
+      out[1 * N + idx] = curl_q(1, m, kappa);
+      out[2 * N + idx] = -curl_q(0, m, kappa);
+    }
+  });
+  return 0;
+}
 
 int green_table(const int n[3], double kappa, std::complex<double>* out, int nthreads) {
   const long n1 = n[0], n2 = n[1], n3 = n[2];

@@ -318,7 +318,7 @@ __global__ __launch_bounds__(1024) void k_fft_lines(double2* __restrict__ F, int
 }
 
 __global__ void k_octant(const double2* __restrict__ F, double2* __restrict__ g64, float2* __restrict__ g32,
-                         Geom g, int comp, double invP) {
+                         Geom g, int comp, int ncomp, double invP) {
   const long H = (long)g.H1 * g.H2 * g.H3;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < H; i += (long)gridDim.x * blockDim.x) {
     const int k1 = (int)(i % g.H1);
@@ -327,8 +327,8 @@ __global__ void k_octant(const double2* __restrict__ F, double2* __restrict__ g6
     double2 v = F[((long)k1 * g.M2 + k2) * g.M3 + k3];
     v.x *= invP;
     v.y *= invP;
-    g64[i * 6 + comp] = v;
-    if (g32) g32[i * 6 + comp] = float2{(float)v.x, (float)v.y};
+    g64[i * ncomp + comp] = v;
+    if (g32) g32[i * ncomp + comp] = float2{(float)v.x, (float)v.y};
   }
 }
 
@@ -365,7 +365,25 @@ hipError_t launch_spectrum(const Geom& g, const double2* table_dev, double2* ful
     if ((e = hipGetLastError())) return e;
     for (int axis = 2; axis >= 0; --axis)
       if ((e = fft_axis(full_tmp, g, axis, tw64[axis], s))) return e;
-    hipLaunchKernelGGL(k_octant, dim3(1024), dim3(256), 0, s, full_tmp, goct64, goct32, g, c, invP);
+    hipLaunchKernelGGL(k_octant, dim3(1024), dim3(256), 0, s, full_tmp, goct64, goct32, g, c, 6, invP);
+    if ((e = hipGetLastError())) return e;
+  }
+  return hipSuccess;
+}
+
+// The spectrum of K = curl S (JM-VIE) on the same octant: components (0,1), (0,2),
+// (1,2), each odd along its third axis c (k_embed with parities (c, none)).
+hipError_t launch_curl_spectrum(const Geom& g, const double2* ktable_dev, double2* full_tmp, double2* koct64,
+                                float2* koct32, const double2* const tw64[3], hipStream_t s) {
+  static const int odd_axis[3] = {2, 1, 0};
+  const double invP = 1.0 / ((double)g.M1 * g.M2 * g.M3);
+  hipError_t e;
+  for (int c = 0; c < 3; ++c) {
+    hipLaunchKernelGGL(k_embed, dim3(2048), dim3(256), 0, s, ktable_dev, full_tmp, g, c, odd_axis[c], -1);
+    if ((e = hipGetLastError())) return e;
+    for (int axis = 2; axis >= 0; --axis)
+      if ((e = fft_axis(full_tmp, g, axis, tw64[axis], s))) return e;
+    hipLaunchKernelGGL(k_octant, dim3(1024), dim3(256), 0, s, full_tmp, koct64, koct32, g, c, 3, invP);
     if ((e = hipGetLastError())) return e;
   }
   return hipSuccess;

@@ -52,6 +52,23 @@ std::shared_ptr<const std::vector<std::complex<double>>> cached_table(const int 
   return t;
 }
 
+std::shared_ptr<const std::vector<std::complex<double>>> cached_curl_table(const int n[3], double kappa) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, double>, std::shared_ptr<const std::vector<std::complex<double>>>> cache;
+  const auto key = std::make_tuple(n[0], n[1], n[2], kappa);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  auto t = std::make_shared<std::vector<std::complex<double>>>((size_t)3 * n[0] * n[1] * n[2]);
+  vie::curl_table(n, kappa, t->data(), 0);
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache.size() >= 16) cache.clear();
+  cache[key] = t;
+  return t;
+}
+
 template <typename T>
 struct GmresWs {
   long n = 0;
@@ -140,6 +157,20 @@ struct vie_plan_s {
   bool has_contrast = false;
   vie_net_s* net = nullptr;    // learned preconditioner (not owned)
   vie::Circ* circ = nullptr;   // block-circulant preconditioner of the current contrast
+  // JM-VIE (vie_jm_enable): spectrum of K = curl S on the octant, magnetic
+  // contrast (mu_r - 1)/mu_r, the magnetic half's z-pass intermediate, the full
+  // cross-section spectra of the six components, FP32 vectors of the mixed tier
+  bool jm = false;
+  double2* koct64 = nullptr;
+  float2* koct32 = nullptr;
+  double2* chim64 = nullptr;
+  float2* chim32 = nullptr;
+  double2* Um64 = nullptr;
+  float2* Um32 = nullptr;
+  double2* S64 = nullptr;
+  float2* S32 = nullptr;
+  float2* jm32a = nullptr;
+  float2* jm32b = nullptr;
   std::shared_ptr<const std::vector<std::complex<double>>> table;   // host Toeplitz table
   GmresWs<double> ws64;
   GmresWs<float> ws32;
@@ -365,6 +396,28 @@ struct Op32c {
     hipError_t e = full(xc);
     return e ? e : gather<float>(u, p->fy32, rc, bc, p->stream);
   }
+};
+
+// The JM-VIE operator on full 6N vectors (electric, then magnetic in impedance units).
+struct OpJM64 {
+  vie_plan_s* p;
+  hipError_t run(const double2* x, double2* y, const double2* b, int mode) {
+    const void* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+    return launch_jm_matvec<double>(p->g, p->t64, x, y, b, mode, p->U64, p->Um64, p->S64, p->goct64, p->koct64,
+                                    p->chi64, p->chim64, p->kappa, tw, p->stream);
+  }
+  hipError_t apply(const double2* x, double2* y) { return run(x, y, nullptr, 0); }
+  hipError_t residual(const double2* x, const double2* b, double2* r) { return run(x, r, b, 1); }
+};
+struct OpJM32 {
+  vie_plan_s* p;
+  hipError_t run(const float2* x, float2* y, const float2* b, int mode) {
+    const void* tw[3] = {p->tw32[0], p->tw32[1], p->tw32[2]};
+    return launch_jm_matvec<float>(p->g, p->t32, x, y, b, mode, p->U32, p->Um32, p->S32, p->goct32, p->koct32,
+                                   p->chi32, p->chim32, p->kappa, tw, p->stream);
+  }
+  hipError_t apply(const float2* x, float2* y) { return run(x, y, nullptr, 0); }
+  hipError_t residual(const float2* x, const float2* b, float2* r) { return run(x, r, b, 1); }
 };
 
 struct Stats {
@@ -1012,6 +1065,188 @@ int vie_circulant_apply(vie_plan_t p, const vie_c128* r, vie_c128* z) {
   return VIE_OK;
 }
 
+int vie_curl_table(const int grid[3], double kappa, vie_c128* out, int nthreads) {
+  if (!grid || !out) return fail(nullptr, VIE_EINVAL, "null argument");
+  for (int d = 0; d < 3; ++d)
+    if (grid[d] < 1 || grid[d] > 4096) return fail(nullptr, VIE_EINVAL, "grid size out of range");
+  if (!std::isfinite(kappa)) return fail(nullptr, VIE_EINVAL, "kappa not finite");
+  vie::curl_table(grid, kappa, reinterpret_cast<std::complex<double>*>(out), nthreads);
+  return VIE_OK;
+}
+
+int vie_jm_enable(vie_plan_t p) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (p->jm) return VIE_OK;
+  const Geom& g = p->g;
+  if (g.M1 * g.M2 > 64 * 64) return fail(p, VIE_EINVAL, "cross-section too large for the JM kernels");
+  const bool f32 = p->goct32 != nullptr;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  const auto kt = cached_curl_table(n, p->kappa);
+  const long H = (long)g.H1 * g.H2 * g.H3;
+  const long P = (long)g.M1 * g.M2 * g.M3;
+  const size_t nU = 3 * (size_t)g.n1 * g.n2 * g.M3;
+  double2* kdev = nullptr;
+  double2* full = nullptr;
+  auto done = [&](int code) {
+    if (kdev) (void)hipFree(kdev);
+    if (full) (void)hipFree(full);
+    return code;
+  };
+#define JMTRY(expr)                                              \
+  do {                                                           \
+    hipError_t _e = (expr);                                      \
+    if (_e != hipSuccess) return done(hipfail(p, _e, #expr));    \
+  } while (0)
+  JMTRY(allow_lds_jm<double>());
+  JMTRY(allow_lds_jm<float>());
+  JMTRY(hipMalloc(&p->koct64, sizeof(double2) * 3 * H));
+  if (f32) JMTRY(hipMalloc(&p->koct32, sizeof(float2) * 3 * H));
+  JMTRY(hipMalloc(&p->chim64, sizeof(double2) * g.N));
+  JMTRY(hipMalloc(&p->chim32, sizeof(float2) * g.N));
+  JMTRY(hipMemsetAsync(p->chim64, 0, sizeof(double2) * g.N, p->stream));
+  JMTRY(hipMemsetAsync(p->chim32, 0, sizeof(float2) * g.N, p->stream));
+  JMTRY(hipMalloc(&p->Um64, sizeof(double2) * nU));
+  JMTRY(hipMalloc(&p->S64, sizeof(double2) * jm_spectrum_values(g)));
+  if (f32) {
+    JMTRY(hipMalloc(&p->Um32, sizeof(float2) * nU));
+    JMTRY(hipMalloc(&p->S32, sizeof(float2) * jm_spectrum_values(g)));
+  }
+  JMTRY(hipMalloc(&kdev, sizeof(double2) * 3 * g.N));
+  JMTRY(hipMalloc(&full, sizeof(double2) * P));
+  JMTRY(hipMemcpyAsync(kdev, kt->data(), sizeof(double2) * 3 * g.N, hipMemcpyHostToDevice, p->stream));
+  {
+    const double2* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
+    JMTRY(launch_curl_spectrum(g, kdev, full, p->koct64, p->koct32, tw, p->stream));
+  }
+  JMTRY(hipStreamSynchronize(p->stream));
+#undef JMTRY
+  p->jm = true;
+  return done(VIE_OK);
+}
+
+int vie_jm_set_permeability(vie_plan_t p, const vie_c128* mu_r) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!p->jm) return fail(p, VIE_ESTATE, "vie_jm_enable first");
+  if (!mu_r) return fail(p, VIE_EINVAL, "null mu_r");
+  HIPTRY(p, hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
+  // (mu_r - 1)/mu_r = 1 - 1/mu_r: the contrast kernel with a unit background
+  HIPTRY(p, launch_contrast(p->g.N, reinterpret_cast<const double2*>(mu_r), 1.0, p->chim64, p->chim32, p->flag,
+                            p->stream));
+  int bad = 0;
+  HIPTRY(p, hipMemcpyAsync(&bad, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIPTRY(p, hipStreamSynchronize(p->stream));
+  if (bad) return fail(p, VIE_EINVAL, "mu_r has a zero or non-finite entry");
+  return VIE_OK;
+}
+
+int vie_jm_rhs(vie_plan_t p, const vie_c128* e_inc, const vie_c128* etah_inc, vie_c128* b) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!p->jm || !p->has_contrast) return fail(p, VIE_ESTATE, "vie_jm_enable and set_contrast first");
+  if (!e_inc || !etah_inc || !b) return fail(p, VIE_EINVAL, "null vector");
+  const double sc = std::pow(p->h, 1.5);
+  double2* bd = reinterpret_cast<double2*>(b);
+  HIPTRY(p, launch_rhs(p->g.N, sc, p->chi64, reinterpret_cast<const double2*>(e_inc), bd, p->stream));
+  HIPTRY(p, launch_rhs(p->g.N, sc, p->chim64, reinterpret_cast<const double2*>(etah_inc), bd + 3 * p->g.N,
+                       p->stream));
+  return VIE_OK;
+}
+
+int vie_jm_matvec(vie_plan_t p, const vie_c128* x, vie_c128* y) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!p->jm || !p->has_contrast) return fail(p, VIE_ESTATE, "vie_jm_enable and set_contrast first");
+  if (!x || !y || (const void*)x == (const void*)y) return fail(p, VIE_EINVAL, "x, y null or aliased");
+  OpJM64 A{p};
+  HIPTRY(p, A.apply(reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y)));
+  return VIE_OK;
+}
+
+int vie_jm_matvec_c64(vie_plan_t p, const vie_c64* x, vie_c64* y) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!p->jm || !p->has_contrast) return fail(p, VIE_ESTATE, "vie_jm_enable and set_contrast first");
+  if (!p->S32) return fail(p, VIE_ESTATE, "FP32 product needs a plan built with VIE_WITH_FP32");
+  if (!x || !y || (const void*)x == (const void*)y) return fail(p, VIE_EINVAL, "x, y null or aliased");
+  OpJM32 A{p};
+  HIPTRY(p, A.apply(reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(y)));
+  return VIE_OK;
+}
+
+int vie_jm_residual(vie_plan_t p, const vie_c128* x, const vie_c128* b, vie_c128* r) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!p->jm || !p->has_contrast) return fail(p, VIE_ESTATE, "vie_jm_enable and set_contrast first");
+  if (!x || !b || !r || (const void*)x == (const void*)r || (const void*)b == (const void*)r)
+    return fail(p, VIE_EINVAL, "x, b, r null or aliased");
+  OpJM64 A{p};
+  HIPTRY(p, A.residual(reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(b),
+                       reinterpret_cast<double2*>(r)));
+  return VIE_OK;
+}
+
+int vie_jm_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts* opts,
+                 vie_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!p->jm || !p->has_contrast) return fail(p, VIE_ESTATE, "vie_jm_enable and set_contrast first");
+  if (!b || !x || (const void*)b == (const void*)x) return fail(p, VIE_EINVAL, "b, x null or aliased");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(p, VIE_EINVAL, "tol must be positive");
+  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4, 0};
+  if (opts) o = *opts;
+  if (o.restart <= 0) o.restart = 50;
+  if (o.maxit <= 0) o.maxit = 10000;
+  if (o.inner_restart <= 0) o.inner_restart = 20;
+  if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
+  if (o.restart > 4096 || o.inner_restart > 4096) return fail(p, VIE_EINVAL, "restart too large");
+  if (o.precision != 0 && o.precision != 1) return fail(p, VIE_EINVAL, "JM solves take precision 0 or 1");
+  if (o.precision == 1 && !p->S32) return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
+  hipStream_t s = p->stream;
+  const long n = 6 * p->g.N;
+  const double2* bd = reinterpret_cast<const double2*>(b);
+  double2* xd = reinterpret_cast<double2*>(x);
+  Stats st;
+  OpJM64 A{p};
+  int status;
+  if (o.precision == 0) {
+    status = gmres_core<double, OpJM64, NoPrecond>(p, p->ws64, A, nullptr, n, bd, xd, tol, o.restart, o.maxit,
+                                                   o.use_x0 != 0, true, st);
+  } else {
+    if (!p->jm32a) {
+      HIPTRY(p, hipMalloc(&p->jm32a, sizeof(float2) * n));
+      HIPTRY(p, hipMalloc(&p->jm32b, sizeof(float2) * n));
+    }
+    OpJM32 A32{p};
+    // right preconditioner: z = inner FP32 GMRES solve of A z = v
+    auto inner = [&](const void* v, void* z, Stats& outer) -> hipError_t {
+      hipError_t e = convert<double, float>(reinterpret_cast<const double2*>(v), p->jm32a, n, s);
+      if (e) return e;
+      Stats si;
+      int rc = gmres_core<float, OpJM32, NoPrecond>(p, p->ws32, A32, nullptr, n, p->jm32a, p->jm32b, o.inner_tol,
+                                                     o.inner_restart, o.inner_restart, false, false, si);
+      outer.inner += si.iters;
+      if (rc != VIE_OK && rc != VIE_ENOCONV) return hipErrorUnknown;
+      return convert<float, double>(p->jm32b, reinterpret_cast<double2*>(z), n, s);
+    };
+    struct Pc {
+      decltype(inner)& f;
+      hipError_t operator()(const void* v, void* z, Stats& st_) { return f(v, z, st_); }
+    } pc{inner};
+    status = gmres_core<double, OpJM64, Pc>(p, p->ws64, A, &pc, n, bd, xd, tol, o.restart, o.maxit, o.use_x0 != 0,
+                                            true, st);
+  }
+  if (status == VIE_OK || status == VIE_ENOCONV) HIPTRY(p, hipStreamSynchronize(s));
+  if (info) {
+    info->iters = st.iters;
+    info->inner_iters = st.inner;
+    info->restarts = st.restarts;
+    info->matvecs = st.matvecs;
+    info->status = status;
+    info->rel_res_true = st.rel_true;
+    info->rel_res_est = st.est;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->fallback = 0;
+  }
+  if (status == VIE_ENOCONV && p->err.empty()) p->err = "tolerance not reached within maxit";
+  return status;
+}
+
 void vie_destroy(vie_plan_t p) {
   if (!p) return;
   if (p->circ) {
@@ -1023,7 +1258,9 @@ void vie_destroy(vie_plan_t p) {
   for (void* q : {(void*)p->goct64, (void*)p->goct32, (void*)p->chi64, (void*)p->chi32, (void*)p->U64,
                   (void*)p->U32, (void*)p->rvec, (void*)p->v32a, (void*)p->v32b, (void*)p->flag, (void*)p->colflag,
                   (void*)p->scol, (void*)p->fx, (void*)p->fy, (void*)p->fx32, (void*)p->fy32, (void*)p->bc,
-                  (void*)p->xc, (void*)p->partial_full, (void*)p->sumsq_full})
+                  (void*)p->xc, (void*)p->partial_full, (void*)p->sumsq_full, (void*)p->koct64,
+                  (void*)p->koct32, (void*)p->chim64, (void*)p->chim32, (void*)p->Um64, (void*)p->Um32,
+                  (void*)p->S64, (void*)p->S32, (void*)p->jm32a, (void*)p->jm32b})
     if (q) (void)hipFree(q);
   for (int d = 0; d < 3; ++d) {
     if (p->tw64[d]) (void)hipFree(p->tw64[d]);

@@ -10,6 +10,9 @@ namespace vie {
 
 // Host FP64 Toeplitz table (green_table.cpp): out[6][n1][n2][n3].
 int green_table(const int n[3], double kappa, std::complex<double>* out, int nthreads);
+// Host FP64 table of K = curl S (green_table.cpp): out[3][n1][n2][n3], components
+// (0,1), (0,2), (1,2) at h = 1.
+int curl_table(const int n[3], double kappa, std::complex<double>* out, int nthreads);
 
 // Geometry and launch shapes of one operator, passed to the kernel launchers.
 struct Geom {
@@ -53,6 +56,21 @@ hipError_t launch_pass(int which, const Geom& g, const Tune& t, const void* x, v
 // ---- plan-time spectrum -----------------------------------------------------
 hipError_t launch_spectrum(const Geom& g, const double2* table_dev, double2* full_tmp, double2* goct64,
                            float2* goct32, const double2* const tw64[3], hipStream_t s);
+
+hipError_t launch_curl_spectrum(const Geom& g, const double2* ktable_dev, double2* full_tmp, double2* koct64,
+                                float2* koct32, const double2* const tw64[3], hipStream_t s);
+
+// ---- JM-VIE product (jm.hip) --------------------------------------------------
+// y = (I - M T~) x on 6N vectors (electric then magnetic, each [3][n1][n2][n3]);
+// mode 1: y = b - (I - M T~) x.  Ue, Um: z-pass intermediates of each half; S:
+// jm_spectrum_values(g) values.  M1 M2 <= 4096.
+size_t jm_spectrum_values(const Geom& g);
+template <typename T>
+hipError_t allow_lds_jm();
+template <typename T>
+hipError_t launch_jm_matvec(const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
+                            void* Ue, void* Um, void* S, const void* goct, const void* koct, const void* chi_e,
+                            const void* chi_m, double kappa, const void* const tw[3], hipStream_t s);
 
 // ---- contrast / rhs ---------------------------------------------------------
 hipError_t launch_contrast(long N, const double2* eps, double eps_b, double2* chi64, float2* chi32,

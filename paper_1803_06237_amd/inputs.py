@@ -206,6 +206,27 @@ def complex_source_dipole_field(n: Sequence[int], h: float, r0: Sequence[float],
     return out
 
 
+def complex_source_dipole_hfield(n: Sequence[int], h: float, r0: Sequence[float], p: Sequence[complex],
+                                 k: float, shift: Sequence[float]) -> np.ndarray:
+    """eta H of the same complex-source dipole, in the units of complex_source_dipole_field:
+    ``eta H = k^2 (n x p) e^{ikR}/R (1 - 1/(ikR))`` (the textbook magnetic field of a
+    radiating dipole, continued to the complex source point; ``curl E = i k eta H`` for
+    exp(-i omega t)).  Returns shape (3, n1, n2, n3) complex128."""
+    n1, n2, n3 = n
+    c = [h * (np.arange(nn) + 0.5) for nn in (n1, n2, n3)]
+    s = np.asarray(shift, dtype=float)
+    X, Y, Z = np.meshgrid(c[0] - r0[0] - 1j * s[0], c[1] - r0[1] - 1j * s[1], c[2] - r0[2] - 1j * s[2],
+                          indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)              # principal branch, Re >= 0
+    if np.any(np.abs(r) < 1e-12 * h):
+        raise ValueError("a voxel centre lies on the complex source's branch rim")
+    nv = (X / r, Y / r, Z / r)
+    p = np.asarray(p, dtype=np.complex128)
+    amp = k * k * np.exp(1j * k * r) / r * (1.0 - 1.0 / (1j * k * r))
+    cross = (nv[1] * p[2] - nv[2] * p[1], nv[2] * p[0] - nv[0] * p[2], nv[0] * p[1] - nv[1] * p[0])
+    return np.stack([amp * cc for cc in cross])
+
+
 def gaussian_rhs(n: Sequence[int], seed: int = 0) -> np.ndarray:
     """Seeded complex Gaussian vector of shape (3, n1, n2, n3)."""
     z = np.random.default_rng(seed).standard_normal((3, n[0], n[1], n[2], 2))
@@ -311,6 +332,14 @@ def strip_paper(length_um: float, d: int, r_rt: float = 1e-10) -> Waveguide:
     sig = sigma_max_for(r_rt, d, n_abs * H_PAPER)
     return Waveguide(n=(30, 12, n3), h=H_PAPER, core_x=(0, 30), core_y=(0, 12), core_z=(0, n3), n_abs=n_abs,
                      d=d, sigma_max=sig, ends="right")
+
+
+def strip_paper_source_h(wg: Waveguide) -> np.ndarray:
+    """eta H of strip_paper_source (the magnetic right-hand side of the JM-VIE)."""
+    lam_si = LAMBDA0 / math.sqrt(wg.eps_core)
+    r0 = (0.5 * wg.n[0] * wg.h, 0.5 * wg.n[1] * wg.h, wg.core_z[0] * wg.h + lam_si / 4.0)
+    kb = wg.k0 * math.sqrt(wg.eps_b)
+    return complex_source_dipole_hfield(wg.n, wg.h, r0, (1, 0, 0), kb, (0.0, 0.0, lam_si))
 
 
 def strip_paper_source(wg: Waveguide) -> np.ndarray:

@@ -100,6 +100,15 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_int, vp]
         L.vie_net_last_error.restype = ctypes.c_char_p
         L.vie_net_last_error.argtypes = [vp]
+        L.vie_curl_table.argtypes = [ip, ctypes.c_double, vp, ctypes.c_int]
+        L.vie_jm_enable.argtypes = [vp]
+        L.vie_jm_set_permeability.argtypes = [vp, vp]
+        L.vie_jm_rhs.argtypes = [vp, vp, vp, vp]
+        L.vie_jm_matvec.argtypes = [vp, vp, vp]
+        L.vie_jm_matvec_c64.argtypes = [vp, vp, vp]
+        L.vie_jm_residual.argtypes = [vp, vp, vp, vp]
+        L.vie_jm_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(SolveOpts),
+                                   ctypes.POINTER(SolveInfo)]
         _lib = L
     return _lib
 
@@ -118,6 +127,13 @@ def green_table(grid: Sequence[int], kappa: float, nthreads: int = 0) -> np.ndar
     """Host FP64 Toeplitz table N^{ab}(m), shape (6, n1, n2, n3), components xx xy xz yy yz zz."""
     out = np.empty((6,) + tuple(int(v) for v in grid), dtype=np.complex128)
     _check(lib().vie_green_table(_grid(grid), float(kappa), out.ctypes.data, int(nthreads)))
+    return out
+
+
+def curl_table(grid: Sequence[int], kappa: float, nthreads: int = 0) -> np.ndarray:
+    """Host FP64 table of K = curl S, shape (3, n1, n2, n3), components xy xz yz (vie_curl_table)."""
+    out = np.empty((3,) + tuple(int(v) for v in grid), dtype=np.complex128)
+    _check(lib().vie_curl_table(_grid(grid), float(kappa), out.ctypes.data, int(nthreads)))
     return out
 
 
@@ -269,6 +285,68 @@ class Plan:
                                _ptr(x, torch.complex128, 3 * self.N, "x"), float(tol), ctypes.byref(opts),
                                ctypes.byref(info))
         if code not in (VIE_OK, VIE_ENOCONV) or (raise_on_noconv and code != VIE_OK):
+            _check(code, self._h)
+        return x, info.as_dict()
+
+    # ---- JM-VIE: electric and magnetic currents, 6N values (see include/vie.h)
+    def jm_enable(self):
+        """Spectrum of K = curl S and the JM buffers; mu_r = 1 (vie_jm_enable)."""
+        _check(lib().vie_jm_enable(self._h), self._h)
+
+    def set_permeability(self, mu_r):
+        """Relative permeability per voxel, device complex128 of N values."""
+        import torch
+        _check(lib().vie_jm_set_permeability(self._h, _ptr(mu_r, torch.complex128, self.N, "mu_r")), self._h)
+
+    def jm_rhs(self, e_inc, etah_inc, out=None):
+        """b = h^{3/2} (M_eps e_inc, M_mu eta h_inc), 6N values (vie_jm_rhs)."""
+        import torch
+        if out is None:
+            out = torch.empty(6 * self.N, dtype=torch.complex128, device=e_inc.device)
+        _check(lib().vie_jm_rhs(self._h, _ptr(e_inc, torch.complex128, 3 * self.N, "e_inc"),
+                                _ptr(etah_inc, torch.complex128, 3 * self.N, "etah_inc"),
+                                _ptr(out, torch.complex128, 6 * self.N, "b")), self._h)
+        return out
+
+    def jm_matvec(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().vie_jm_matvec(self._h, _ptr(x, torch.complex128, 6 * self.N, "x"),
+                                   _ptr(y, torch.complex128, 6 * self.N, "y")), self._h)
+        return y
+
+    def jm_matvec_c64(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().vie_jm_matvec_c64(self._h, _ptr(x, torch.complex64, 6 * self.N, "x"),
+                                       _ptr(y, torch.complex64, 6 * self.N, "y")), self._h)
+        return y
+
+    def jm_residual(self, x, b, r=None):
+        import torch
+        if r is None:
+            r = torch.empty_like(b)
+        _check(lib().vie_jm_residual(self._h, _ptr(x, torch.complex128, 6 * self.N, "x"),
+                                     _ptr(b, torch.complex128, 6 * self.N, "b"),
+                                     _ptr(r, torch.complex128, 6 * self.N, "r")), self._h)
+        return r
+
+    def jm_solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000, precision: int = 0,
+                 use_x0: bool = False, inner_restart: int = 20, inner_tol: float = 1e-4):
+        """GMRES(restart) (precision 0) or FP32-inner / FP64-outer FGMRES (1) on the 6N
+        unknowns (vie_jm_solve).  Returns (x, info dict)."""
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        opts = SolveOpts(int(restart), int(maxit), int(bool(use_x0)), int(precision), int(inner_restart),
+                         float(inner_tol), 0)
+        info = SolveInfo()
+        code = lib().vie_jm_solve(self._h, _ptr(b, torch.complex128, 6 * self.N, "b"),
+                                  _ptr(x, torch.complex128, 6 * self.N, "x"), float(tol), ctypes.byref(opts),
+                                  ctypes.byref(info))
+        if code not in (VIE_OK, VIE_ENOCONV):
             _check(code, self._h)
         return x, info.as_dict()
 

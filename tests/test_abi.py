@@ -8,7 +8,7 @@ import re
 import numpy as np
 import pytest
 
-from oracle import green
+from oracle import green, jm
 from paper_1803_06237_amd import vie
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -56,6 +56,14 @@ def test_host_table_sampled_at_long_grid():
     assert np.max(np.abs(No - Nl)) < 2e-15
 
 
+@pytest.mark.parametrize("grid,kappa", [((8, 8, 12), 0.29266), ((3, 5, 7), 1.1), ((2, 1, 3), 0.0)])
+def test_host_curl_table_matches_oracle(grid, kappa):
+    K = vie.curl_table(grid, kappa)
+    Ko = jm.curl_table(grid, kappa)
+    assert np.max(np.abs(K - Ko)) < 2e-15
+    assert np.max(np.abs(Ko)) > 1e-3
+
+
 def test_plan_rejects_bad_arguments_before_touching_the_device():
     L = vie.lib()
     h = ctypes.c_void_p()
@@ -75,4 +83,12 @@ def test_plan_rejects_bad_arguments_before_touching_the_device():
     assert L.vie_circulant_apply(None, None, None) == vie.VIE_EINVAL
     assert L.vie_get_tune(None, 0, None, None) == vie.VIE_EINVAL
     assert L.vie_set_tune(None, 0, 0, 0) == vie.VIE_EINVAL
+    assert L.vie_curl_table(zero, 0.1, None, 0) == vie.VIE_EINVAL
+    assert L.vie_jm_enable(None) == vie.VIE_EINVAL
+    assert L.vie_jm_set_permeability(None, None) == vie.VIE_EINVAL
+    assert L.vie_jm_rhs(None, None, None, None) == vie.VIE_EINVAL
+    assert L.vie_jm_matvec(None, None, None) == vie.VIE_EINVAL
+    assert L.vie_jm_matvec_c64(None, None, None) == vie.VIE_EINVAL
+    assert L.vie_jm_residual(None, None, None, None) == vie.VIE_EINVAL
+    assert L.vie_jm_solve(None, None, None, 1e-8, None, None) == vie.VIE_EINVAL
     L.vie_destroy(None)

@@ -151,3 +151,27 @@ def test_reflection_analysis_on_exact_power_laws():
     R2 = list(R)
     R2[-1] = 1e-12
     assert ex.analyse_reflection(L, R2, 0, 1e-25, 9.45) == ex.analyse_reflection(L, R, 0, 1e-25, 9.45)
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.3])
+def test_magnetic_field_is_the_curl_of_the_electric_field(shift):
+    """curl E = i k eta H (exp(-i omega t)) by central differences ahead of the source."""
+    k, h = 10.0, 0.002
+    n = (9, 9, 9)
+    r0 = (4.5 * h + 0.01, 4.5 * h - 0.02, -0.45)
+    p = (0.2, 0.7j, -0.4)
+    E = inputs.complex_source_dipole_field(n, h, r0, p, k, (0.0, 0.0, shift))
+    H = inputs.complex_source_dipole_hfield(n, h, r0, p, k, (0.0, 0.0, shift))
+
+    def d(f, ax):
+        sp = [slice(1, -1)] * 3
+        sm = [slice(1, -1)] * 3
+        sp[ax] = slice(2, None)
+        sm[ax] = slice(None, -2)
+        return (f[tuple(sp)] - f[tuple(sm)]) / (2 * h)
+
+    curl = [d(E[2], 1) - d(E[1], 2), d(E[0], 2) - d(E[2], 0), d(E[1], 0) - d(E[0], 1)]
+    c = (slice(1, -1),) * 3
+    scale = k * np.max(np.abs(H))
+    for a in range(3):
+        assert np.max(np.abs(curl[a] - 1j * k * H[a][c])) < 1e-3 * scale
