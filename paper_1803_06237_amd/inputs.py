@@ -69,6 +69,9 @@ class Waveguide:
     # which ends of the core carry an absorber: "both", or "right" (high-z end
     # only, as for the directional source of Section V-A)
     ends: str = "both"
+    # magnetic conductivity alongside the electric one, impedance matched
+    # (Section IV-B: mu'' = eps''/eps' in the absorber); False keeps mu_r = 1
+    magnetic: bool = False
 
     def __post_init__(self):
         if self.ends not in ("both", "right"):
@@ -133,6 +136,18 @@ class Waveguide:
         core_val = self.eps_core + 1j * self.sigma_max * prof   # per z
         eps[mask] = np.broadcast_to(core_val, self.n)[mask]
         return eps
+
+    def mu(self) -> np.ndarray:
+        """Relative permeability per voxel: 1 everywhere, except, when the absorber is
+        magnetic, 1 + i eps''/eps' in its core voxels (exp(-i omega t) sign), so that
+        mu_r/eps_r stays 1/eps_core and the absorber's impedance matches the core's."""
+        mu = np.ones(self.n, dtype=np.complex128)
+        if not self.magnetic:
+            return mu
+        eps = self.eps()
+        lossy = self.core_mask() & (eps.imag != 0)
+        mu[lossy] = 1.0 + 1j * eps.imag[lossy] / eps.real[lossy]
+        return mu
 
     def core_axis(self) -> Tuple[int, int]:
         """(i1, i2) indices of the voxel column on the core's centre line."""
@@ -323,15 +338,17 @@ H_PAPER = 0.05 / 3.0                 # 50/3 nm voxels (Section II-A)
 STRIP_LEN = 810                      # 13.5 um lossless strip in voxels (Section II-A)
 
 
-def strip_paper(length_um: float, d: int, r_rt: float = 1e-10) -> Waveguide:
+def strip_paper(length_um: float, d: int, r_rt: float = 1e-10, magnetic: bool = False) -> Waveguide:
     """The strip of Section II-A: a 500 x 200 nm silicon core 13.5 um long in silica,
     voxels of 50/3 nm (30 x 12 across, 810 along), with one absorber of length
-    length_um appended at the far end (Section V-A).  The grid is the core itself."""
+    length_um appended at the far end (Section V-A).  The grid is the core itself.
+    With magnetic=True the absorber is impedance matched and its strength takes the
+    factor D = 4 of the round-trip estimate (Section IV-C) instead of 2."""
     n_abs = int(round(length_um / H_PAPER))
     n3 = STRIP_LEN + n_abs
-    sig = sigma_max_for(r_rt, d, n_abs * H_PAPER)
+    sig = sigma_max_for(r_rt, d, n_abs * H_PAPER, D=4.0 if magnetic else 2.0)
     return Waveguide(n=(30, 12, n3), h=H_PAPER, core_x=(0, 30), core_y=(0, 12), core_z=(0, n3), n_abs=n_abs,
-                     d=d, sigma_max=sig, ends="right")
+                     d=d, sigma_max=sig, ends="right", magnetic=magnetic)
 
 
 def strip_paper_source_h(wg: Waveguide) -> np.ndarray:

@@ -175,3 +175,15 @@ def test_magnetic_field_is_the_curl_of_the_electric_field(shift):
     scale = k * np.max(np.abs(H))
     for a in range(3):
         assert np.max(np.abs(curl[a] - 1j * k * H[a][c])) < 1e-3 * scale
+
+
+def test_matched_absorber_permeability():
+    """mu'' = eps''/eps' in the absorber (Section IV-B) and D = 4 in the strength."""
+    wg = inputs.strip_paper(0.9, 2, 1e-25, magnetic=True)
+    eps, mu = wg.eps(), wg.mu()
+    assert np.all(mu[:, :, :810] == 1)
+    assert np.allclose(mu[:, :, 810:], 1 + 1j * eps[:, :, 810:].imag / inputs.EPS_SI, rtol=1e-15, atol=0)
+    assert np.allclose(mu[:, :, 810:] / eps[:, :, 810:], 1 / inputs.EPS_SI, rtol=1e-14, atol=0)
+    e_only = inputs.strip_paper(0.9, 2, 1e-25)
+    assert wg.sigma_max == pytest.approx(0.5 * e_only.sigma_max, rel=1e-14)
+    assert np.all(e_only.mu() == 1)
