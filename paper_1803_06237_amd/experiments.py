@@ -211,6 +211,8 @@ LAMBDA_SI = inputs.LAMBDA0 / math.sqrt(inputs.EPS_SI)                # wavelengt
 # Absorber length (silicon wavelengths) for R = 1e-8 with electric currents only, as the
 # paper's table of Section V-A gives it (d = 0 and some d = 1 entries are extrapolations there)
 PAPER_LENGTH_FOR_1E8 = {1e-25: {0: 13000.0, 1: 49.0, 2: 9.5, 3: 7.2}, 1e-10: {0: 4500.0, 1: 32.0, 2: 7.1, 3: 6.2}}
+# the same with electric and magnetic currents and an impedance-matched absorber
+PAPER_LENGTH_FOR_1E8_EM = {1e-25: {0: 350.0, 1: 14.0, 2: 5.1, 3: 5.9}, 1e-10: {0: 230.0, 1: 9.0, 2: 4.8, 3: 6.1}}
 
 
 def strip_axis_field(wg: inputs.Waveguide, w: np.ndarray) -> np.ndarray:
@@ -279,6 +281,88 @@ def analyse_reflection(lengths: Sequence[float], R: Sequence[float], d: int, r_r
     return out
 
 
+def _strip_guide(L: float, d: int, r_rt: float, strip_len: int, magnetic: bool) -> inputs.Waveguide:
+    wg = inputs.strip_paper(L, d, r_rt, magnetic=magnetic)
+    if strip_len != inputs.STRIP_LEN:
+        wg = inputs.Waveguide(n=(wg.n[0], wg.n[1], strip_len + wg.n_abs), h=wg.h, core_x=wg.core_x,
+                              core_y=wg.core_y, core_z=(0, strip_len + wg.n_abs), n_abs=wg.n_abs, d=d,
+                              sigma_max=wg.sigma_max, ends="right", magnetic=magnetic)
+    return wg
+
+
+def _reflection(fields: dict, lengths: Sequence[float]):
+    """R(L) = |E_ref - E_L|^2 / |E_ref|^2 on the centre line, against the longest absorber."""
+    Lref = max(lengths)
+    ref = fields[Lref]
+    Ls = [L for L in lengths if L != Lref]
+    return Ls, [float(np.sum(np.abs(ref - fields[L]) ** 2) / np.sum(np.abs(ref) ** 2)) for L in Ls]
+
+
+def strip_reflection_study_em(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: Sequence[int] = DEGREES,
+                              lengths: Sequence[float] = STRIP_LENGTHS, precision: int = 1, tol: float = 1e-8,
+                              restart: int = 50, inner_restart: int = 20, inner_tol: float = 1e-3,
+                              strip_len: int = inputs.STRIP_LEN, progress=None) -> dict:
+    """The e&m columns of Section V-A: the same strip, source and lengths, with magnetic
+    conductivity matched to the electric one (mu'' = eps''/eps', strength with D = 4) and the
+    JM-VIE solved for both currents (the source's eta H as the magnetic right-hand side).
+    One plan at a time: each length's plan serves every (R_rt, d), then is freed.
+    progress, if given, is called with a line per finished length."""
+    import torch
+    out = {"lengths_um": list(lengths), "lambda_si_um": LAMBDA_SI, "strip_voxels": strip_len, "runs": {},
+           "formulation": "JM-VIE, impedance-matched absorber"}
+    groups = [(r_rt, d) for r_rt in r_rts for d in degrees]
+    fields = {g: {} for g in groups}
+    stats = {g: {"solve_seconds": 0.0, "max_rel_res": 0.0, "outer_iters": [], "inner_iters": [], "status": 0,
+                 "unknowns": 0} for g in groups}
+    t_all = time.perf_counter()
+    for L in lengths:
+        t0 = time.perf_counter()
+        wg0 = _strip_guide(L, degrees[0], r_rts[0], strip_len, True)
+        plan = vie.Plan(wg0.n, wg0.h, wg0.k0, wg0.eps_b, fp32=precision != 0)
+        try:
+            plan.set_contrast(torch.from_numpy(wg0.eps()).cuda())
+            plan.jm_enable()
+            e_inc = torch.from_numpy(inputs.strip_paper_source(wg0)).cuda()
+            h_inc = torch.from_numpy(inputs.strip_paper_source_h(wg0)).cuda()
+            setup_s = time.perf_counter() - t0
+            for g in groups:
+                r_rt, d = g
+                wg = _strip_guide(L, d, r_rt, strip_len, True)
+                plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+                plan.set_permeability(torch.from_numpy(wg.mu()).cuda())
+                b = plan.jm_rhs(e_inc, h_inc)
+                t1 = time.perf_counter()
+                x, info = plan.jm_solve(b, tol=tol, restart=restart, precision=precision,
+                                        inner_restart=inner_restart, inner_tol=inner_tol)
+                torch.cuda.synchronize()
+                st = stats[g]
+                st["solve_seconds"] += time.perf_counter() - t1
+                st["max_rel_res"] = max(st["max_rel_res"], info["rel_res_true"])
+                st["outer_iters"].append(info["iters"])
+                st["inner_iters"].append(info["inner_iters"])
+                st["unknowns"] += 6 * wg.N
+                if info["status"] != vie.VIE_OK:
+                    st["status"] = info["status"]
+                w = x.view((6,) + wg.n)[:3].cpu().numpy()
+                fields[g][L] = strip_axis_field(wg, w)
+        finally:
+            plan.close()
+        if progress is not None:
+            progress(f"L = {L} um: {6 * wg0.N} unknowns, setup {setup_s:.1f} s, "
+                     f"{len(groups)} JM solves in {time.perf_counter() - t0 - setup_s:.1f} s")
+    out["seconds"] = round(time.perf_counter() - t_all, 3)
+    for g in groups:
+        r_rt, d = g
+        Ls, R = _reflection(fields[g], lengths)
+        run = dict(stats[g])
+        run["solve_seconds"] = round(run["solve_seconds"], 3)
+        run.update({"r_rt": r_rt, "d": d, "R": R,
+                    "paper_length_for_1e-8_lambda": PAPER_LENGTH_FOR_1E8_EM.get(r_rt, {}).get(d)})
+        run.update(analyse_reflection(Ls, R, d, r_rt, max(lengths)))
+        out["runs"][f"{r_rt:g}/{d}"] = run
+    return out
+
+
 def strip_reflection_study(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: Sequence[int] = DEGREES,
                            lengths: Sequence[float] = STRIP_LENGTHS, precision: int = 1, tol: float = 1e-8,
                            restart: int = 50, inner_restart: int = 20, inner_tol: float = 1e-3,
@@ -293,12 +377,7 @@ def strip_reflection_study(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: Seq
     import torch
 
     def guide(L, d, r_rt):
-        wg = inputs.strip_paper(L, d, r_rt)
-        if strip_len != inputs.STRIP_LEN:
-            wg = inputs.Waveguide(n=(wg.n[0], wg.n[1], strip_len + wg.n_abs), h=wg.h, core_x=wg.core_x,
-                                  core_y=wg.core_y, core_z=(0, strip_len + wg.n_abs), n_abs=wg.n_abs, d=d,
-                                  sigma_max=wg.sigma_max, ends="right")
-        return wg
+        return _strip_guide(L, d, r_rt, strip_len, False)
 
     Lref = max(lengths)
     out = {"lengths_um": list(lengths), "lambda_si_um": LAMBDA_SI, "strip_voxels": strip_len, "runs": {}}
@@ -327,9 +406,7 @@ def strip_reflection_study(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: Seq
                 torch.cuda.synchronize()
                 solve_s = time.perf_counter() - t0
                 fields = {L: strip_axis_field(wg, x.cpu().numpy()) for L, wg, x in zip(lengths, wgs, xs)}
-                ref = fields[Lref]
-                Ls = [L for L in lengths if L != Lref]
-                R = [float(np.sum(np.abs(ref - fields[L]) ** 2) / np.sum(np.abs(ref) ** 2)) for L in Ls]
+                Ls, R = _reflection(fields, lengths)
                 run = {"r_rt": r_rt, "d": d, "status": code, "setup_seconds": round(setup_s, 3),
                        "solve_seconds": round(solve_s, 3), "unknowns": sum(3 * wg.N for wg in wgs),
                        "max_rel_res": max(i["rel_res_true"] for i in infos),
@@ -353,6 +430,8 @@ if __name__ == "__main__":
     ap.add_argument("which", choices=["strip"], help="strip: the reflection study of Section V-A")
     ap.add_argument("--out", default=None, help="write the JSON result here")
     ap.add_argument("--quick", action="store_true", help="every other absorber length")
+    ap.add_argument("--em", action="store_true", help="electric and magnetic currents, matched absorber")
+    ap.add_argument("--r-rt", type=float, nargs="*", default=[1e-25, 1e-10], help="round-trip reflections")
     a = ap.parse_args()
     lengths = STRIP_LENGTHS[::2] if a.quick else STRIP_LENGTHS
     if lengths[-1] != STRIP_LENGTHS[-1]:
@@ -365,7 +444,12 @@ if __name__ == "__main__":
               "L(1e-8)/lambda", fmt(r["length_lambda"]), r["method"], "paper", r["paper_length_for_1e-8_lambda"],
               "solve s", r["solve_seconds"], "max res", f"{r['max_rel_res']:.1e}", flush=True)
 
-    res = strip_reflection_study(lengths=lengths, progress=show)
+    if a.em:
+        res = strip_reflection_study_em(r_rts=tuple(a.r_rt), lengths=lengths, progress=lambda m: print(m, flush=True))
+        for r in res["runs"].values():
+            show(r)
+    else:
+        res = strip_reflection_study(r_rts=tuple(a.r_rt), lengths=lengths, progress=show)
     if a.out:
         with open(a.out, "w") as f:
             f.write(json.dumps(res, indent=1))

@@ -24,3 +24,21 @@ def test_strip_study_converges_and_reflection_falls_with_length():
     assert len(R) == 3 and all(np.isfinite(R))
     assert R[0] > R[1] > R[2]
     assert R[0] < 1.0
+
+
+def test_matched_absorber_study_converges_and_reflection_falls_with_length():
+    """The e&m variant through the JM-VIE at the same reduced length."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1803_06237_amd import experiments, vie
+    vie.lib()
+    kw = dict(r_rts=(1e-10,), degrees=(2,), lengths=(0.45, 0.9, 1.8, 3.6), strip_len=120)
+    em = experiments.strip_reflection_study_em(**kw)["runs"]["1e-10/2"]
+    e = experiments.strip_reflection_study(**kw)["runs"]["1e-10/2"]
+    print("e&m", em)
+    print("e", e["R"])
+    assert em["status"] == vie.VIE_OK
+    assert em["max_rel_res"] <= 1e-8
+    R = em["R"]
+    assert len(R) == 3 and all(np.isfinite(R))
+    assert R[0] > R[1] > R[2]
