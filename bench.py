@@ -42,6 +42,75 @@ def pass_bytes(n, M, cs):
             U + 3 * N * cs + N * cs + 3 * N * cs]  # pass 3: read U, x, chi; write y
 
 
+def jm_pass_bytes(n, M, cs, fused):
+    """Algorithmic HBM bytes of the JM-VIE product (6N unknowns) per kernel: the z passes
+    run once per half; the cross-section work is one fused kernel (spectra in LDS) or the
+    forward transforms, the product and the inverse transforms through full spectra."""
+    n1, n2, n3 = n
+    M1, M2, M3 = M
+    N = n1 * n2 * n3
+    U = 3 * n1 * n2 * M3 * cs
+    H = (M1 // 2 + 1) * (M2 // 2 + 1) * (M3 // 2 + 1)
+    G, K = 6 * H * cs, 3 * H * cs
+    S3 = 3 * M1 * M2 * M3 * cs
+    z = {"z forward (x2)": 2 * (3 * N * cs + U), "z inverse (x2)": 2 * (U + 7 * N * cs)}
+    if fused:
+        z["k_jm_xy"] = 4 * U + G + K
+    else:
+        z["k_jm_xyfwd (x2)"] = 2 * (U + S3)
+        z["k_jm_product"] = 4 * S3 + G + K
+        z["k_jm_xyinv (x2)"] = 2 * (S3 + U)
+    return z
+
+
+def jm_measurement(steps: int):
+    """JM-VIE products (Section III: electric and magnetic currents, 6N unknowns) timed
+    with HIP events on the plan's stream: the bench guide with impedance-matched magnetic
+    absorbers, and the paper's strip (30 x 12 x 1377, the longest absorber of the e&m study)."""
+    import numpy as np
+    import torch
+
+    from paper_1803_06237_amd import inputs, vie
+    wg_bench = inputs.strip_long(d=2)
+    wg_bench.magnetic = True
+    cases = (("32x32x512 guide, matched absorbers", wg_bench),
+             ("30x12x1377 strip, matched 9.45 um absorber", inputs.strip_paper(9.45, 2, 1e-10, magnetic=True)))
+    out = {}
+    for name, wg in cases:
+        plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+        plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+        plan.jm_enable()
+        plan.set_permeability(torch.from_numpy(wg.mu()).cuda())
+        rng = np.random.default_rng(1)
+        xh = rng.standard_normal(6 * wg.N) + 1j * rng.standard_normal(6 * wg.N)
+        res = {"grid": list(wg.n), "unknowns": 6 * wg.N}
+        for prec, label in ((0, "fp64"), (1, "fp32")):
+            x = torch.from_numpy(xh).cuda()
+            if prec:
+                x = x.to(torch.complex64)
+            y = torch.empty_like(x)
+            f = plan.jm_matvec if prec == 0 else plan.jm_matvec_c64
+            for _ in range(5):
+                f(x, y)
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                f(x, y)
+            t1.record()
+            t1.synchronize()
+            ms = t0.elapsed_time(t1) / steps
+            fused = plan.jm_route(prec)
+            by = jm_pass_bytes(wg.n, circulant(wg.n), 16 if prec == 0 else 8, fused)
+            tot = sum(by.values())
+            res[label] = {"avg_us": round(ms * 1e3, 2), "matvecs_per_s": round(1e3 / ms, 1),
+                          "route": "fused" if fused else "through HBM", "modelled_bytes": tot,
+                          "GBs": round(tot / (ms * 1e-3) / 1e9, 1),
+                          "frac": round(tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "bytes_by_kernel": by}
+        plan.close()
+        out[name] = res
+    return out
+
+
 KERNEL_SOURCES = {
     "k_xy64<double, 0>": ["xy64.hip", "fft_device.hpp"],
     "k_xy64<double, 1>": ["xy64.hip", "fft_device.hpp"],
@@ -148,6 +217,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiler run: one device copy of a vector (counter calibration, bytes known) and the "
                          "timed FP64 products only")
+    ap.add_argument("--profile-jm", action="store_true",
+                    help="profiler run: the JM-VIE products only (both grids, both precisions)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver in this build is "
@@ -159,6 +230,9 @@ def main():
 
     from paper_1803_06237_amd import inputs, vie
     torch.cuda.set_device(0)
+    if args.profile_jm:
+        print(json.dumps({"jm_matvec": jm_measurement(args.steps)}), flush=True)
+        return
     wg = inputs.strip_long(d=2)
     n = wg.n
     M = circulant(n)
@@ -227,6 +301,9 @@ def main():
                            "GBs": round(sum(b32) / (t32 * 1e-3) / 1e9, 1),
                            "passes_us": [round(v * 1e3, 2) for v in p32]},
            "plan_seconds": round(plan_s, 3)}
+
+    if not args.profile:
+        out["jm_matvec"] = jm_measurement(max(10, args.steps // 4))
 
     if not args.no_solve:
         e_inc = inputs.transverse_dipole_field(wg)

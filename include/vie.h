@@ -316,9 +316,17 @@ const char* vie_net_last_error(vie_net_t net);
  * vie_curl_table -- host-only, FP64: K^{ab}(m) for 0 <= m_d < grid[d], out
  *   [3][n1][n2][n3] for the components xy, xz, yz (K^{ba} = -K^{ab}, K^{aa} = 0);
  *   negating m_d multiplies K^{ab} by -1 exactly when d is neither a nor b.
- * vie_jm_enable -- builds the spectrum of K and the JM buffers (about 6 M1 M2 M3
- *   complex values per precision) and sets mu_r = 1 everywhere.  Idempotent.
- *   VIE_EINVAL when M1 M2 > 4096.  Synchronises.
+ * vie_jm_enable -- builds the spectrum of K and the JM buffers and sets mu_r = 1
+ *   everywhere.  Idempotent.  VIE_EINVAL when M1 M2 > 4096.  Synchronises.
+ *   The cross-section pass runs fused (spectra in LDS) when the six
+ *   row-transformed components of a plane fit with one column chunk:
+ *   (6 n2 M1 + 6 M2 cc) complex values in 160 KiB for some cc >= 1 (every FP32
+ *   grid; in FP64 e.g. the 30 x 12 strip, not a 32 x 32 cross-section);
+ *   otherwise through full spectra in HBM (6 M1 M2 M3 complex values per
+ *   precision, allocated only then).
+ * vie_jm_set_route / vie_jm_get_route -- per precision (0 FP64, 1 FP32): fused 1
+ *   = the fused pass (VIE_EINVAL where it does not fit), 0 = through HBM
+ *   (allocates the spectra on first use).  Same results to rounding.
  * vie_jm_set_permeability -- mu_r: device, N relative permeabilities (copied).
  *   VIE_EINVAL for a zero or non-finite entry.  Synchronises.
  * vie_jm_rhs -- b = h^{3/2} (M_eps e_inc, M_mu etah_inc): e_inc and etah_inc
@@ -334,6 +342,8 @@ const char* vie_net_last_error(vie_net_t net);
  */
 int vie_curl_table(const int grid[3], double kappa, vie_c128* out, int nthreads);
 int vie_jm_enable(vie_plan_t plan);
+int vie_jm_set_route(vie_plan_t plan, int precision, int fused);
+int vie_jm_get_route(vie_plan_t plan, int precision, int* fused);
 int vie_jm_set_permeability(vie_plan_t plan, const vie_c128* mu_r);
 int vie_jm_rhs(vie_plan_t plan, const vie_c128* e_inc, const vie_c128* etah_inc, vie_c128* b);
 int vie_jm_matvec(vie_plan_t plan, const vie_c128* x, vie_c128* y);

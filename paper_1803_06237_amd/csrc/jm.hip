@@ -6,12 +6,16 @@
 // and exp(-i omega t); K = curl S is block Toeplitz like N, with three
 // antisymmetric components (K^{ba} = -K^{ab}) odd along the axis other than a
 // and b, so its spectrum is stored on one octant too.  The product reuses the
-// z passes of the J-VIE once per half and adds three kernels over full
-// cross-section spectra:
+// z passes of the J-VIE once per half.  Between them, when the row-transformed
+// plane of all six components fits in LDS (every FP32 grid; FP64 while
+// 6 n2 M1 values leave room for the column chunk), one fused kernel per kz plane:
+//   k_jm_xy:      rows along x, column chunks along y, the 6 x 6 product with
+//                 N^ and K^, inverse columns and rows, crop: U_e, U_m in place.
+// Otherwise three kernels over full cross-section spectra in HBM:
 //   k_jm_xyfwd:   per (kz, component) plane: the n2 x n1 slice of the
 //                 z-transformed intermediate, zero padded to M2 x M1, 2-D FFT
 //                 in LDS, into S[component][kz][ky][kx]
-//   k_jm_product: per spectral point: the 6 x 6 product with N^ and K^
+//   k_jm_product: per spectral point: the 6 x 6 product
 //   k_jm_xyinv:   per plane: inverse 2-D FFT, crop to n2 x n1, back into U
 // A plane is at most 64 x 64 values (n1, n2 <= 32), 64 KiB in FP64.
 #include <hip/hip_runtime.h>
@@ -24,6 +28,11 @@ namespace {
 
 constexpr int kJmThreads = 256;
 constexpr int kJmMaxV = 16;   // values per thread per FFT stage: 256 x 16 = 4096 = the largest plane
+constexpr size_t kJmFusedLds = 160 * 1024;   // the fused pass may take a CU's whole LDS
+// Largest fused workgroup: 16 values per thread over at most 160 KiB of values
+// (640 threads in FP64, 1280 in FP32, capped at 1024).
+template <typename T>
+constexpr int kJmFusedThreads = sizeof(T) == 8 ? 640 : 1024;
 
 template <typename T>
 __global__ __launch_bounds__(kJmThreads) void k_jm_xyfwd(const cx<T>* __restrict__ U, cx<T>* __restrict__ S, Geom g,
@@ -79,6 +88,50 @@ __device__ __forceinline__ cx<T> ikap(T kappa, cx<T> z) {
   return cx<T>{-kappa * z.y, kappa * z.x};
 }
 
+// N and K at one frequency of the full circulant, from the stored octant: the
+// signs of the odd components follow the folded axes (N^{ab} odd along d when
+// exactly one of a, b is d; K^{ab} odd along its third axis).
+template <typename T>
+struct JmCoef {
+  cx<T> gxx, gxy, gxz, gyy, gyz, gzz, kxy, kxz, kyz;
+};
+
+template <typename T>
+__device__ __forceinline__ JmCoef<T> jm_coef(const cx<T>* __restrict__ G, const cx<T>* __restrict__ Kp, T s1, T s2,
+                                             T s3) {
+  JmCoef<T> c;
+  c.gxx = G[0];
+  c.gyy = G[3];
+  c.gzz = G[5];
+  c.gxy = cscale(G[1], s1 * s2);
+  c.gxz = cscale(G[2], s1 * s3);
+  c.gyz = cscale(G[4], s2 * s3);
+  c.kxy = cscale(Kp[0], s3);
+  c.kxz = cscale(Kp[1], s2);
+  c.kyz = cscale(Kp[2], s1);
+  return c;
+}
+
+// out_e = N u_e + i kappa K u_m, out_m = N u_m - i kappa K u_e (K antisymmetric)
+template <typename T>
+__device__ __forceinline__ void jm_apply(const JmCoef<T>& c, T kappa, const cx<T> ue[3], const cx<T> um[3],
+                                         cx<T> oe[3], cx<T> om[3]) {
+  const cx<T> zero{(T)0, (T)0};
+  const cx<T> kue[3] = {cadd(cmul(c.kxy, ue[1]), cmul(c.kxz, ue[2])), csub(cmul(c.kyz, ue[2]), cmul(c.kxy, ue[0])),
+                        csub(zero, cadd(cmul(c.kxz, ue[0]), cmul(c.kyz, ue[1])))};
+  const cx<T> kum[3] = {cadd(cmul(c.kxy, um[1]), cmul(c.kxz, um[2])), csub(cmul(c.kyz, um[2]), cmul(c.kxy, um[0])),
+                        csub(zero, cadd(cmul(c.kxz, um[0]), cmul(c.kyz, um[1])))};
+  const cx<T> ne[3] = {cfma3(c.gxx, ue[0], c.gxy, ue[1], c.gxz, ue[2]), cfma3(c.gxy, ue[0], c.gyy, ue[1], c.gyz, ue[2]),
+                       cfma3(c.gxz, ue[0], c.gyz, ue[1], c.gzz, ue[2])};
+  const cx<T> nm[3] = {cfma3(c.gxx, um[0], c.gxy, um[1], c.gxz, um[2]), cfma3(c.gxy, um[0], c.gyy, um[1], c.gyz, um[2]),
+                       cfma3(c.gxz, um[0], c.gyz, um[1], c.gzz, um[2])};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    oe[a] = cadd(ne[a], ikap(kappa, kum[a]));
+    om[a] = csub(nm[a], ikap(kappa, kue[a]));
+  }
+}
+
 template <typename T>
 __global__ void k_jm_product(cx<T>* __restrict__ S, const cx<T>* __restrict__ goct, const cx<T>* __restrict__ koct,
                              Geom g, T kappa) {
@@ -97,35 +150,105 @@ __global__ void k_jm_product(cx<T>* __restrict__ S, const cx<T>* __restrict__ go
     const long o = ((long)k3 * g.H2 + k2) * g.H1 + k1;
     const cx<T>* G = goct + o * 6;
     const cx<T>* Kp = koct + o * 3;
-    // N^{ab} is odd along d when exactly one of a, b is d; K^{ab} along the third axis
-    const cx<T> gxx = G[0], gyy = G[3], gzz = G[5];
-    const cx<T> gxy = cscale(G[1], s1 * s2), gxz = cscale(G[2], s1 * s3), gyz = cscale(G[4], s2 * s3);
-    const cx<T> kxy = cscale(Kp[0], s3), kxz = cscale(Kp[1], s2), kyz = cscale(Kp[2], s1);
-    cx<T> ue[3], um[3];
+    const JmCoef<T> c = jm_coef<T>(goct + o * 6, koct + o * 3, s1, s2, s3);
+    cx<T> ue[3], um[3], oe[3], om[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       ue[a] = S[a * P + i];
       um[a] = S[(3 + a) * P + i];
     }
-    const cx<T> zero{(T)0, (T)0};
-    // (K u)_x = K^{xy} u_y + K^{xz} u_z, (K u)_y = -K^{xy} u_x + K^{yz} u_z, (K u)_z = -K^{xz} u_x - K^{yz} u_y
-    auto Kmul = [&](const cx<T>* u, cx<T>* out) {
-      out[0] = cadd(cmul(kxy, u[1]), cmul(kxz, u[2]));
-      out[1] = csub(cmul(kyz, u[2]), cmul(kxy, u[0]));
-      out[2] = csub(zero, cadd(cmul(kxz, u[0]), cmul(kyz, u[1])));
-    };
-    cx<T> kue[3], kum[3];
-    Kmul(ue, kue);
-    Kmul(um, kum);
-    const cx<T> ne[3] = {cfma3(gxx, ue[0], gxy, ue[1], gxz, ue[2]), cfma3(gxy, ue[0], gyy, ue[1], gyz, ue[2]),
-                         cfma3(gxz, ue[0], gyz, ue[1], gzz, ue[2])};
-    const cx<T> nm[3] = {cfma3(gxx, um[0], gxy, um[1], gxz, um[2]), cfma3(gxy, um[0], gyy, um[1], gyz, um[2]),
-                         cfma3(gxz, um[0], gyz, um[1], gzz, um[2])};
+    jm_apply<T>(c, kappa, ue, um, oe, om);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      S[a * P + i] = cadd(ne[a], ikap(kappa, kum[a]));
-      S[(3 + a) * P + i] = csub(nm[a], ikap(kappa, kue[a]));
+      S[a * P + i] = oe[a];
+      S[(3 + a) * P + i] = om[a];
     }
+  }
+}
+
+// Fused cross-section pass of the JM product on one kz plane (used when the
+// plane's row transforms of all six components fit in LDS): row transforms
+// along x of the n2 valid rows, then for each chunk of cc x-frequencies the
+// column transforms along y, the coupled product with N and i kappa K, the
+// inverse column transforms, and at the end the inverse row transforms and the
+// crop.  Ue, Um are read and overwritten in place; the spectra stay in LDS.
+template <typename T>
+__global__ __launch_bounds__(kJmFusedThreads<T>) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* __restrict__ Um,
+                                                const cx<T>* __restrict__ goct, const cx<T>* __restrict__ koct,
+                                                Geom g, int cc, T kappa, const cx<T>* __restrict__ tw1,
+                                                const cx<T>* __restrict__ tw2) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* rows = reinterpret_cast<cx<T>*>(smem_raw);      // [6][n2][M1]: e components, then m
+  cx<T>* cols = rows + 6 * g.n2 * g.M1;                   // [6][M2][cc]
+  const int kz = blockIdx.x;
+  const int plane = 3 * g.n1 * g.n2;
+  cx<T>* Pe = Ue + (long)kz * plane;
+  cx<T>* Pm = Um + (long)kz * plane;
+  for (int t = threadIdx.x; t < 2 * plane; t += blockDim.x) {
+    const bool mag = t >= plane;
+    const int q = mag ? t - plane : t;
+    const int x = q % g.n1, r = q / g.n1 + (mag ? 3 * g.n2 : 0);
+    rows[r * g.M1 + x] = mag ? Pm[q] : Pe[q];
+  }
+  __syncthreads();
+  fft_lds<T, false, kJmMaxV>(rows, SeqMap{0, 0, g.M1, 1}, 6 * g.n2, g.L1, g.n1, tw1, 1);
+
+  const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
+  const T s3 = kz <= g.M3 / 2 ? (T)1 : (T)-1;
+  const cx<T>* G3 = goct + (long)k3 * g.H2 * g.H1 * 6;
+  const cx<T>* K3 = koct + (long)k3 * g.H2 * g.H1 * 3;
+  int cclog = 0;
+  while ((1 << cclog) < cc) ++cclog;
+  const SeqMap cmap{cclog, 1, g.M2 * cc, cc};
+  const int cstride = g.M2 * cc;
+  for (int c0 = 0; c0 < g.M1; c0 += cc) {
+    for (int t = threadIdx.x; t < 6 * g.n2 * cc; t += blockDim.x) {
+      const int col = t % cc, r = t / cc;           // r = comp * n2 + y, comp 0..5
+      const int comp = r / g.n2, yy = r % g.n2;
+      cols[comp * cstride + yy * cc + col] = rows[r * g.M1 + c0 + col];
+    }
+    __syncthreads();
+    fft_lds<T, false, kJmMaxV>(cols, cmap, 6 * cc, g.L2, g.n2, tw2, 1);
+    for (int t = threadIdx.x; t < g.M2 * cc; t += blockDim.x) {
+      const int col = t % cc, ky = t / cc;
+      const int kx = c0 + col;
+      const int k1 = kx <= g.M1 / 2 ? kx : g.M1 - kx;
+      const int k2 = ky <= g.M2 / 2 ? ky : g.M2 - ky;
+      const T s1 = kx <= g.M1 / 2 ? (T)1 : (T)-1;
+      const T s2 = ky <= g.M2 / 2 ? (T)1 : (T)-1;
+      const long f = (long)k2 * g.H1 + k1;
+      const JmCoef<T> c = jm_coef<T>(G3 + f * 6, K3 + f * 3, s1, s2, s3);
+      const int o = ky * cc + col;
+      cx<T> ue[3], um[3], oe[3], om[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        ue[a] = cols[a * cstride + o];
+        um[a] = cols[(3 + a) * cstride + o];
+      }
+      jm_apply<T>(c, kappa, ue, um, oe, om);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cols[a * cstride + o] = oe[a];
+        cols[(3 + a) * cstride + o] = om[a];
+      }
+    }
+    __syncthreads();
+    fft_lds<T, true, kJmMaxV>(cols, cmap, 6 * cc, g.L2, g.M2, tw2, 1);
+    for (int t = threadIdx.x; t < 6 * g.n2 * cc; t += blockDim.x) {
+      const int col = t % cc, r = t / cc;
+      const int comp = r / g.n2, yy = r % g.n2;
+      rows[r * g.M1 + c0 + col] = cols[comp * cstride + yy * cc + col];
+    }
+    __syncthreads();
+  }
+  fft_lds<T, true, kJmMaxV>(rows, SeqMap{0, 0, g.M1, 1}, 6 * g.n2, g.L1, g.M1, tw1, 1);
+  for (int t = threadIdx.x; t < 2 * plane; t += blockDim.x) {
+    const bool mag = t >= plane;
+    const int q = mag ? t - plane : t;
+    const int x = q % g.n1, r = q / g.n1 + (mag ? 3 * g.n2 : 0);
+    const cx<T> v = rows[r * g.M1 + x];
+    if (mag) Pm[q] = v;
+    else Pe[q] = v;
   }
 }
 
@@ -134,10 +257,32 @@ __global__ void k_jm_product(cx<T>* __restrict__ S, const cx<T>* __restrict__ go
 size_t jm_spectrum_values(const Geom& g) { return (size_t)6 * g.M1 * g.M2 * g.M3; }
 
 template <typename T>
+bool jm_fused_shape(const Geom& g, int* cc_out, int* threads_out) {
+  const size_t cs = sizeof(cx<T>);
+  const size_t rows = (size_t)6 * g.n2 * g.M1;
+  int cc = g.M1 < 16 ? g.M1 : 16;
+  while (cc > 1 && (rows + (size_t)6 * g.M2 * cc) * cs > kJmFusedLds) cc >>= 1;
+  const size_t cols = (size_t)6 * g.M2 * cc;
+  if ((rows + cols) * cs > kJmFusedLds) return false;
+  // every FFT stage holds at most kJmMaxV values per thread
+  const size_t need = rows > cols ? rows : cols;
+  int threads = (int)((need + kJmMaxV - 1) / kJmMaxV);
+  threads = ((threads + 63) / 64) * 64;
+  if (threads < 256) threads = 256;
+  if (threads > kJmFusedThreads<T>) return false;
+  if (cc_out) *cc_out = cc;
+  if (threads_out) *threads_out = threads;
+  return true;
+}
+
+template <typename T>
 hipError_t allow_lds_jm() {
   const int bytes = 64 * 64 * (int)sizeof(cx<T>);
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)k_jm_xyfwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_jm_xy<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kJmFusedLds)))
     return e;
   return hipFuncSetAttribute((const void*)k_jm_xyinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
@@ -145,9 +290,12 @@ hipError_t allow_lds_jm() {
 template <typename T>
 hipError_t launch_jm_matvec(const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
                             void* Ue, void* Um, void* S, const void* goct, const void* koct, const void* chi_e,
-                            const void* chi_m, double kappa, const void* const tw[3], hipStream_t s) {
+                            const void* chi_m, double kappa, bool fused, const void* const tw[3], hipStream_t s) {
   using C = cx<T>;
   if (g.M1 * g.M2 > 64 * 64) return hipErrorInvalidValue;
+  int cc = 0, threads = 0;
+  if (fused && !jm_fused_shape<T>(g, &cc, &threads)) return hipErrorInvalidValue;
+  if (!fused && !S) return hipErrorInvalidValue;
   const long n3 = 3 * g.N;
   const C* xe = static_cast<const C*>(x);
   const C* xm = xe + n3;
@@ -158,6 +306,14 @@ hipError_t launch_jm_matvec(const Geom& g, const Tune& t, const void* x, void* y
   hipError_t e;
   if ((e = launch_pass<T>(0, g, t, xe, nullptr, nullptr, 0, Ue, goct, chi_e, tw, s))) return e;
   if ((e = launch_pass<T>(0, g, t, xm, nullptr, nullptr, 0, Um, goct, chi_m, tw, s))) return e;
+  if (fused) {
+    const size_t lds = ((size_t)6 * g.n2 * g.M1 + (size_t)6 * g.M2 * cc) * sizeof(C);
+    hipLaunchKernelGGL(k_jm_xy<T>, dim3(g.M3), dim3(threads), lds, s, (C*)Ue, (C*)Um, (const C*)goct,
+                       (const C*)koct, g, cc, (T)kappa, (const C*)tw[0], (const C*)tw[1]);
+    if ((e = hipGetLastError())) return e;
+    if ((e = launch_pass<T>(2, g, t, xe, ye, be, mode, Ue, goct, chi_e, tw, s))) return e;
+    return launch_pass<T>(2, g, t, xm, ym, bm, mode, Um, goct, chi_m, tw, s);
+  }
   const size_t lds = (size_t)g.M1 * g.M2 * sizeof(C);
   const dim3 planes(3 * g.M3), block(kJmThreads);
   hipLaunchKernelGGL(k_jm_xyfwd<T>, planes, block, lds, s, (const C*)Ue, (C*)S, g, 0, (const C*)tw[0],
@@ -180,11 +336,13 @@ hipError_t launch_jm_matvec(const Geom& g, const Tune& t, const void* x, void* y
 
 template hipError_t allow_lds_jm<double>();
 template hipError_t allow_lds_jm<float>();
+template bool jm_fused_shape<double>(const Geom&, int*, int*);
+template bool jm_fused_shape<float>(const Geom&, int*, int*);
 template hipError_t launch_jm_matvec<double>(const Geom&, const Tune&, const void*, void*, const void*, int, void*,
                                              void*, void*, const void*, const void*, const void*, const void*, double,
-                                             const void* const[3], hipStream_t);
+                                             bool, const void* const[3], hipStream_t);
 template hipError_t launch_jm_matvec<float>(const Geom&, const Tune&, const void*, void*, const void*, int, void*,
                                             void*, void*, const void*, const void*, const void*, const void*, double,
-                                            const void* const[3], hipStream_t);
+                                            bool, const void* const[3], hipStream_t);
 
 }  // namespace vie

@@ -171,6 +171,8 @@ struct vie_plan_s {
   float2* S32 = nullptr;
   float2* jm32a = nullptr;
   float2* jm32b = nullptr;
+  bool jm_fused64 = false;   // cross-section pass with the spectra in LDS (else through S64 / S32)
+  bool jm_fused32 = false;
   std::shared_ptr<const std::vector<std::complex<double>>> table;   // host Toeplitz table
   GmresWs<double> ws64;
   GmresWs<float> ws32;
@@ -404,7 +406,7 @@ struct OpJM64 {
   hipError_t run(const double2* x, double2* y, const double2* b, int mode) {
     const void* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
     return launch_jm_matvec<double>(p->g, p->t64, x, y, b, mode, p->U64, p->Um64, p->S64, p->goct64, p->koct64,
-                                    p->chi64, p->chim64, p->kappa, tw, p->stream);
+                                    p->chi64, p->chim64, p->kappa, p->jm_fused64, tw, p->stream);
   }
   hipError_t apply(const double2* x, double2* y) { return run(x, y, nullptr, 0); }
   hipError_t residual(const double2* x, const double2* b, double2* r) { return run(x, r, b, 1); }
@@ -414,7 +416,7 @@ struct OpJM32 {
   hipError_t run(const float2* x, float2* y, const float2* b, int mode) {
     const void* tw[3] = {p->tw32[0], p->tw32[1], p->tw32[2]};
     return launch_jm_matvec<float>(p->g, p->t32, x, y, b, mode, p->U32, p->Um32, p->S32, p->goct32, p->koct32,
-                                   p->chi32, p->chim32, p->kappa, tw, p->stream);
+                                   p->chi32, p->chim32, p->kappa, p->jm_fused32, tw, p->stream);
   }
   hipError_t apply(const float2* x, float2* y) { return run(x, y, nullptr, 0); }
   hipError_t residual(const float2* x, const float2* b, float2* r) { return run(x, r, b, 1); }
@@ -1106,10 +1108,12 @@ int vie_jm_enable(vie_plan_t p) {
   JMTRY(hipMemsetAsync(p->chim64, 0, sizeof(double2) * g.N, p->stream));
   JMTRY(hipMemsetAsync(p->chim32, 0, sizeof(float2) * g.N, p->stream));
   JMTRY(hipMalloc(&p->Um64, sizeof(double2) * nU));
-  JMTRY(hipMalloc(&p->S64, sizeof(double2) * jm_spectrum_values(g)));
+  p->jm_fused64 = jm_fused_shape<double>(g, nullptr, nullptr);
+  p->jm_fused32 = f32 && jm_fused_shape<float>(g, nullptr, nullptr);
+  if (!p->jm_fused64) JMTRY(hipMalloc(&p->S64, sizeof(double2) * jm_spectrum_values(g)));
   if (f32) {
     JMTRY(hipMalloc(&p->Um32, sizeof(float2) * nU));
-    JMTRY(hipMalloc(&p->S32, sizeof(float2) * jm_spectrum_values(g)));
+    if (!p->jm_fused32) JMTRY(hipMalloc(&p->S32, sizeof(float2) * jm_spectrum_values(g)));
   }
   JMTRY(hipMalloc(&kdev, sizeof(double2) * 3 * g.N));
   JMTRY(hipMalloc(&full, sizeof(double2) * P));
@@ -1122,6 +1126,32 @@ int vie_jm_enable(vie_plan_t p) {
 #undef JMTRY
   p->jm = true;
   return done(VIE_OK);
+}
+
+int vie_jm_set_route(vie_plan_t p, int precision, int fused) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!p->jm) return fail(p, VIE_ESTATE, "vie_jm_enable first");
+  if (precision != 0 && precision != 1) return fail(p, VIE_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+  if (precision == 1 && !p->goct32) return fail(p, VIE_ESTATE, "plan made without VIE_WITH_FP32");
+  const bool fits = precision == 0 ? jm_fused_shape<double>(p->g, nullptr, nullptr)
+                                   : jm_fused_shape<float>(p->g, nullptr, nullptr);
+  if (fused && !fits) return fail(p, VIE_EINVAL, "the fused cross-section pass does not fit this grid");
+  if (!fused) {
+    void** S = precision == 0 ? (void**)&p->S64 : (void**)&p->S32;
+    const size_t cs = precision == 0 ? sizeof(double2) : sizeof(float2);
+    if (!*S) HIPTRY(p, hipMalloc(S, cs * jm_spectrum_values(p->g)));
+  }
+  (precision == 0 ? p->jm_fused64 : p->jm_fused32) = fused != 0;
+  return VIE_OK;
+}
+
+int vie_jm_get_route(vie_plan_t p, int precision, int* fused) {
+  if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
+  if (!p->jm) return fail(p, VIE_ESTATE, "vie_jm_enable first");
+  if (precision != 0 && precision != 1) return fail(p, VIE_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+  if (!fused) return fail(p, VIE_EINVAL, "null output");
+  *fused = precision == 0 ? p->jm_fused64 : p->jm_fused32;
+  return VIE_OK;
 }
 
 int vie_jm_set_permeability(vie_plan_t p, const vie_c128* mu_r) {
@@ -1163,7 +1193,7 @@ int vie_jm_matvec(vie_plan_t p, const vie_c128* x, vie_c128* y) {
 int vie_jm_matvec_c64(vie_plan_t p, const vie_c64* x, vie_c64* y) {
   if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
   if (!p->jm || !p->has_contrast) return fail(p, VIE_ESTATE, "vie_jm_enable and set_contrast first");
-  if (!p->S32) return fail(p, VIE_ESTATE, "FP32 product needs a plan built with VIE_WITH_FP32");
+  if (!p->Um32) return fail(p, VIE_ESTATE, "FP32 product needs a plan built with VIE_WITH_FP32");
   if (!x || !y || (const void*)x == (const void*)y) return fail(p, VIE_EINVAL, "x, y null or aliased");
   OpJM32 A{p};
   HIPTRY(p, A.apply(reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(y)));
@@ -1196,7 +1226,7 @@ int vie_jm_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const
   if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
   if (o.restart > 4096 || o.inner_restart > 4096) return fail(p, VIE_EINVAL, "restart too large");
   if (o.precision != 0 && o.precision != 1) return fail(p, VIE_EINVAL, "JM solves take precision 0 or 1");
-  if (o.precision == 1 && !p->S32) return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
+  if (o.precision == 1 && !p->Um32) return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
   hipStream_t s = p->stream;
   const long n = 6 * p->g.N;
   const double2* bd = reinterpret_cast<const double2*>(b);

@@ -62,15 +62,19 @@ hipError_t launch_curl_spectrum(const Geom& g, const double2* ktable_dev, double
 
 // ---- JM-VIE product (jm.hip) --------------------------------------------------
 // y = (I - M T~) x on 6N vectors (electric then magnetic, each [3][n1][n2][n3]);
-// mode 1: y = b - (I - M T~) x.  Ue, Um: z-pass intermediates of each half; S:
-// jm_spectrum_values(g) values.  M1 M2 <= 4096.
+// mode 1: y = b - (I - M T~) x.  Ue, Um: z-pass intermediates of each half.
+// fused: one cross-section kernel with the spectra in LDS (requires
+// jm_fused_shape); otherwise the spectra go through S, jm_spectrum_values(g)
+// values.  M1 M2 <= 4096.
 size_t jm_spectrum_values(const Geom& g);
+template <typename T>
+bool jm_fused_shape(const Geom& g, int* cc, int* threads);
 template <typename T>
 hipError_t allow_lds_jm();
 template <typename T>
 hipError_t launch_jm_matvec(const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
                             void* Ue, void* Um, void* S, const void* goct, const void* koct, const void* chi_e,
-                            const void* chi_m, double kappa, const void* const tw[3], hipStream_t s);
+                            const void* chi_m, double kappa, bool fused, const void* const tw[3], hipStream_t s);
 
 // ---- contrast / rhs ---------------------------------------------------------
 hipError_t launch_contrast(long N, const double2* eps, double eps_b, double2* chi64, float2* chi32,

@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
         L.vie_curl_table.argtypes = [ip, ctypes.c_double, vp, ctypes.c_int]
         L.vie_jm_enable.argtypes = [vp]
         L.vie_jm_set_permeability.argtypes = [vp, vp]
+        L.vie_jm_set_route.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.vie_jm_get_route.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.vie_jm_rhs.argtypes = [vp, vp, vp, vp]
         L.vie_jm_matvec.argtypes = [vp, vp, vp]
         L.vie_jm_matvec_c64.argtypes = [vp, vp, vp]
@@ -292,6 +294,16 @@ class Plan:
     def jm_enable(self):
         """Spectrum of K = curl S and the JM buffers; mu_r = 1 (vie_jm_enable)."""
         _check(lib().vie_jm_enable(self._h), self._h)
+
+    def jm_route(self, precision: int = 0) -> bool:
+        """True when the JM cross-section pass runs fused in LDS (vie_jm_get_route)."""
+        v = ctypes.c_int()
+        _check(lib().vie_jm_get_route(self._h, int(precision), ctypes.byref(v)), self._h)
+        return bool(v.value)
+
+    def set_jm_route(self, precision: int, fused: bool):
+        """Force the fused or the through-HBM cross-section pass (vie_jm_set_route)."""
+        _check(lib().vie_jm_set_route(self._h, int(precision), int(bool(fused))), self._h)
 
     def set_permeability(self, mu_r):
         """Relative permeability per voxel, device complex128 of N values."""

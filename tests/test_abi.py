@@ -86,6 +86,8 @@ def test_plan_rejects_bad_arguments_before_touching_the_device():
     assert L.vie_curl_table(zero, 0.1, None, 0) == vie.VIE_EINVAL
     assert L.vie_jm_enable(None) == vie.VIE_EINVAL
     assert L.vie_jm_set_permeability(None, None) == vie.VIE_EINVAL
+    assert L.vie_jm_set_route(None, 0, 1) == vie.VIE_EINVAL
+    assert L.vie_jm_get_route(None, 0, None) == vie.VIE_EINVAL
     assert L.vie_jm_rhs(None, None, None, None) == vie.VIE_EINVAL
     assert L.vie_jm_matvec(None, None, None) == vie.VIE_EINVAL
     assert L.vie_jm_matvec_c64(None, None, None) == vie.VIE_EINVAL

@@ -90,6 +90,34 @@ def test_fp32_jm_matvec_matches_oracle(case):
     assert err < 5e-6
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_other_cross_section_route_matches_oracle(case, precision):
+    """The fused pass (spectra in LDS) and the route through full spectra in HBM give the
+    same product; each grid runs the route it does not pick by default here."""
+    vie = _dev()
+    n, rng, plan = case["n"], case["rng"], case["plan"]
+    default = plan.jm_route(precision)
+    try:
+        plan.set_jm_route(precision, not default)
+    except vie.VieError as e:
+        assert e.code == vie.VIE_EINVAL and not default     # the fused pass does not fit this grid
+        pytest.skip("fused pass does not fit")
+    try:
+        x = _cvec(rng, (6,) + n)
+        want = _want(case, x)
+        if precision == 0:
+            got = plan.jm_matvec(_t(x)).cpu().numpy()
+            tol = 1e-12
+        else:
+            got = plan.jm_matvec_c64(_t(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+            tol = 5e-6
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        print(f"grid {n} precision {precision} fused={not default} rel err {err:.3e}")
+        assert err < tol
+    finally:
+        plan.set_jm_route(precision, default)
+
+
 def test_jm_residual_is_b_minus_matvec(case):
     n, rng = case["n"], case["rng"]
     x, b = _cvec(rng, (6,) + n), _cvec(rng, (6,) + n)
