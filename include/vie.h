@@ -233,17 +233,19 @@ int vie_circulant_apply(vie_plan_t plan, const vie_c128* r, vie_c128* z);
  * Launch-shape tuning.  Unless VIE_NO_AUTOTUNE is given, vie_plan times the
  * candidate shapes of the product's kernels on the plan's own buffers (two
  * untimed and five timed launches each, HIP events) and keeps the fastest:
- * pencils per workgroup of the four-step z passes (forward and inverse timed
- * together) and, for 64 x 64 circulant cross-sections, the xy pass variant
+ * pencils per workgroup of the four-step z passes, or the generic z passes
+ * (forward and inverse timed together; circulant lengths 512 to 4096 have
+ * four-step shapes) and, for 64 x 64 circulant cross-sections, the xy pass variant
  * (0: full plane in LDS; 1: x-frequency halves, two workgroups per CU; 2: full
  * plane with 512 threads and private exchange areas, one workgroup per CU).  Choices
  * are cached per (device, grid, precision) for the life of the process.
  * vie_get_tune: the current choice for precision 0 (FP64) or 1 (FP32):
  *   *xy_variant (-1 when the grid does not use the 64 x 64 kernel),
  *   *z_pencils (0 when the z passes use the generic kernels).
- * vie_set_tune: force a choice; z_pencils 0 = the default for the grid, any
- *   other value must be one of the tuner's candidates (VIE_EINVAL otherwise).
- *   Synchronises the plan's stream first.
+ * vie_set_tune: force a choice; z_pencils -1 = the generic z passes, 0 = the
+ *   four-step z passes with their default pencils (generic where the grid has no
+ *   four-step shape), any other value must be one of the tuner's candidates
+ *   (VIE_EINVAL otherwise).  Synchronises the plan's stream first.
  */
 int vie_get_tune(vie_plan_t plan, int precision, int* xy_variant, int* z_pencils);
 int vie_set_tune(vie_plan_t plan, int precision, int xy_variant, int z_pencils);

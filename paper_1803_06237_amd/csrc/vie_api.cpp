@@ -299,6 +299,17 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
       }
     }
     t->zp = bestp;
+    // the generic LDS passes as one more candidate (the 64-value shapes of long
+    // pencils run at low occupancy in FP64)
+    Tune c = *t;
+    c.z4 = 0;
+    float ms = 0, ms2 = 0;
+    if (!e) e = time_passes<T>(g, c, 0, 0, x, y, U, goct, chi, tw, s, &ms);
+    if (!e) e = time_passes<T>(g, c, 2, 2, x, y, U, goct, chi, tw, s, &ms2);
+    if (!e && ms + ms2 < best) {
+      t->z4 = 0;
+      t->zp = 0;
+    }
   }
   if (!e && g.M1 == 64 && g.M2 == 64) {
     float best = INFINITY;
@@ -1022,14 +1033,17 @@ int vie_set_tune(vie_plan_t p, int precision, int xy_variant, int z_pencils) {
   const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 8)
                                : z4_pencil_options<float>(p->g.M3, opts, 8);
   Tune& t = precision == 0 ? p->t64 : p->t32;
-  if (z_pencils != 0) {
+  if (z_pencils > 0) {
     bool ok = false;
     for (int i = 0; i < n; ++i) ok = ok || opts[i] == z_pencils;
-    if (!ok || !t.z4) return fail(p, VIE_EINVAL, "z_pencils is not a candidate for this grid");
+    if (!ok) return fail(p, VIE_EINVAL, "z_pencils is not a candidate for this grid");
+  } else if (z_pencils < -1) {
+    return fail(p, VIE_EINVAL, "z_pencils must be -1, 0 or a candidate");
   }
   HIPTRY(p, hipStreamSynchronize(p->stream));
   t.xyv = xy_variant;
-  t.zp = z_pencils;
+  t.z4 = (z_pencils >= 0 && n > 0) ? 1 : 0;
+  t.zp = z_pencils > 0 ? z_pencils : 0;
   return VIE_OK;
 }
 

@@ -296,8 +296,12 @@ int z4_pencil_options(int M3, int* out, int cap) {
   } else if (M3 == 1024) {                           // A = 32
     if (dbl) { opts[0] = 4; opts[1] = 2; opts[2] = 8; n = 3; }
     else { opts[0] = 8; opts[1] = 4; opts[2] = 2; n = 3; }
-  } else if (M3 == 2048 && !dbl) {                   // A = 32
-    opts[0] = 4; opts[1] = 2; n = 2;
+  } else if (M3 == 2048) {                           // A = 32, 64 values per thread
+    if (dbl) { opts[0] = 2; opts[1] = 4; opts[2] = 1; n = 3; }
+    else { opts[0] = 4; opts[1] = 2; n = 2; }
+  } else if (M3 == 4096) {                           // A = 64, 64 values per thread
+    if (dbl) { opts[0] = 2; opts[1] = 1; n = 2; }
+    else { opts[0] = 2; opts[1] = 4; opts[2] = 1; n = 3; }
   }
   for (int i = 0; i < n && i < cap; ++i) out[i] = opts[i];
   return n;
@@ -314,7 +318,8 @@ static bool zshape(int M3, ZShape<T>* s, int P = 0) {
   const int p = P ? P : opts[0];
   if (M3 == 512) *s = {16, 32, p};
   else if (M3 == 1024) *s = {32, 32, p};
-  else *s = {32, 64, p};
+  else if (M3 == 2048) *s = {32, 64, p};
+  else *s = {64, 64, p};
   return true;
 }
 
@@ -348,9 +353,8 @@ hipError_t launch_z4(int which, const Geom& g, int P, const void* x, void* y, co
   }
   VIE_Z4(16, 32)
   VIE_Z4(32, 32)
-  if constexpr (sizeof(T) == 4) {
-    VIE_Z4(32, 64)
-  }
+  VIE_Z4(32, 64)
+  VIE_Z4(64, 64)
 #undef VIE_Z4
   return hipErrorNotSupported;
 }
@@ -424,9 +428,8 @@ hipError_t launch_z4_batch(int which, int mode, const PassDesc* d, const int* pr
   }
   VIE_Z4B(16, 32)
   VIE_Z4B(32, 32)
-  if constexpr (sizeof(T) == 4) {
-    VIE_Z4B(32, 64)
-  }
+  VIE_Z4B(32, 64)
+  VIE_Z4B(64, 64)
 #undef VIE_Z4B
   return hipErrorNotSupported;
 }
@@ -446,9 +449,8 @@ hipError_t allow_lds_z4() {
     return e;
   VIE_ALLOW(16, 32)
   VIE_ALLOW(32, 32)
-  if constexpr (sizeof(T) == 4) {
-    VIE_ALLOW(32, 64)
-  }
+  VIE_ALLOW(32, 64)
+  VIE_ALLOW(64, 64)
 #undef VIE_ALLOW
 #define VIE_ALLOWB(AA, BB)                                                                                         \
   if ((e = hipFuncSetAttribute((const void*)k_zfwd4_batch<T, AA, BB>,                                           \
@@ -462,9 +464,8 @@ hipError_t allow_lds_z4() {
     return e;
   VIE_ALLOWB(16, 32)
   VIE_ALLOWB(32, 32)
-  if constexpr (sizeof(T) == 4) {
-    VIE_ALLOWB(32, 64)
-  }
+  VIE_ALLOWB(32, 64)
+  VIE_ALLOWB(64, 64)
 #undef VIE_ALLOWB
   return hipSuccess;
 }

@@ -263,7 +263,15 @@ TUNED_GRIDS = {
     "32x32x512_M3_1024": lambda: inputs.strip_long(d=2),
     "24x20x200_M3_512": lambda: inputs.Waveguide(n=(24, 20, 200), h=0.025, core_x=(4, 20), core_y=(6, 14),
                                                  core_z=(0, 200), n_abs=30, d=2, sigma_max=10.0),
+    "20x18x700_M3_2048": lambda: inputs.Waveguide(n=(20, 18, 700), h=0.025, core_x=(4, 16), core_y=(5, 13),
+                                                  core_z=(0, 700), n_abs=60, d=2, sigma_max=10.0),
+    "17x32x1100_M3_4096": lambda: inputs.Waveguide(n=(17, 32, 1100), h=0.025, core_x=(3, 14), core_y=(10, 22),
+                                                   core_z=(0, 1100), n_abs=80, d=3, sigma_max=10.0),
 }
+# z-pass pencils per workgroup the tuner tries, per precision and circulant length;
+# -1 forces the generic z passes
+PENCILS = {0: {512: (8, 4, 16, 2), 1024: (4, 2, 8), 2048: (2, 4, 1), 4096: (2, 1)},
+           1: {512: (16, 8, 4, 2), 1024: (8, 4, 2), 2048: (4, 2), 4096: (2, 4, 1)}}
 
 
 @pytest.mark.parametrize("grid", sorted(TUNED_GRIDS))
@@ -277,7 +285,7 @@ def test_every_launch_shape_matches_the_oracle(grid):
     plan.set_contrast(_t(wg.eps()))
     print(grid, "tuned:", plan.tune(0), plan.tune(1))
     M3 = 1 << int(np.ceil(np.log2(2 * wg.n[2] - 1)))
-    pencils = {0: {512: (8, 4, 16, 2), 1024: (4, 2, 8)}[M3], 1: {512: (16, 8, 4, 2), 1024: (8, 4, 2)}[M3]}
+    pencils = {p: PENCILS[p][M3] + (-1,) for p in (0, 1)}
     xt = _t(x)
     xt32 = _t(x, torch.complex64)
     i = tuple(outs.T)
@@ -285,7 +293,7 @@ def test_every_launch_shape_matches_the_oracle(grid):
         for xyv in (0, 1, 2):
             for zp in pencils[precision]:
                 plan.set_tune(precision, xyv, zp)
-                assert plan.tune(precision) == {"xy_variant": xyv, "z_pencils": zp}
+                assert plan.tune(precision) == {"xy_variant": xyv, "z_pencils": max(zp, 0)}
                 if precision == 0:
                     y = plan.matvec(xt).cpu().numpy()
                 else:
