@@ -1106,6 +1106,16 @@ int vie_jm_enable(vie_plan_t p) {
   auto done = [&](int code) {
     if (kdev) (void)hipFree(kdev);
     if (full) (void)hipFree(full);
+    if (code != VIE_OK) {
+      // leave the plan as before the call: no JM buffer survives a failure
+      (void)hipStreamSynchronize(p->stream);
+      for (void** q : {(void**)&p->koct64, (void**)&p->koct32, (void**)&p->chim64, (void**)&p->chim32,
+                       (void**)&p->Um64, (void**)&p->Um32, (void**)&p->S64, (void**)&p->S32}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+      }
+      p->jm_fused64 = p->jm_fused32 = false;
+    }
     return code;
   };
 #define JMTRY(expr)                                              \
