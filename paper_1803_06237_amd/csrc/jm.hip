@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_device.hpp"
+#include "lds_fft.hpp"
 #include "vie_internal.hpp"
 
 namespace vie {
@@ -169,191 +170,8 @@ __global__ void k_jm_product(cx<T>* __restrict__ S, const cx<T>* __restrict__ go
 // inverse column transforms, and at the end the inverse row transforms and the
 // crop.  Ue, Um are read and overwritten in place; the spectra stay in LDS.
 //
-// LDS layouts are bank-conflict free for the radix-8 strides: a row sequence
-// keeps element k at k + k/8 (one spare slot per 8, row pitch M1 + M1/8); the
-// column chunk is stored position-major, C[comp][k + k/8][col], and its stages
-// give consecutive lanes consecutive columns.  The first forward column stage
-// reads the chunk straight from the rows and the last inverse stage writes the
-// kept positions straight back.  Twiddles are staged in LDS.
-
-__device__ __forceinline__ int jm_pad(int k) { return k + (k >> 3); }
-
-template <typename T>
-constexpr int kJmFusedMaxV = 8;   // values per thread per stage
-
-// One radix-R stage over nseq row sequences of length 2^Llog2 at A + s pitch.
-template <typename T, int R, bool INV>
-__device__ __forceinline__ void jm_row_stage(cx<T>* A, int nseq, int pitch, int Llog2, int Nslog2, int valid,
-                                             const cx<T>* tw, int tid) {
-  constexpr int TPT = kJmFusedMaxV<T> / R;
-  constexpr int Rlog2 = R == 2 ? 1 : (R == 4 ? 2 : 3);
-  const int perlog2 = Llog2 - Rlog2;
-  const int total = nseq << perlog2;
-  cx<T> v[TPT][R];
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int t = tid + q * blockDim.x;
-    if (t < total) {
-      const int s = t >> perlog2, j = t & ((1 << perlog2) - 1);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int k = j + (r << perlog2);
-        v[q][r] = k < valid ? A[s * pitch + jm_pad(k)] : cx<T>{(T)0, (T)0};
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int t = tid + q * blockDim.x;
-    if (t < total) {
-      const int s = t >> perlog2, j = t & ((1 << perlog2) - 1);
-      const int jm = j & ((1 << Nslog2) - 1);
-      if (Nslog2 > 0) {
-        const int step = 1 << (Llog2 - Nslog2 - Rlog2);
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cx<T> w = tw[r * jm * step];
-          v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
-        }
-      }
-      dft<T, R, INV>(v[q]);
-      const int o = ((j >> Nslog2) << (Nslog2 + Rlog2)) + jm;
-#pragma unroll
-      for (int r = 0; r < R; ++r) A[s * pitch + jm_pad(o + (r << Nslog2))] = v[q][r];
-    }
-  }
-  __syncthreads();
-}
-
-template <typename T, bool INV>
-__device__ __forceinline__ void jm_rows(cx<T>* A, int nseq, int pitch, int Llog2, int valid, const cx<T>* tw,
-                                        int tid) {
-  int ns = 0, rem = Llog2;
-  bool first = true;
-  while (rem >= 3) {
-    jm_row_stage<T, 8, INV>(A, nseq, pitch, Llog2, ns, first ? valid : (1 << Llog2), tw, tid);
-    ns += 3;
-    rem -= 3;
-    first = false;
-  }
-  if (rem == 2) jm_row_stage<T, 4, INV>(A, nseq, pitch, Llog2, ns, first ? valid : (1 << Llog2), tw, tid);
-  else if (rem == 1) jm_row_stage<T, 2, INV>(A, nseq, pitch, Llog2, ns, first ? valid : (1 << Llog2), tw, tid);
-}
-
-// Where a column stage reads and writes: the chunk C, or (first forward stage /
-// last inverse stage) the rows, element k of column (comp, col) being
-// A[(comp n2 + k) pitch + jm_pad(c0 + col)], k < n2.
-struct JmCols {
-  int cclog, M2p, n2, pitch, c0;
-};
-
-template <typename T, int R, bool INV, bool SRC_ROWS, bool DST_ROWS>
-__device__ __forceinline__ void jm_col_stage(cx<T>* A, cx<T>* C, const JmCols& m, int Llog2, int Nslog2, int valid,
-                                             const cx<T>* tw, int tid) {
-  constexpr bool src_rows = SRC_ROWS, dst_rows = DST_ROWS;
-  constexpr int TPT = kJmFusedMaxV<T> / R;
-  constexpr int Rlog2 = R == 2 ? 1 : (R == 4 ? 2 : 3);
-  const int perlog2 = Llog2 - Rlog2;
-  const int total = (6 << m.cclog) << perlog2;
-  const int ccm = (1 << m.cclog) - 1;
-  cx<T> v[TPT][R];
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int t = tid + q * blockDim.x;
-    if (t < total) {
-      const int col = t & ccm, j = (t >> m.cclog) & ((1 << perlog2) - 1), comp = t >> (m.cclog + perlog2);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int k = j + (r << perlog2);
-        cx<T> x{(T)0, (T)0};
-        if (k < valid)
-          x = src_rows ? A[(comp * m.n2 + k) * m.pitch + jm_pad(m.c0 + col)]
-                       : C[((comp * m.M2p + jm_pad(k)) << m.cclog) + col];
-        v[q][r] = x;
-      }
-    }
-  }
-  if (src_rows == dst_rows) __syncthreads();   // in place: every read before any write
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int t = tid + q * blockDim.x;
-    if (t < total) {
-      const int col = t & ccm, j = (t >> m.cclog) & ((1 << perlog2) - 1), comp = t >> (m.cclog + perlog2);
-      const int jm = j & ((1 << Nslog2) - 1);
-      if (Nslog2 > 0) {
-        const int step = 1 << (Llog2 - Nslog2 - Rlog2);
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cx<T> w = tw[r * jm * step];
-          v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
-        }
-      }
-      dft<T, R, INV>(v[q]);
-      const int o = ((j >> Nslog2) << (Nslog2 + Rlog2)) + jm;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int k = o + (r << Nslog2);
-        if (dst_rows) {
-          if (k < m.n2) A[(comp * m.n2 + k) * m.pitch + jm_pad(m.c0 + col)] = v[q][r];
-        } else {
-          C[((comp * m.M2p + jm_pad(k)) << m.cclog) + col] = v[q][r];
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// Column transform of the chunk: forward from the rows into C, or inverse from C
-// back into the rows (the first / last stage does the hand-over).  Fewer than two
-// stages: explicit copies around the stages.
-template <typename T, bool INV>
-__device__ __forceinline__ void jm_cols(cx<T>* A, cx<T>* C, const JmCols& m, int Llog2, const cx<T>* tw, int tid) {
-  const int nst = Llog2 == 0 ? 0 : (Llog2 + 2) / 3;
-  const int ccm = (1 << m.cclog) - 1;
-  if (nst < 2 && !INV) {
-    for (int t = tid; t < (6 * m.n2) << m.cclog; t += blockDim.x) {
-      const int col = t & ccm, rc = t >> m.cclog;   // rc = comp * n2 + k
-      const int comp = rc / m.n2, k = rc - comp * m.n2;
-      C[((comp * m.M2p + jm_pad(k)) << m.cclog) + col] = A[rc * m.pitch + jm_pad(m.c0 + col)];
-    }
-    // positions n2 <= k < M2 stay unread: the transform takes them as zero
-    __syncthreads();
-  }
-  int ns = 0, rem = Llog2, st = 0;
-  while (rem > 0) {
-    const int R = rem >= 3 ? 8 : (rem == 2 ? 4 : 2);
-    const bool src_rows = !INV && st == 0 && nst >= 2;
-    const bool dst_rows = INV && st == nst - 1 && nst >= 2;
-    const int valid = (!INV && st == 0) ? m.n2 : (1 << Llog2);
-    if (src_rows) {
-      // first forward stage (INV false): radix 8, 4 or 2 from the rows
-      if (R == 8) jm_col_stage<T, 8, INV, true, false>(A, C, m, Llog2, ns, valid, tw, tid);
-      else if (R == 4) jm_col_stage<T, 4, INV, true, false>(A, C, m, Llog2, ns, valid, tw, tid);
-      else jm_col_stage<T, 2, INV, true, false>(A, C, m, Llog2, ns, valid, tw, tid);
-    } else if (dst_rows) {
-      if (R == 8) jm_col_stage<T, 8, INV, false, true>(A, C, m, Llog2, ns, valid, tw, tid);
-      else if (R == 4) jm_col_stage<T, 4, INV, false, true>(A, C, m, Llog2, ns, valid, tw, tid);
-      else jm_col_stage<T, 2, INV, false, true>(A, C, m, Llog2, ns, valid, tw, tid);
-    } else {
-      if (R == 8) jm_col_stage<T, 8, INV, false, false>(A, C, m, Llog2, ns, valid, tw, tid);
-      else if (R == 4) jm_col_stage<T, 4, INV, false, false>(A, C, m, Llog2, ns, valid, tw, tid);
-      else jm_col_stage<T, 2, INV, false, false>(A, C, m, Llog2, ns, valid, tw, tid);
-    }
-    ns += R == 8 ? 3 : (R == 4 ? 2 : 1);
-    rem -= R == 8 ? 3 : (R == 4 ? 2 : 1);
-    ++st;
-  }
-  if (nst < 2 && INV) {
-    for (int t = tid; t < (6 * m.n2) << m.cclog; t += blockDim.x) {
-      const int col = t & ccm, rc = t >> m.cclog;
-      const int comp = rc / m.n2, k = rc - comp * m.n2;
-      A[rc * m.pitch + jm_pad(m.c0 + col)] = C[((comp * m.M2p + jm_pad(k)) << m.cclog) + col];
-    }
-    __syncthreads();
-  }
-}
+// The transforms are the padded LDS stages of lds_fft.hpp (bank-conflict free
+// rows and position-major column chunks); twiddles are staged in LDS.
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* __restrict__ Um,
@@ -376,14 +194,14 @@ __global__ __launch_bounds__(1024) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* _
   const int rows = 6 * g.n2;
   for (int t = threadIdx.x; t < rows << wlog; t += blockDim.x) {
     const int x = t & ((1 << wlog) - 1), r = t >> wlog;
-    if (x < g.n1) A[r * pitch + jm_pad(x)] = r < 3 * g.n2 ? Pe[r * g.n1 + x] : Pm[(r - 3 * g.n2) * g.n1 + x];
+    if (x < g.n1) A[r * pitch + pad8(x)] = r < 3 * g.n2 ? Pe[r * g.n1 + x] : Pm[(r - 3 * g.n2) * g.n1 + x];
   }
   for (int t = threadIdx.x; t < g.M1; t += blockDim.x) W1[t] = tw1[t];
   for (int t = threadIdx.x; t < g.M2; t += blockDim.x) W2[t] = tw2[t];
   __syncthreads();
   // the electric rows, then the magnetic rows (half the plane per call)
-  jm_rows<T, false>(A, 3 * g.n2, pitch, g.L1, g.n1, W1, opaque_tid());
-  jm_rows<T, false>(A + 3 * g.n2 * pitch, 3 * g.n2, pitch, g.L1, g.n1, W1, opaque_tid());
+  pad_rows<T, false>(A, 3 * g.n2, pitch, g.L1, g.n1, W1, opaque_tid());
+  pad_rows<T, false>(A + 3 * g.n2 * pitch, 3 * g.n2, pitch, g.L1, g.n1, W1, opaque_tid());
 
   const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
   const T s3 = kz <= g.M3 / 2 ? (T)1 : (T)-1;
@@ -393,11 +211,11 @@ __global__ __launch_bounds__(1024) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* _
   while ((1 << cclog) < cc) ++cclog;
   const int npts = g.M2 << cclog;
   for (int c0 = 0; c0 < g.M1; c0 += cc) {
-    const JmCols m{cclog, M2p, g.n2, pitch, c0};
+    const PadCols m{6, cclog, M2p, g.n2, pitch, c0};
     // a fresh opaque thread index per chunk: otherwise every stage's per-lane
     // address terms are hoisted out of the chunk loop and held in registers
     const int tid = opaque_tid();
-    jm_cols<T, false>(A, C, m, g.L2, W2, tid);
+    pad_cols<T, false>(A, C, m, g.L2, W2, tid);
     // product points: col fastest, then ky
     for (int t = tid; t < npts; t += blockDim.x) {
       const int col = t & (cc - 1), ky = t >> cclog;
@@ -407,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* _
       const long f = (long)k2 * g.H1 + k1;
       const JmCoef<T> c =
           jm_coef<T>(G3 + f * 6, K3 + f * 3, kx <= g.M1 / 2 ? (T)1 : (T)-1, ky <= g.M2 / 2 ? (T)1 : (T)-1, s3);
-      const int o = ((jm_pad(ky)) << cclog) + col;
+      const int o = ((pad8(ky)) << cclog) + col;
       const int cs = M2p << cclog;
       cx<T> ue[3], um[3], oe[3], om[3];
 #pragma unroll
@@ -423,14 +241,14 @@ __global__ __launch_bounds__(1024) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* _
       }
     }
     __syncthreads();
-    jm_cols<T, true>(A, C, m, g.L2, W2, tid);
+    pad_cols<T, true>(A, C, m, g.L2, W2, tid);
   }
-  jm_rows<T, true>(A, 3 * g.n2, pitch, g.L1, g.M1, W1, opaque_tid());
-  jm_rows<T, true>(A + 3 * g.n2 * pitch, 3 * g.n2, pitch, g.L1, g.M1, W1, opaque_tid());
+  pad_rows<T, true>(A, 3 * g.n2, pitch, g.L1, g.M1, W1, opaque_tid());
+  pad_rows<T, true>(A + 3 * g.n2 * pitch, 3 * g.n2, pitch, g.L1, g.M1, W1, opaque_tid());
   for (int t = threadIdx.x; t < rows << wlog; t += blockDim.x) {
     const int x = t & ((1 << wlog) - 1), r = t >> wlog;
     if (x < g.n1) {
-      const cx<T> v = A[r * pitch + jm_pad(x)];
+      const cx<T> v = A[r * pitch + pad8(x)];
       if (r < 3 * g.n2) Pe[r * g.n1 + x] = v;
       else Pm[(r - 3 * g.n2) * g.n1 + x] = v;
     }
@@ -455,7 +273,7 @@ bool jm_fused_shape(const Geom& g, int* cc_out, int* threads_out) {
   // every stage holds at most kJmFusedMaxV values per thread (rows: one half at a time)
   const size_t rows = (size_t)3 * g.n2 * g.M1, cols = (size_t)6 * g.M2 * cc;
   const size_t need = rows > cols ? rows : cols;
-  int threads = (int)((need + kJmFusedMaxV<T> - 1) / kJmFusedMaxV<T>);
+  int threads = (int)((need + kPadMaxV - 1) / kPadMaxV);
   threads = ((threads + 63) / 64) * 64;
   if (threads < 256) threads = 256;
   if (threads > 1024) return false;

@@ -7,7 +7,7 @@
 //
 //   pass 1 (k_zfwd):  per z-pencil of one component: zero-pad n3 -> M3, forward
 //                     FFT, write kz-plane-major  U[kz][c][i2][i1]
-//   pass 2 (k_xyg):   per kz plane: forward FFT along i1 (pad n1 -> M1) and i2
+//   pass 2 (k_xyp):   per kz plane: forward FFT along i1 (pad n1 -> M1) and i2
 //                     (pad n2 -> M2), 3x3 symmetric product with the Green
 //                     spectrum, inverse FFT along i2 and i1, crop to n2 x n1
 //   pass 3 (k_zinv):  per z-pencil: inverse FFT, crop to n3, and the contrast:
@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_device.hpp"
+#include "lds_fft.hpp"
 #include "vie_internal.hpp"
 
 namespace vie {
@@ -108,22 +109,35 @@ __global__ __launch_bounds__(1024) void k_zinv(const cx<T>* __restrict__ U, cons
 }
 
 // ------------------------------------------------------------------ pass 2
+// Cross-sections other than 64 x 64: one workgroup per kz plane.  x transforms
+// of the 3 n2 valid rows, then for each chunk of cc x-frequencies the y
+// transforms, the 3 x 3 Green product and the inverse y transforms, finally the
+// inverse x transforms and the crop; U is read and overwritten in place.  The
+// transforms are the padded LDS stages of lds_fft.hpp (bank-conflict-free rows
+// and position-major column chunks); twiddles are staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_xyg(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, Geom g,
-                                               int cc, const cx<T>* __restrict__ tw1,
-                                               const cx<T>* __restrict__ tw2) {
+__global__ __launch_bounds__(1024) void k_xyp(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, Geom g, int cc,
+                                              const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2) {
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* rows = reinterpret_cast<cx<T>*>(smem_raw);      // [3][n2][M1]
-  cx<T>* cols = rows + 3 * g.n2 * g.M1;                   // [3][M2][cc]
+  const int pitch = g.M1 + (g.M1 >> 3);
+  const int M2p = g.M2 + (g.M2 >> 3);
+  cx<T>* A = reinterpret_cast<cx<T>*>(smem_raw);      // [3 n2][pitch]
+  cx<T>* C = A + 3 * g.n2 * pitch;                     // [3][M2p][cc]
+  cx<T>* W1 = C + 3 * M2p * cc;                        // twiddles of M1, then of M2
+  cx<T>* W2 = W1 + g.M1;
   const int kz = blockIdx.x;
-  const int plane = 3 * g.n1 * g.n2;
-  cx<T>* P = U + (long)kz * plane;
-  for (int t = threadIdx.x; t < plane; t += blockDim.x) {
-    const int x = t % g.n1, r = t / g.n1;
-    rows[r * g.M1 + x] = P[t];
+  cx<T>* P = U + (long)kz * 3 * g.n1 * g.n2;
+  // rows r < 3 n2, x < n1: lanes along x with a power-of-two row width
+  const int wlog = g.L1 > 0 ? g.L1 - 1 : 0;
+  const int rows = 3 * g.n2;
+  for (int t = threadIdx.x; t < rows << wlog; t += blockDim.x) {
+    const int x = t & ((1 << wlog) - 1), r = t >> wlog;
+    if (x < g.n1) A[r * pitch + pad8(x)] = P[r * g.n1 + x];
   }
+  for (int t = threadIdx.x; t < g.M1; t += blockDim.x) W1[t] = tw1[t];
+  for (int t = threadIdx.x; t < g.M2; t += blockDim.x) W2[t] = tw2[t];
   __syncthreads();
-  fft_lds<T, false, kMaxV>(rows, SeqMap{0, 0, g.M1, 1}, 3 * g.n2, g.L1, g.n1, tw1, 1);
+  pad_rows<T, false>(A, rows, pitch, g.L1, g.n1, W1, opaque_tid());
 
   // plane frequency along z, folded to the stored octant
   const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
@@ -131,18 +145,16 @@ __global__ __launch_bounds__(1024) void k_xyg(cx<T>* __restrict__ U, const cx<T>
   const cx<T>* G3 = goct + (long)k3 * g.H2 * g.H1 * 6;
   int cclog = 0;
   while ((1 << cclog) < cc) ++cclog;
-  const SeqMap cmap{cclog, 1, g.M2 * cc, cc};
-  const int cstride = g.M2 * cc;
+  const int npts = g.M2 << cclog;
+  const int cs = M2p << cclog;
   for (int c0 = 0; c0 < g.M1; c0 += cc) {
-    for (int t = threadIdx.x; t < 3 * g.n2 * cc; t += blockDim.x) {
-      const int col = t % cc, r = t / cc;           // r = comp * n2 + y
-      const int comp = r / g.n2, yy = r % g.n2;
-      cols[comp * cstride + yy * cc + col] = rows[r * g.M1 + c0 + col];
-    }
-    __syncthreads();
-    fft_lds<T, false, kMaxV>(cols, cmap, 3 * cc, g.L2, g.n2, tw2, 1);
-    for (int t = threadIdx.x; t < g.M2 * cc; t += blockDim.x) {
-      const int col = t % cc, ky = t / cc;
+    const PadCols m{3, cclog, M2p, g.n2, pitch, c0};
+    // a fresh opaque thread index per chunk keeps the stages' per-lane address
+    // terms from being hoisted out of the chunk loop
+    const int tid = opaque_tid();
+    pad_cols<T, false>(A, C, m, g.L2, W2, tid);
+    for (int t = tid; t < npts; t += blockDim.x) {
+      const int col = t & (cc - 1), ky = t >> cclog;
       const int kx = c0 + col;
       const int k1 = kx <= g.M1 / 2 ? kx : g.M1 - kx;
       const int k2 = ky <= g.M2 / 2 ? ky : g.M2 - ky;
@@ -151,25 +163,19 @@ __global__ __launch_bounds__(1024) void k_xyg(cx<T>* __restrict__ U, const cx<T>
       const cx<T>* Gp = G3 + ((long)k2 * g.H1 + k1) * 6;
       const cx<T> gxx = Gp[0], gyy = Gp[3], gzz = Gp[5];
       const cx<T> gxy = cscale(Gp[1], s1 * s2), gxz = cscale(Gp[2], s1 * s3), gyz = cscale(Gp[4], s2 * s3);
-      const int o = ky * cc + col;
-      const cx<T> ux = cols[o], uy = cols[cstride + o], uz = cols[2 * cstride + o];
-      cols[o] = cadd(cadd(cmul(gxx, ux), cmul(gxy, uy)), cmul(gxz, uz));
-      cols[cstride + o] = cadd(cadd(cmul(gxy, ux), cmul(gyy, uy)), cmul(gyz, uz));
-      cols[2 * cstride + o] = cadd(cadd(cmul(gxz, ux), cmul(gyz, uy)), cmul(gzz, uz));
+      const int o = (pad8(ky) << cclog) + col;
+      const cx<T> ux = C[o], uy = C[cs + o], uz = C[2 * cs + o];
+      C[o] = cadd(cadd(cmul(gxx, ux), cmul(gxy, uy)), cmul(gxz, uz));
+      C[cs + o] = cadd(cadd(cmul(gxy, ux), cmul(gyy, uy)), cmul(gyz, uz));
+      C[2 * cs + o] = cadd(cadd(cmul(gxz, ux), cmul(gyz, uy)), cmul(gzz, uz));
     }
     __syncthreads();
-    fft_lds<T, true, kMaxV>(cols, cmap, 3 * cc, g.L2, g.M2, tw2, 1);
-    for (int t = threadIdx.x; t < 3 * g.n2 * cc; t += blockDim.x) {
-      const int col = t % cc, r = t / cc;
-      const int comp = r / g.n2, yy = r % g.n2;
-      rows[r * g.M1 + c0 + col] = cols[comp * cstride + yy * cc + col];
-    }
-    __syncthreads();
+    pad_cols<T, true>(A, C, m, g.L2, W2, tid);
   }
-  fft_lds<T, true, kMaxV>(rows, SeqMap{0, 0, g.M1, 1}, 3 * g.n2, g.L1, g.M1, tw1, 1);
-  for (int t = threadIdx.x; t < plane; t += blockDim.x) {
-    const int x = t % g.n1, r = t / g.n1;
-    P[t] = rows[r * g.M1 + x];
+  pad_rows<T, true>(A, rows, pitch, g.L1, g.M1, W1, opaque_tid());
+  for (int t = threadIdx.x; t < rows << wlog; t += blockDim.x) {
+    const int x = t & ((1 << wlog) - 1), r = t >> wlog;
+    if (x < g.n1) P[r * g.n1 + x] = A[r * pitch + pad8(x)];
   }
 }
 
@@ -177,8 +183,11 @@ template <typename T>
 size_t z_lds_bytes(const Geom& g, int tp) { return (size_t)tp * (g.M3 + 1) * sizeof(cx<T>); }
 template <typename T>
 size_t xy_lds_bytes(const Geom& g, int cc) {
-  return ((size_t)3 * g.n2 * g.M1 + (size_t)3 * g.M2 * cc) * sizeof(cx<T>);
+  const size_t pitch = g.M1 + (g.M1 >> 3), M2p = g.M2 + (g.M2 >> 3);
+  return (3 * g.n2 * pitch + 3 * M2p * cc + g.M1 + g.M2) * sizeof(cx<T>);
 }
+template size_t xy_lds_bytes<double>(const Geom&, int);
+template size_t xy_lds_bytes<float>(const Geom&, int);
 
 template <typename T>
 hipError_t launch_pass(int which, const Geom& g, const Tune& t, const void* x, void* y, const void* b, int mode,
@@ -193,7 +202,7 @@ hipError_t launch_pass(int which, const Geom& g, const Tune& t, const void* x, v
   } else if (which == 1 && g.M1 == 64 && g.M2 == 64) {
     return launch_xy64<T>(g, t.xyv, U, goct, tw[0], s);
   } else if (which == 1) {
-    hipLaunchKernelGGL((k_xyg<T>), dim3(g.M3), dim3(t.xythreads), xy_lds_bytes<T>(g, t.cc), s, (C*)U,
+    hipLaunchKernelGGL((k_xyp<T>), dim3(g.M3), dim3(t.xythreads), xy_lds_bytes<T>(g, t.cc), s, (C*)U,
                        (const C*)goct, g, t.cc, (const C*)tw[0], (const C*)tw[1]);
   } else if (mode == 0) {
     hipLaunchKernelGGL((k_zinv<T, 0>), gz, dim3(t.zthreads), zl, s, (const C*)U, (const C*)x, (C*)y,
@@ -247,7 +256,7 @@ hipError_t allow_lds(size_t bytes) {
     return e;
   if ((e = allow_lds_xy64<T>())) return e;
   if ((e = allow_lds_z4<T>())) return e;
-  return hipFuncSetAttribute((const void*)k_xyg<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return hipFuncSetAttribute((const void*)k_xyp<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 template hipError_t allow_lds<double>(size_t);
 template hipError_t allow_lds<float>(size_t);

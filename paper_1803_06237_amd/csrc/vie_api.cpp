@@ -217,15 +217,17 @@ bool pick_tune(const Geom& g, size_t budget, size_t zbudget, Tune* t) {
   if (zt < 64) zt = 64;
   if (zt > 1024) return false;
   t->zthreads = zt < 256 ? (tp * g.M3 >= 256 ? 256 : zt) : zt;
+  // generic xy pass (cross-sections other than 64 x 64): column chunk cc within
+  // the LDS budget, at most 8 values per thread per transform stage
   int cc = g.M1 < 16 ? g.M1 : 16;
-  while (cc > 1 && ((size_t)3 * g.n2 * g.M1 + (size_t)3 * g.M2 * cc) * cs > budget) cc >>= 1;
-  if (((size_t)3 * g.n2 * g.M1 + (size_t)3 * g.M2 * cc) * cs > budget) return false;
+  while (cc > 1 && xy_lds_bytes<T>(g, cc) > budget) cc >>= 1;
+  if (xy_lds_bytes<T>(g, cc) > budget) return false;
   t->cc = cc;
   int need = 3 * g.n2 * g.M1;
   if (3 * g.M2 * cc > need) need = 3 * g.M2 * cc;
-  int xt = (need + 15) / 16;
+  int xt = (need + 7) / 8;
   xt = ((xt + 63) / 64) * 64;
-  if (xt < 256) xt = need >= 256 ? 256 : 64;
+  if (xt < 256) xt = 256;
   if (xt > 1024) return false;
   t->xythreads = xt;
   const size_t z4 = z4_lds_bytes<T>(g.M3);

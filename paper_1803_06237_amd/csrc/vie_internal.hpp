@@ -60,6 +60,10 @@ hipError_t launch_spectrum(const Geom& g, const double2* table_dev, double2* ful
 hipError_t launch_curl_spectrum(const Geom& g, const double2* ktable_dev, double2* full_tmp, double2* koct64,
                                 float2* koct32, const double2* const tw64[3], hipStream_t s);
 
+// LDS bytes of the generic xy pass with column chunks of cc x-frequencies
+template <typename T>
+size_t xy_lds_bytes(const Geom& g, int cc);
+
 // ---- JM-VIE product (jm.hip) --------------------------------------------------
 // y = (I - M T~) x on 6N vectors (electric then magnetic, each [3][n1][n2][n3]);
 // mode 1: y = b - (I - M T~) x.  Ue, Um: z-pass intermediates of each half.
