@@ -1,9 +1,10 @@
 // GMRES(m) and flexible GMRES(m) on the device (Section V-D: the discrete J-VIE
 // is solved by GMRES with matrix-vector products only).
 //
-// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): two sweeps of a fused
+// Arnoldi uses classical Gram-Schmidt with a selective second sweep: a fused
 // multi-dot h = V^H w over all basis vectors followed by a multi-axpy
-// w -= V h.  The Hessenberg matrix is kept in upper-triangular form with complex
+// w -= V h, repeated once when the first sweep cancelled more than the
+// criterion of Daniel, Gragg, Kaufman and Stewart allows (decided on the device).  The Hessenberg matrix is kept in upper-triangular form with complex
 // Givens rotations by one device thread; the host reads only the residual
 // estimate |g_{j+1}| / ||b|| after each step.  Reductions are two-stage and in
 // a fixed order, so results are bitwise reproducible run to run.  All
@@ -61,7 +62,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_mdot(const cx<T>* __restrict__ V, long ldv, int nv,
                                                     const cx<T>* __restrict__ w, long n,
-                                                    double2* __restrict__ partial) {
+                                                    double2* __restrict__ partial, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double lds[(kThreads / 64) * 2 * kGroup];
   const long e0 = (long)blockIdx.x * kChunk + threadIdx.x;
   double2 wv[kEPT];
@@ -99,7 +101,9 @@ __global__ __launch_bounds__(kThreads) void k_mdot(const cx<T>* __restrict__ V, 
 
 // out[i] (+)= sum_b partial[i * nblk + b], one workgroup per i, fixed order
 __global__ __launch_bounds__(kThreads) void k_reduce(const double2* __restrict__ partial, int nblk,
-                                                      double2* __restrict__ out, int accumulate) {
+                                                      double2* __restrict__ out, int accumulate,
+                                                      const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double lds[(kThreads / 64) * 2];
   const int i = blockIdx.x;
   double v[2] = {0.0, 0.0};
@@ -120,7 +124,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double2* __restrict__
 template <typename T, typename TW>
 __global__ __launch_bounds__(kThreads) void k_maxpy(const cx<T>* __restrict__ V, long ldv, int nv,
                                                      const double2* __restrict__ coef, double sign,
-                                                     cx<TW>* __restrict__ w, long n) {
+                                                     cx<TW>* __restrict__ w, long n, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double2 c[512];
   for (int i = threadIdx.x; i < nv && i < 512; i += kThreads) c[i] = double2{sign * coef[i].x, sign * coef[i].y};
   __syncthreads();
@@ -141,7 +146,9 @@ __global__ __launch_bounds__(kThreads) void k_maxpy(const cx<T>* __restrict__ V,
 // partial[blk] = sum |w|^2 over the block's chunk
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_nrm2_partial(const cx<T>* __restrict__ w, long n,
-                                                            double2* __restrict__ partial) {
+                                                            double2* __restrict__ partial,
+                                                            const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double lds[(kThreads / 64) * 2];
   const long e0 = (long)blockIdx.x * kChunk + threadIdx.x;
   double v[2] = {0.0, 0.0};
@@ -180,6 +187,24 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_zero(cx<T>* __restrict__ dst, long n) {
   for (long e = (long)blockIdx.x * kThreads + threadIdx.x; e < n; e += (long)gridDim.x * kThreads)
     dst[e] = cx<T>{(T)0, (T)0};
+}
+
+// Selective second Gram-Schmidt sweep (Daniel, Gragg, Kaufman and Stewart's
+// criterion with eta = 1/sqrt(2)): after the first sweep w' = w - V h, and for
+// an orthonormal V, ||w||^2 = ||w'||^2 + ||h||^2, so ||w'|| < eta ||w|| holds
+// exactly when ||w'||^2 < ||h||^2.  Then *gate = 1 and the second sweep runs;
+// otherwise *gate = 0, its kernels return at once and h2 is zeroed here (the
+// Hessenberg column is h1 + h2).  A non-finite norm keeps the second sweep.
+__global__ void k_dgks(const double2* __restrict__ h, int nv, const double2* __restrict__ sumsq,
+                       int* __restrict__ gate, double2* __restrict__ h2) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nv; i += 64) v += h[i].x * h[i].x + h[i].y * h[i].y;
+  v = wave_sum(v);
+  const double hh = __shfl(v, 0, 64);
+  const int again = (sumsq[0].x >= hh) ? 0 : 1;
+  if (threadIdx.x == 0) *gate = again;
+  if (!again)
+    for (int i = threadIdx.x; i < nv; i += 64) h2[i] = double2{0.0, 0.0};
 }
 
 // One Arnoldi step's Hessenberg bookkeeping (single thread).
@@ -305,33 +330,41 @@ __global__ __launch_bounds__(kThreads) void k_column_flags(const double2* __rest
 static inline int nblocks(long n) { return (int)((n + kChunk - 1) / kChunk); }
 
 template <typename T>
-hipError_t KrylovOps<T>::nrm2sq(const cx<T>* w, long n, double2* partial, double2* out, hipStream_t s) {
+hipError_t KrylovOps<T>::nrm2sq(const cx<T>* w, long n, double2* partial, double2* out, hipStream_t s,
+                                const int* gate) {
   const int nb = nblocks(n);
-  hipLaunchKernelGGL((k_nrm2_partial<T>), dim3(nb), dim3(kThreads), 0, s, w, n, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, partial, nb, out, 0);
+  hipLaunchKernelGGL((k_nrm2_partial<T>), dim3(nb), dim3(kThreads), 0, s, w, n, partial, gate);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, partial, nb, out, 0, gate);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t KrylovOps<T>::mdot(const cx<T>* V, long ldv, int nv, const cx<T>* w, long n, double2* partial,
-                              double2* out, int accumulate, hipStream_t s) {
+                              double2* out, int accumulate, hipStream_t s, const int* gate) {
   const int nb = nblocks(n);
   hipLaunchKernelGGL((k_mdot<T>), dim3(nb, (nv + kGroup - 1) / kGroup), dim3(kThreads), 0, s, V, ldv, nv, w, n,
-                     partial);
-  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kThreads), 0, s, partial, nb, out, accumulate);
+                     partial, gate);
+  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kThreads), 0, s, partial, nb, out, accumulate, gate);
   return hipGetLastError();
 }
 
 template <typename T>
 template <typename TW>
 hipError_t KrylovOps<T>::maxpy(const cx<T>* V, long ldv, int nv, const double2* coef, double sign, cx<TW>* w,
-                               long n, hipStream_t s) {
+                               long n, hipStream_t s, const int* gate) {
   for (int i0 = 0; i0 < nv; i0 += 512) {
     const int cnt = nv - i0 < 512 ? nv - i0 : 512;
     hipLaunchKernelGGL((k_maxpy<T, TW>), dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                        V + (long)i0 * ldv, ldv, cnt,
-                       coef + i0, sign, w, n);
+                       coef + i0, sign, w, n, gate);
   }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::dgks(const double2* h1, int nv, const double2* sumsq, int* gate, double2* h2,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, s, h1, nv, sumsq, gate, h2);
   return hipGetLastError();
 }
 
@@ -376,9 +409,9 @@ hipError_t convert(const cx<TS>* src, cx<TD>* dst, long n, hipStream_t s) {
 template struct KrylovOps<double>;
 template struct KrylovOps<float>;
 template hipError_t KrylovOps<double>::maxpy<double>(const cx<double>*, long, int, const double2*, double,
-                                                     cx<double>*, long, hipStream_t);
+                                                     cx<double>*, long, hipStream_t, const int*);
 template hipError_t KrylovOps<float>::maxpy<float>(const cx<float>*, long, int, const double2*, double,
-                                                   cx<float>*, long, hipStream_t);
+                                                   cx<float>*, long, hipStream_t, const int*);
 template hipError_t convert<double, float>(const cx<double>*, cx<float>*, long, hipStream_t);
 template hipError_t convert<float, double>(const cx<float>*, cx<double>*, long, hipStream_t);
 template hipError_t convert<double, double>(const cx<double>*, cx<double>*, long, hipStream_t);

@@ -9,14 +9,18 @@ namespace vie {
 template <typename T>
 struct KrylovOps {
   // out[0].x = ||w||^2 (FP64 accumulation); partial needs partial_blocks(n) entries
-  static hipError_t nrm2sq(const cx<T>* w, long n, double2* partial, double2* out, hipStream_t s);
+  // gate (device, optional): when *gate == 0 at run time the kernels do nothing
+  static hipError_t nrm2sq(const cx<T>* w, long n, double2* partial, double2* out, hipStream_t s,
+                           const int* gate = nullptr);
   // out[i] (+)= V_i^H w for i < nv; partial needs nv * partial_blocks(n) entries
   static hipError_t mdot(const cx<T>* V, long ldv, int nv, const cx<T>* w, long n, double2* partial,
-                         double2* out, int accumulate, hipStream_t s);
+                         double2* out, int accumulate, hipStream_t s, const int* gate = nullptr);
   // w += sign * sum_i coef[i] V_i
   template <typename TW>
   static hipError_t maxpy(const cx<T>* V, long ldv, int nv, const double2* coef, double sign, cx<TW>* w, long n,
-                          hipStream_t s);
+                          hipStream_t s, const int* gate = nullptr);
+  // *gate = 1 when ||w'||^2 = sumsq->x < ||h1||^2 (second sweep needed), else 0 and h2 = 0
+  static hipError_t dgks(const double2* h1, int nv, const double2* sumsq, int* gate, double2* h2, hipStream_t s);
   // dst = src / sqrt(sumsq->x)
   static hipError_t scale(const cx<T>* src, cx<T>* dst, long n, const double2* sumsq, hipStream_t s);
   static hipError_t zero(cx<T>* dst, long n, hipStream_t s);

@@ -87,10 +87,11 @@ struct GmresWs {
   double* cs = nullptr;
   double* state = nullptr;
   double* state_h = nullptr;
+  int* gate = nullptr;   // second Gram-Schmidt sweep needed (device flag)
 
   void release() {
     for (void* p : {(void*)V, (void*)Z, (void*)partial, (void*)h1, (void*)h2, (void*)sumsq, (void*)H, (void*)sn,
-                    (void*)g, (void*)y, (void*)cs, (void*)state})
+                    (void*)g, (void*)y, (void*)cs, (void*)state, (void*)gate})
       if (p) (void)hipFree(p);
     if (state_h) (void)hipHostFree(state_h);
     *this = GmresWs();
@@ -109,6 +110,7 @@ struct GmresWs {
     if ((e = hipMalloc(&h1, sizeof(double2) * (m + 2)))) return e;
     if ((e = hipMalloc(&h2, sizeof(double2) * (m + 2)))) return e;
     if ((e = hipMalloc(&sumsq, sizeof(double2) * 2))) return e;
+    if ((e = hipMalloc(&gate, sizeof(int)))) return e;
     if ((e = hipMalloc(&H, sizeof(double2) * (size_t)(m + 1) * m))) return e;
     if ((e = hipMalloc(&sn, sizeof(double2) * (m + 1)))) return e;
     if ((e = hipMalloc(&g, sizeof(double2) * (m + 1)))) return e;
@@ -508,9 +510,12 @@ int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, long n, const cx<T>* 
       st.matvecs++;
       HIPTRY(p, K::mdot(W.V, n, j + 1, w, n, W.partial, W.h1, 0, s));
       HIPTRY(p, K::template maxpy<T>(W.V, n, j + 1, W.h1, -1.0, w, n, s));
-      HIPTRY(p, K::mdot(W.V, n, j + 1, w, n, W.partial, W.h2, 0, s));
-      HIPTRY(p, K::template maxpy<T>(W.V, n, j + 1, W.h2, -1.0, w, n, s));
       HIPTRY(p, K::nrm2sq(w, n, W.partial, W.sumsq, s));
+      // second sweep only where the first cancelled too much (decided on the device)
+      HIPTRY(p, K::dgks(W.h1, j + 1, W.sumsq, W.gate, W.h2, s));
+      HIPTRY(p, K::mdot(W.V, n, j + 1, w, n, W.partial, W.h2, 0, s, W.gate));
+      HIPTRY(p, K::template maxpy<T>(W.V, n, j + 1, W.h2, -1.0, w, n, s, W.gate));
+      HIPTRY(p, K::nrm2sq(w, n, W.partial, W.sumsq, s, W.gate));
       HIPTRY(p, K::scale(w, w, n, W.sumsq, s));
       HIPTRY(p, K::arnoldi_update(W.h1, W.h2, W.sumsq, W.H, ldh, W.cs, W.sn, W.g, j, bnorm, W.state, s));
       HIPTRY(p, hipMemcpyAsync(W.state_h, W.state, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
