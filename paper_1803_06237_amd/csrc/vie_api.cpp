@@ -88,12 +88,15 @@ struct GmresWs {
   double* state = nullptr;
   double* state_h = nullptr;
   int* gate = nullptr;   // second Gram-Schmidt sweep needed (device flag)
+  hipEvent_t ev[2] = {nullptr, nullptr};   // step j's state copied to state_h + 4 (j & 1)
 
   void release() {
     for (void* p : {(void*)V, (void*)Z, (void*)partial, (void*)h1, (void*)h2, (void*)sumsq, (void*)H, (void*)sn,
                     (void*)g, (void*)y, (void*)cs, (void*)state, (void*)gate})
       if (p) (void)hipFree(p);
     if (state_h) (void)hipHostFree(state_h);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
     *this = GmresWs();
   }
   hipError_t ensure(long n_, int m_, bool flex_) {
@@ -117,7 +120,9 @@ struct GmresWs {
     if ((e = hipMalloc(&y, sizeof(double2) * (m + 1)))) return e;
     if ((e = hipMalloc(&cs, sizeof(double) * (m + 1)))) return e;
     if ((e = hipMalloc(&state, sizeof(double) * 4))) return e;
-    if ((e = hipHostMalloc(&state_h, sizeof(double) * 4, hipHostMallocDefault))) return e;
+    if ((e = hipHostMalloc(&state_h, sizeof(double) * 8, hipHostMallocDefault))) return e;
+    for (hipEvent_t& ev_i : ev)
+      if ((e = hipEventCreateWithFlags(&ev_i, hipEventDisableTiming))) return e;
     return hipSuccess;
   }
 };
@@ -496,35 +501,56 @@ int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, long n, const cx<T>* 
     if (st.iters >= maxit) break;
     HIPTRY(p, K::set_g(W.g, m, W.sumsq, s));
     HIPTRY(p, K::scale(V0, V0, n, W.sumsq, s));
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
+    // One Arnoldi step queued on the stream, ending with a copy of its state
+    // (residual estimate, breakdown, non-finite flags) to pinned slot j & 1.
+    auto step = [&](int j) -> hipError_t {
       cx<T>* Vj = W.V + (long)j * n;
       cx<T>* w = W.V + (long)(j + 1) * n;
       const cx<T>* z = Vj;
+      hipError_t e;
       if (M) {
         cx<T>* Zj = W.Z + (long)j * n;
-        HIPTRY(p, (*M)(Vj, Zj, st));
+        if ((e = (*M)(Vj, Zj, st))) return e;
         z = Zj;
       }
-      HIPTRY(p, A.apply(z, w));
+      if ((e = A.apply(z, w))) return e;
       st.matvecs++;
-      HIPTRY(p, K::mdot(W.V, n, j + 1, w, n, W.partial, W.h1, 0, s));
-      HIPTRY(p, K::template maxpy<T>(W.V, n, j + 1, W.h1, -1.0, w, n, s));
-      HIPTRY(p, K::nrm2sq(w, n, W.partial, W.sumsq, s));
+      if ((e = K::mdot(W.V, n, j + 1, w, n, W.partial, W.h1, 0, s))) return e;
+      if ((e = K::template maxpy<T>(W.V, n, j + 1, W.h1, -1.0, w, n, s))) return e;
+      if ((e = K::nrm2sq(w, n, W.partial, W.sumsq, s))) return e;
       // second sweep only where the first cancelled too much (decided on the device)
-      HIPTRY(p, K::dgks(W.h1, j + 1, W.sumsq, W.gate, W.h2, s));
-      HIPTRY(p, K::mdot(W.V, n, j + 1, w, n, W.partial, W.h2, 0, s, W.gate));
-      HIPTRY(p, K::template maxpy<T>(W.V, n, j + 1, W.h2, -1.0, w, n, s, W.gate));
-      HIPTRY(p, K::nrm2sq(w, n, W.partial, W.sumsq, s, W.gate));
-      HIPTRY(p, K::scale(w, w, n, W.sumsq, s));
-      HIPTRY(p, K::arnoldi_update(W.h1, W.h2, W.sumsq, W.H, ldh, W.cs, W.sn, W.g, j, bnorm, W.state, s));
-      HIPTRY(p, hipMemcpyAsync(W.state_h, W.state, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPTRY(p, hipStreamSynchronize(s));
+      if ((e = K::dgks(W.h1, j + 1, W.sumsq, W.gate, W.h2, s))) return e;
+      if ((e = K::mdot(W.V, n, j + 1, w, n, W.partial, W.h2, 0, s, W.gate))) return e;
+      if ((e = K::template maxpy<T>(W.V, n, j + 1, W.h2, -1.0, w, n, s, W.gate))) return e;
+      if ((e = K::nrm2sq(w, n, W.partial, W.sumsq, s, W.gate))) return e;
+      if ((e = K::scale(w, w, n, W.sumsq, s))) return e;
+      if ((e = K::arnoldi_update(W.h1, W.h2, W.sumsq, W.H, ldh, W.cs, W.sn, W.g, j, bnorm, W.state, s))) return e;
+      if ((e = hipMemcpyAsync(W.state_h + 4 * (j & 1), W.state, 3 * sizeof(double), hipMemcpyDeviceToHost, s)))
+        return e;
+      return hipEventRecord(W.ev[j & 1], s);
+    };
+    // Without a preconditioner the steps are pipelined: step j + 1 is queued
+    // before the host waits for step j's state, so the device does not idle
+    // through the host round trip.  A step queued after convergence is
+    // discarded: it writes only V_{j+2}, Hessenberg column j + 1 and g_{j+1},
+    // g_{j+2}, none of which the solution with k = j + 1 columns reads.  (The
+    // flexible variant's preconditioner synchronises by itself.)
+    const bool pipe = M == nullptr;
+    int k = 0;
+    if (pipe) HIPTRY(p, step(0));
+    for (int j = 0; j < m; ++j) {
+      if (!pipe) HIPTRY(p, step(j));
+      else if (j + 1 < m && st.iters + 2 <= maxit) HIPTRY(p, step(j + 1));
+      HIPTRY(p, hipEventSynchronize(W.ev[j & 1]));
+      const double* sh = W.state_h + 4 * (j & 1);
       st.iters++;
       k = j + 1;
-      st.est = W.state_h[0];
-      if (W.state_h[2] != 0.0) return fail(p, VIE_ENUMERIC, "non-finite value in Arnoldi step");
-      if (W.state_h[0] <= tol || W.state_h[1] == 0.0 || st.iters >= maxit) break;
+      st.est = sh[0];
+      if (sh[2] != 0.0) {
+        (void)hipStreamSynchronize(s);
+        return fail(p, VIE_ENUMERIC, "non-finite value in Arnoldi step");
+      }
+      if (sh[0] <= tol || sh[1] == 0.0 || st.iters >= maxit) break;
     }
     HIPTRY(p, K::trisolve(W.H, ldh, W.g, k, W.y, s));
     HIPTRY(p, K::template maxpy<T>(M ? W.Z : W.V, n, k, W.y, 1.0, x, n, s));
