@@ -103,3 +103,24 @@ def test_maxit_reports_noconv_with_best_iterate(small_strip):
     assert info["status"] == vie.VIE_ENOCONV
     rr = _oracle_rel_res(op, b_gau, x.cpu().numpy())
     assert rr < 1.0 and abs(rr - info["rel_res_true"]) < 1e-10
+
+
+@pytest.mark.parametrize("maxit", [1, 2, 4, 5, 6, 9, 13])
+def test_truncated_gmres_matches_oracle_gmres(small_strip, maxit):
+    """After every step count the device GMRES(5) iterate is the oracle's GMRES(5)
+    iterate: maxit inside a restart cycle (a following step is already queued on the
+    device and must be discarded), at its end, and across restarts.  The dipole
+    right-hand side lies on the contrast's support, where the device's compressed
+    Krylov space equals the full one."""
+    vie = _dev()
+    wg, op, plan, b_dip, _, _ = small_strip
+    x, info = plan.solve(torch.from_numpy(b_dip).cuda(), tol=1e-14, restart=5, maxit=maxit)
+    xo, io = solve.gmres(op, b_dip.ravel(), tol=1e-14, restart=5, maxit=maxit)
+    assert info["status"] == vie.VIE_ENOCONV and info["iters"] == maxit == io.iters
+    xg = x.cpu().numpy().ravel()
+    rr = _oracle_rel_res(op, b_dip, xg)
+    ro = np.linalg.norm(b_dip.ravel() - op(xo)) / np.linalg.norm(b_dip)
+    print(maxit, rr, ro, info["rel_res_est"], io.history[-1])
+    assert abs(rr - ro) <= 1e-9 * ro
+    assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert abs(info["rel_res_est"] - io.history[-1]) <= 1e-9 * io.history[-1]
