@@ -14,9 +14,9 @@
 // elements through an LDS staging array [kz][P + 1] (padded against bank
 // conflicts); the z-contiguous vectors x, y, chi are accessed directly.
 //
-// In FP64 the exchange moves the real parts, then the imaginary parts, and the
-// staging array holds one half of the kz range at a time.  That halves the LDS
-// of a pencil (8 KiB at M3 = 1024), so a CU holds twice as many pencils: at
+// The exchange moves the real parts, then the imaginary parts, and the staging
+// array holds one half of the kz range at a time.  That halves the LDS of a
+// pencil (8 KiB at M3 = 1024 in FP64), so a CU holds twice as many pencils: at
 // 32 x 32 x 512 every pencil of a pass is resident at once instead of in one
 // and a half rounds of workgroups.
 #include <hip/hip_runtime.h>
@@ -44,11 +44,12 @@ __device__ __forceinline__ int xcd_pair(int b, int nblocks) {
   return base + 2 * (r % 8) + r / 8;
 }
 
-// FP64 pencils exchange real and imaginary parts separately and stage half of
-// the kz range at a time
+// Pencils exchange real and imaginary parts separately and stage half of the
+// kz range at a time (both precisions: it halves the LDS of a workgroup, so
+// twice as many are resident; FP32 forward pass 21.4 -> 15.6 us at 32x32x512)
 template <typename T>
 constexpr bool z4_split() {
-  return sizeof(T) == 8;
+  return true;
 }
 
 // Thread a of pencil p hands v[k1] to the owner of frequency k1; afterwards
