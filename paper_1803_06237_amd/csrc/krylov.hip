@@ -218,52 +218,63 @@ __global__ void k_arnoldi_update(const double2* __restrict__ h1, const double2* 
                                  double2* __restrict__ H, int ldh, double* __restrict__ cs,
                                  double2* __restrict__ sn, double2* __restrict__ gvec, int j, double bnorm,
                                  double* __restrict__ state) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // the new column h = h1 + h2 is staged in LDS by the whole block; one thread
+  // then sweeps the previous rotations down it with the running entry in a
+  // register (the loads of h, cs, sn do not depend on the sweep, so they are
+  // issued ahead of it), and the block writes the column back
+  extern __shared__ unsigned char smem_raw[];
+  double2* hs = reinterpret_cast<double2*>(smem_raw);   // j + 2 entries
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] = double2{h1[i].x + h2[i].x, h1[i].y + h2[i].y};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(sumsq->x);
+    // previous rotations: [c s; -conj(s) c] on (h_i, h_{i+1})
+    double2 a = hs[0];
+    for (int i = 0; i < j; ++i) {
+      const double2 b = hs[i + 1];
+      const double c = cs[i];
+      const double2 s = sn[i];
+      hs[i] = double2{c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x)};
+      a = double2{-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y};
+    }
+    // new rotation zeroing h_{j+1} = ||w||
+    const double2 b = double2{hn, 0.0};
+    const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+    double c;
+    double2 sv, r;
+    if (nb == 0.0) {
+      c = 1.0;
+      sv = double2{0.0, 0.0};
+      r = a;
+    } else if (na == 0.0) {
+      c = 0.0;
+      sv = double2{1.0, 0.0};
+      r = b;
+    } else {
+      const double t = hypot(na, nb);
+      const double2 ph = double2{a.x / na, a.y / na};
+      c = na / t;
+      // s = ph * conj(b) / t
+      sv = double2{(ph.x * b.x + ph.y * b.y) / t, (ph.y * b.x - ph.x * b.y) / t};
+      r = double2{ph.x * t, ph.y * t};
+    }
+    cs[j] = c;
+    sn[j] = sv;
+    hs[j] = r;
+    hs[j + 1] = double2{0.0, 0.0};
+    const double2 gj = gvec[j];
+    // g_{j+1} = -conj(s) g_j ; g_j = c g_j
+    const double2 gn = double2{-(sv.x * gj.x + sv.y * gj.y), -(sv.x * gj.y - sv.y * gj.x)};
+    gvec[j + 1] = gn;
+    gvec[j] = double2{c * gj.x, c * gj.y};
+    const double est = hypot(gn.x, gn.y) / bnorm;
+    state[0] = est;
+    state[1] = hn;
+    state[2] = (isfinite(est) && isfinite(hn) && isfinite(r.x) && isfinite(r.y)) ? 0.0 : 1.0;
+  }
+  __syncthreads();
   double2* h = H + (long)j * ldh;
-  for (int i = 0; i <= j; ++i) h[i] = double2{h1[i].x + h2[i].x, h1[i].y + h2[i].y};
-  const double hn = sqrt(sumsq->x);
-  h[j + 1] = double2{hn, 0.0};
-  // previous rotations: [c s; -conj(s) c]
-  for (int i = 0; i < j; ++i) {
-    const double2 a = h[i], b = h[i + 1];
-    const double c = cs[i];
-    const double2 s = sn[i];
-    h[i] = double2{c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x)};
-    h[i + 1] = double2{-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y};
-  }
-  // new rotation zeroing h[j+1]
-  const double2 a = h[j], b = h[j + 1];
-  const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
-  double c;
-  double2 s, r;
-  if (nb == 0.0) {
-    c = 1.0;
-    s = double2{0.0, 0.0};
-    r = a;
-  } else if (na == 0.0) {
-    c = 0.0;
-    s = double2{1.0, 0.0};
-    r = b;
-  } else {
-    const double t = hypot(na, nb);
-    const double2 ph = double2{a.x / na, a.y / na};
-    c = na / t;
-    // s = ph * conj(b) / t
-    s = double2{(ph.x * b.x + ph.y * b.y) / t, (ph.y * b.x - ph.x * b.y) / t};
-    r = double2{ph.x * t, ph.y * t};
-  }
-  cs[j] = c;
-  sn[j] = s;
-  h[j] = r;
-  h[j + 1] = double2{0.0, 0.0};
-  const double2 gj = gvec[j];
-  // g_{j+1} = -conj(s) g_j ; g_j = c g_j
-  gvec[j + 1] = double2{-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x)};
-  gvec[j] = double2{c * gj.x, c * gj.y};
-  const double est = hypot(gvec[j + 1].x, gvec[j + 1].y) / bnorm;
-  state[0] = est;
-  state[1] = hn;
-  state[2] = (isfinite(est) && isfinite(hn) && isfinite(r.x) && isfinite(r.y)) ? 0.0 : 1.0;
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) h[i] = hs[i];
 }
 
 // y = R^{-1} g for the leading k x k upper triangle of H (single thread)
@@ -384,7 +395,12 @@ template <typename T>
 hipError_t KrylovOps<T>::arnoldi_update(const double2* h1, const double2* h2, const double2* sumsq, double2* H,
                                         int ldh, double* cs, double2* sn, double2* g, int j, double bnorm,
                                         double* state, hipStream_t s) {
-  hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(64), 0, s, h1, h2, sumsq, H, ldh, cs, sn, g, j, bnorm, state);
+  // up to 4097 staged values (restart <= 4096): a little above the default 64 KiB
+  static const hipError_t lds_ok = hipFuncSetAttribute((const void*)k_arnoldi_update,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 4098 * 16);
+  if (lds_ok != hipSuccess) return lds_ok;
+  hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(64), (size_t)(j + 2) * sizeof(double2), s, h1, h2, sumsq, H,
+                     ldh, cs, sn, g, j, bnorm, state);
   return hipGetLastError();
 }
 
