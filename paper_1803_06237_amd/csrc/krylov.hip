@@ -189,6 +189,64 @@ __global__ __launch_bounds__(kThreads) void k_zero(cx<T>* __restrict__ dst, long
     dst[e] = cx<T>{(T)0, (T)0};
 }
 
+// w += sign * sum_i coef[i] V_i (nv <= 512) and, of the stored result, the block
+// partial sums of |w|^2: partial[blk] (blocks of kThreads elements).  Saves the
+// separate norm pass over w.
+template <typename T, typename TW>
+__global__ __launch_bounds__(kThreads) void k_maxpy_nrm(const cx<T>* __restrict__ V, long ldv, int nv,
+                                                         const double2* __restrict__ coef, double sign,
+                                                         cx<TW>* __restrict__ w, long n,
+                                                         double2* __restrict__ partial,
+                                                         const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ double2 c[512];
+  __shared__ double lds[kThreads / 64];
+  for (int i = threadIdx.x; i < nv && i < 512; i += kThreads) c[i] = double2{sign * coef[i].x, sign * coef[i].y};
+  __syncthreads();
+  const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+  double v[1] = {0.0};
+  if (e < n) {
+    double2 acc = to_d(w[e]);
+    const cx<T>* Ve = V + e;
+#pragma unroll 4
+    for (int i = 0; i < nv; ++i) {
+      const double2 ci = c[i];
+      const double2 a = to_d(Ve[(long)i * ldv]);
+      acc.x += ci.x * a.x - ci.y * a.y;
+      acc.y += ci.x * a.y + ci.y * a.x;
+    }
+    const cx<TW> out = from_d<cx<TW>>(acc);
+    w[e] = out;
+    const double2 o = to_d(out);
+    v[0] = o.x * o.x + o.y * o.y;
+  }
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = double2{v[0], 0.0};
+}
+
+// First-sweep norm and the second-sweep decision in one block: sumsq = sum of
+// the partials (||w'||^2), then the criterion below on ||h||^2.
+__global__ __launch_bounds__(kThreads) void k_reduce_dgks(const double2* __restrict__ partial, int nblk,
+                                                           double2* __restrict__ sumsq,
+                                                           const double2* __restrict__ h, int nv,
+                                                           int* __restrict__ gate, double2* __restrict__ h2) {
+  __shared__ double lds[(kThreads / 64) * 2];
+  __shared__ int s_again;
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v[0] += partial[b].x;
+  for (int i = threadIdx.x; i < nv; i += kThreads) v[1] += h[i].x * h[i].x + h[i].y * h[i].y;
+  block_sum<2>(v, lds);
+  if (threadIdx.x == 0) {
+    sumsq[0] = double2{v[0], 0.0};
+    const int again = (v[0] >= v[1]) ? 0 : 1;
+    *gate = again;
+    s_again = again;
+  }
+  __syncthreads();
+  if (!s_again)
+    for (int i = threadIdx.x; i < nv; i += kThreads) h2[i] = double2{0.0, 0.0};
+}
+
 // Selective second Gram-Schmidt sweep (Daniel, Gragg, Kaufman and Stewart's
 // criterion with eta = 1/sqrt(2)): after the first sweep w' = w - V h, and for
 // an orthonormal V, ||w||^2 = ||w'||^2 + ||h||^2, so ||w'|| < eta ||w|| holds
@@ -373,6 +431,31 @@ hipError_t KrylovOps<T>::maxpy(const cx<T>* V, long ldv, int nv, const double2* 
 }
 
 template <typename T>
+template <typename TW>
+hipError_t KrylovOps<T>::maxpy_nrm(const cx<T>* V, long ldv, int nv, const double2* coef, double sign, cx<TW>* w,
+                                   long n, double2* partial, hipStream_t s, const int* gate) {
+  if (nv > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_maxpy_nrm<T, TW>), dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, V,
+                     ldv, nv, coef, sign, w, n, partial, gate);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::reduce_dgks(const double2* partial, int nblk, double2* sumsq, const double2* h1, int nv,
+                                     int* gate, double2* h2, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_dgks, dim3(1), dim3(kThreads), 0, s, partial, nblk, sumsq, h1, nv, gate, h2);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t KrylovOps<T>::reduce(const double2* partial, int nblk, double2* out, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, partial, nblk, out, 0, gate);
+  return hipGetLastError();
+}
+
+int maxpy_blocks(long n) { return (int)((n + kThreads - 1) / kThreads); }
+
+template <typename T>
 hipError_t KrylovOps<T>::dgks(const double2* h1, int nv, const double2* sumsq, int* gate, double2* h2,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, s, h1, nv, sumsq, gate, h2);
@@ -424,6 +507,10 @@ hipError_t convert(const cx<TS>* src, cx<TD>* dst, long n, hipStream_t s) {
 
 template struct KrylovOps<double>;
 template struct KrylovOps<float>;
+template hipError_t KrylovOps<double>::maxpy_nrm<double>(const cx<double>*, long, int, const double2*, double,
+                                                         cx<double>*, long, double2*, hipStream_t, const int*);
+template hipError_t KrylovOps<float>::maxpy_nrm<float>(const cx<float>*, long, int, const double2*, double,
+                                                       cx<float>*, long, double2*, hipStream_t, const int*);
 template hipError_t KrylovOps<double>::maxpy<double>(const cx<double>*, long, int, const double2*, double,
                                                      cx<double>*, long, hipStream_t, const int*);
 template hipError_t KrylovOps<float>::maxpy<float>(const cx<float>*, long, int, const double2*, double,

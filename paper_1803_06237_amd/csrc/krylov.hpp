@@ -21,6 +21,15 @@ struct KrylovOps {
                           hipStream_t s, const int* gate = nullptr);
   // *gate = 1 when ||w'||^2 = sumsq->x < ||h1||^2 (second sweep needed), else 0 and h2 = 0
   static hipError_t dgks(const double2* h1, int nv, const double2* sumsq, int* gate, double2* h2, hipStream_t s);
+  // maxpy (nv <= 512) that also writes the block partial sums of |w|^2 to partial[0, maxpy_blocks(n))
+  template <typename TW>
+  static hipError_t maxpy_nrm(const cx<T>* V, long ldv, int nv, const double2* coef, double sign, cx<TW>* w, long n,
+                              double2* partial, hipStream_t s, const int* gate = nullptr);
+  // sumsq = sum of nblk partials, then the second-sweep decision of dgks in the same block
+  static hipError_t reduce_dgks(const double2* partial, int nblk, double2* sumsq, const double2* h1, int nv,
+                                int* gate, double2* h2, hipStream_t s);
+  // out[0].x = sum of nblk partials
+  static hipError_t reduce(const double2* partial, int nblk, double2* out, hipStream_t s, const int* gate = nullptr);
   // dst = src / sqrt(sumsq->x)
   static hipError_t scale(const cx<T>* src, cx<T>* dst, long n, const double2* sumsq, hipStream_t s);
   static hipError_t zero(cx<T>* dst, long n, hipStream_t s);
@@ -57,5 +66,7 @@ hipError_t zero_support(const Support& u, cx<T>* full, hipStream_t s);
 hipError_t column_flags(const double2* chi, long n12, int n3, int* flags, hipStream_t s);
 
 int partial_blocks(long n);
+// blocks (partial sums) of maxpy_nrm over n elements
+int maxpy_blocks(long n);
 
 }  // namespace vie

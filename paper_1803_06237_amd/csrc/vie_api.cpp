@@ -516,13 +516,24 @@ int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, long n, const cx<T>* 
       if ((e = A.apply(z, w))) return e;
       st.matvecs++;
       if ((e = K::mdot(W.V, n, j + 1, w, n, W.partial, W.h1, 0, s))) return e;
-      if ((e = K::template maxpy<T>(W.V, n, j + 1, W.h1, -1.0, w, n, s))) return e;
-      if ((e = K::nrm2sq(w, n, W.partial, W.sumsq, s))) return e;
-      // second sweep only where the first cancelled too much (decided on the device)
-      if ((e = K::dgks(W.h1, j + 1, W.sumsq, W.gate, W.h2, s))) return e;
-      if ((e = K::mdot(W.V, n, j + 1, w, n, W.partial, W.h2, 0, s, W.gate))) return e;
-      if ((e = K::template maxpy<T>(W.V, n, j + 1, W.h2, -1.0, w, n, s, W.gate))) return e;
-      if ((e = K::nrm2sq(w, n, W.partial, W.sumsq, s, W.gate))) return e;
+      if (j + 1 <= 512) {
+        // the multi-axpy also sums |w'|^2 per block; one block reduces and takes
+        // the second-sweep decision (decided on the device)
+        const int nbm = maxpy_blocks(n);
+        if ((e = K::template maxpy_nrm<T>(W.V, n, j + 1, W.h1, -1.0, w, n, W.partial, s))) return e;
+        if ((e = K::reduce_dgks(W.partial, nbm, W.sumsq, W.h1, j + 1, W.gate, W.h2, s))) return e;
+        if ((e = K::mdot(W.V, n, j + 1, w, n, W.partial, W.h2, 0, s, W.gate))) return e;
+        if ((e = K::template maxpy_nrm<T>(W.V, n, j + 1, W.h2, -1.0, w, n, W.partial, s, W.gate))) return e;
+        if ((e = K::reduce(W.partial, nbm, W.sumsq, s, W.gate))) return e;
+      } else {
+        if ((e = K::template maxpy<T>(W.V, n, j + 1, W.h1, -1.0, w, n, s))) return e;
+        if ((e = K::nrm2sq(w, n, W.partial, W.sumsq, s))) return e;
+        // second sweep only where the first cancelled too much (decided on the device)
+        if ((e = K::dgks(W.h1, j + 1, W.sumsq, W.gate, W.h2, s))) return e;
+        if ((e = K::mdot(W.V, n, j + 1, w, n, W.partial, W.h2, 0, s, W.gate))) return e;
+        if ((e = K::template maxpy<T>(W.V, n, j + 1, W.h2, -1.0, w, n, s, W.gate))) return e;
+        if ((e = K::nrm2sq(w, n, W.partial, W.sumsq, s, W.gate))) return e;
+      }
       if ((e = K::scale(w, w, n, W.sumsq, s))) return e;
       if ((e = K::arnoldi_update(W.h1, W.h2, W.sumsq, W.H, ldh, W.cs, W.sn, W.g, j, bnorm, W.state, s))) return e;
       if ((e = hipMemcpyAsync(W.state_h + 4 * (j & 1), W.state, 3 * sizeof(double), hipMemcpyDeviceToHost, s)))
