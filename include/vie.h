@@ -323,9 +323,10 @@ const char* vie_net_last_error(vie_net_t net);
  *   The cross-section pass runs fused (spectra in LDS) when the six
  *   row-transformed components of a plane fit with one column chunk:
  *   (6 n2 M1 + 6 M2 cc) complex values in 160 KiB for some cc >= 1 (every FP32
- *   grid; in FP64 e.g. the 30 x 12 strip, not a 32 x 32 cross-section);
- *   otherwise through full spectra in HBM (6 M1 M2 M3 complex values per
- *   precision, allocated only then).
+ *   grid; in FP64 e.g. the 30 x 12 strip), else with the x-frequencies in two
+ *   halves of M1/2 (even and odd kx in turn; in FP64 the 32 x 32
+ *   cross-section); otherwise through full spectra in HBM (6 M1 M2 M3 complex
+ *   values per precision, allocated only then).
  * vie_jm_set_route / vie_jm_get_route -- per precision (0 FP64, 1 FP32): fused 1
  *   = the fused pass (VIE_EINVAL where it does not fit), 0 = through HBM
  *   (allocates the spectra on first use).  Same results to rounding.

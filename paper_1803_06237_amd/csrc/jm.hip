@@ -173,35 +173,46 @@ __global__ void k_jm_product(cx<T>* __restrict__ S, const cx<T>* __restrict__ go
 // The transforms are the padded LDS stages of lds_fft.hpp (bank-conflict free
 // rows and position-major column chunks); twiddles are staged in LDS.
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* __restrict__ Um,
-                                                const cx<T>* __restrict__ goct, const cx<T>* __restrict__ koct,
-                                                Geom g, int cc, T kappa, const cx<T>* __restrict__ tw1,
-                                                const cx<T>* __restrict__ tw2) {
+// SPLIT = 2 (cross-sections whose full rows of six components do not fit in
+// LDS): the x-frequencies in two halves.  With x_n = 0 for n >= M1/2, the
+// M1-point transform splits into X[2m] = DFT_{M1/2}(x)[m] and
+// X[2m + 1] = DFT_{M1/2}(x_n W^n)[m], W = exp(-2 pi i / M1); the inverse with
+// the crop to n < M1/2 is y_n = IDFT(Y_even)_n + W^{-n} IDFT(Y_odd)_n.  The
+// workgroup runs both halves in turn on half-length rows and keeps the first
+// half's output in registers (kAcc values per thread).
+template <int SPLIT>
+constexpr int kJmXyThreads = SPLIT == 1 ? 1024 : 512;
+constexpr int kJmAcc = 16;
+
+template <typename T, int SPLIT>
+__global__ __launch_bounds__(kJmXyThreads<SPLIT>) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* __restrict__ Um,
+                                                               const cx<T>* __restrict__ goct,
+                                                               const cx<T>* __restrict__ koct, Geom g, int cc,
+                                                               T kappa, const cx<T>* __restrict__ tw1,
+                                                               const cx<T>* __restrict__ tw2) {
   extern __shared__ unsigned char smem_raw[];
-  const int pitch = g.M1 + (g.M1 >> 3);
+  const int Mx = g.M1 / SPLIT;                          // row transform length
+  const int Lx = g.L1 - (SPLIT == 2 ? 1 : 0);
+  const int pitch = Mx + (Mx >> 3);
   const int M2p = g.M2 + (g.M2 >> 3);
   cx<T>* A = reinterpret_cast<cx<T>*>(smem_raw);       // [6 n2][pitch]: e components, then m
   cx<T>* C = A + 6 * g.n2 * pitch;                      // [6][M2p][cc]
-  cx<T>* W1 = C + 6 * M2p * cc;                         // twiddles of M1, then of M2
-  cx<T>* W2 = W1 + g.M1;
+  cx<T>* W2 = C + 6 * M2p * cc;                         // twiddles of M2
+  cx<T>* W1 = W2 + g.M2;                                // twiddles of M1 (the twist W^n)
+  cx<T>* Wx = SPLIT == 1 ? W1 : W1 + g.M1;              // twiddles of the row length
   const int kz = blockIdx.x;
   const int plane = 3 * g.n1 * g.n2;
   cx<T>* Pe = Ue + (long)kz * plane;
   cx<T>* Pm = Um + (long)kz * plane;
-  // rows r < 6 n2, x < n1: lanes along x with a power-of-two row width
-  const int wlog = g.L1 > 0 ? g.L1 - 1 : 0;
-  const int rows = 6 * g.n2;
-  for (int t = threadIdx.x; t < rows << wlog; t += blockDim.x) {
-    const int x = t & ((1 << wlog) - 1), r = t >> wlog;
-    if (x < g.n1) A[r * pitch + pad8(x)] = r < 3 * g.n2 ? Pe[r * g.n1 + x] : Pm[(r - 3 * g.n2) * g.n1 + x];
-  }
   for (int t = threadIdx.x; t < g.M1; t += blockDim.x) W1[t] = tw1[t];
   for (int t = threadIdx.x; t < g.M2; t += blockDim.x) W2[t] = tw2[t];
-  __syncthreads();
-  // the electric rows, then the magnetic rows (half the plane per call)
-  pad_rows<T, false>(A, 3 * g.n2, pitch, g.L1, g.n1, W1, opaque_tid());
-  pad_rows<T, false>(A + 3 * g.n2 * pitch, 3 * g.n2, pitch, g.L1, g.n1, W1, opaque_tid());
+  if (SPLIT == 2)
+    for (int t = threadIdx.x; t < Mx; t += blockDim.x) Wx[t] = tw1[2 * t];
+  // rows r < 6 n2, x < n1: lanes along x with a power-of-two row width (M1/2 >= n1)
+  const int wlog = g.L1 > 0 ? g.L1 - 1 : 0;
+  const int rows = 6 * g.n2;
+  const int items = rows << wlog;
+  cx<T> acc[SPLIT == 2 ? kJmAcc : 1];
 
   const int k3 = kz <= g.M3 / 2 ? kz : g.M3 - kz;
   const T s3 = kz <= g.M3 / 2 ? (T)1 : (T)-1;
@@ -210,47 +221,80 @@ __global__ __launch_bounds__(1024) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* _
   int cclog = 0;
   while ((1 << cclog) < cc) ++cclog;
   const int npts = g.M2 << cclog;
-  for (int c0 = 0; c0 < g.M1; c0 += cc) {
-    const PadCols m{6, cclog, M2p, g.n2, pitch, c0};
-    // a fresh opaque thread index per chunk: otherwise every stage's per-lane
-    // address terms are hoisted out of the chunk loop and held in registers
-    const int tid = opaque_tid();
-    pad_cols<T, false>(A, C, m, g.L2, W2, tid);
-    // product points: col fastest, then ky
-    for (int t = tid; t < npts; t += blockDim.x) {
-      const int col = t & (cc - 1), ky = t >> cclog;
-      const int kx = c0 + col;
-      const int k1 = kx <= g.M1 / 2 ? kx : g.M1 - kx;
-      const int k2 = ky <= g.M2 / 2 ? ky : g.M2 - ky;
-      const long f = (long)k2 * g.H1 + k1;
-      const JmCoef<T> c =
-          jm_coef<T>(G3 + f * 6, K3 + f * 3, kx <= g.M1 / 2 ? (T)1 : (T)-1, ky <= g.M2 / 2 ? (T)1 : (T)-1, s3);
-      const int o = ((pad8(ky)) << cclog) + col;
-      const int cs = M2p << cclog;
-      cx<T> ue[3], um[3], oe[3], om[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        ue[a] = C[a * cs + o];
-        um[a] = C[(3 + a) * cs + o];
-      }
-      jm_apply<T>(c, kappa, ue, um, oe, om);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        C[a * cs + o] = oe[a];
-        C[(3 + a) * cs + o] = om[a];
+  for (int h = 0; h < SPLIT; ++h) {
+    __syncthreads();   // the rows of the previous half have been read
+    for (int t = threadIdx.x; t < items; t += blockDim.x) {
+      const int x = t & ((1 << wlog) - 1), r = t >> wlog;
+      if (x < g.n1) {
+        cx<T> v = r < 3 * g.n2 ? Pe[r * g.n1 + x] : Pm[(r - 3 * g.n2) * g.n1 + x];
+        if (SPLIT == 2 && h == 1) v = cmul(v, W1[x]);
+        A[r * pitch + pad8(x)] = v;
       }
     }
     __syncthreads();
-    pad_cols<T, true>(A, C, m, g.L2, W2, tid);
-  }
-  pad_rows<T, true>(A, 3 * g.n2, pitch, g.L1, g.M1, W1, opaque_tid());
-  pad_rows<T, true>(A + 3 * g.n2 * pitch, 3 * g.n2, pitch, g.L1, g.M1, W1, opaque_tid());
-  for (int t = threadIdx.x; t < rows << wlog; t += blockDim.x) {
-    const int x = t & ((1 << wlog) - 1), r = t >> wlog;
-    if (x < g.n1) {
-      const cx<T> v = A[r * pitch + pad8(x)];
-      if (r < 3 * g.n2) Pe[r * g.n1 + x] = v;
-      else Pm[(r - 3 * g.n2) * g.n1 + x] = v;
+    // the electric rows, then the magnetic rows (half the plane per call)
+    pad_rows<T, false>(A, 3 * g.n2, pitch, Lx, g.n1, Wx, opaque_tid());
+    pad_rows<T, false>(A + 3 * g.n2 * pitch, 3 * g.n2, pitch, Lx, g.n1, Wx, opaque_tid());
+    for (int c0 = 0; c0 < Mx; c0 += cc) {
+      const PadCols m{6, cclog, M2p, g.n2, pitch, c0};
+      // a fresh opaque thread index per chunk: otherwise every stage's per-lane
+      // address terms are hoisted out of the chunk loop and held in registers
+      const int tid = opaque_tid();
+      pad_cols<T, false>(A, C, m, g.L2, W2, tid);
+      // product points: col fastest, then ky
+      for (int t = tid; t < npts; t += blockDim.x) {
+        const int col = t & (cc - 1), ky = t >> cclog;
+        const int kx = SPLIT * (c0 + col) + h;
+        const int k1 = kx <= g.M1 / 2 ? kx : g.M1 - kx;
+        const int k2 = ky <= g.M2 / 2 ? ky : g.M2 - ky;
+        const long f = (long)k2 * g.H1 + k1;
+        const JmCoef<T> c =
+            jm_coef<T>(G3 + f * 6, K3 + f * 3, kx <= g.M1 / 2 ? (T)1 : (T)-1, ky <= g.M2 / 2 ? (T)1 : (T)-1, s3);
+        const int o = ((pad8(ky)) << cclog) + col;
+        const int cs = M2p << cclog;
+        cx<T> ue[3], um[3], oe[3], om[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          ue[a] = C[a * cs + o];
+          um[a] = C[(3 + a) * cs + o];
+        }
+        jm_apply<T>(c, kappa, ue, um, oe, om);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          C[a * cs + o] = oe[a];
+          C[(3 + a) * cs + o] = om[a];
+        }
+      }
+      __syncthreads();
+      pad_cols<T, true>(A, C, m, g.L2, W2, tid);
+    }
+    pad_rows<T, true>(A, 3 * g.n2, pitch, Lx, Mx, Wx, opaque_tid());
+    pad_rows<T, true>(A + 3 * g.n2 * pitch, 3 * g.n2, pitch, Lx, Mx, Wx, opaque_tid());
+    if (SPLIT == 1) {
+      for (int t = threadIdx.x; t < items; t += blockDim.x) {
+        const int x = t & ((1 << wlog) - 1), r = t >> wlog;
+        if (x < g.n1) {
+          const cx<T> v = A[r * pitch + pad8(x)];
+          if (r < 3 * g.n2) Pe[r * g.n1 + x] = v;
+          else Pm[(r - 3 * g.n2) * g.n1 + x] = v;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < (SPLIT == 2 ? kJmAcc : 1); ++q) {
+        const int t = threadIdx.x + q * blockDim.x;
+        const int x = t & ((1 << wlog) - 1), r = t >> wlog;
+        if (t < items && x < g.n1) {
+          const cx<T> v = A[r * pitch + pad8(x)];
+          if (h == 0) {
+            acc[q] = v;
+          } else {
+            const cx<T> y = cadd(acc[q], cmulc(v, W1[x]));
+            if (r < 3 * g.n2) Pe[r * g.n1 + x] = y;
+            else Pm[(r - 3 * g.n2) * g.n1 + x] = y;
+          }
+        }
+      }
     }
   }
 }
@@ -260,26 +304,38 @@ __global__ __launch_bounds__(1024) void k_jm_xy(cx<T>* __restrict__ Ue, cx<T>* _
 size_t jm_spectrum_values(const Geom& g) { return (size_t)6 * g.M1 * g.M2 * g.M3; }
 
 template <typename T>
-size_t jm_fused_lds(const Geom& g, int cc) {
-  const size_t pitch = g.M1 + (g.M1 >> 3), M2p = g.M2 + (g.M2 >> 3);
-  return (6 * g.n2 * pitch + 6 * M2p * cc + g.M1 + g.M2) * sizeof(cx<T>);
+size_t jm_fused_lds(const Geom& g, int cc, int split) {
+  const size_t Mx = g.M1 / split;
+  const size_t pitch = Mx + (Mx >> 3), M2p = g.M2 + (g.M2 >> 3);
+  return (6 * g.n2 * pitch + 6 * M2p * cc + g.M1 + g.M2 + (split == 2 ? Mx : 0)) * sizeof(cx<T>);
 }
 
 template <typename T>
-bool jm_fused_shape(const Geom& g, int* cc_out, int* threads_out) {
-  int cc = g.M1 < 16 ? g.M1 : 16;
-  while (cc > 1 && jm_fused_lds<T>(g, cc) > kJmFusedLds) cc >>= 1;
-  if (jm_fused_lds<T>(g, cc) > kJmFusedLds) return false;
-  // every stage holds at most kJmFusedMaxV values per thread (rows: one half at a time)
-  const size_t rows = (size_t)3 * g.n2 * g.M1, cols = (size_t)6 * g.M2 * cc;
-  const size_t need = rows > cols ? rows : cols;
-  int threads = (int)((need + kPadMaxV - 1) / kPadMaxV);
-  threads = ((threads + 63) / 64) * 64;
-  if (threads < 256) threads = 256;
-  if (threads > 1024) return false;
-  if (cc_out) *cc_out = cc;
-  if (threads_out) *threads_out = threads;
-  return true;
+bool jm_fused_shape(const Geom& g, int* cc_out, int* threads_out, int* split_out) {
+  for (int split = 1; split <= 2; ++split) {
+    if (split == 2 && g.M1 < 2) break;
+    const int Mx = g.M1 / split;
+    int cc = Mx < 16 ? Mx : 16;
+    while (cc > 1 && jm_fused_lds<T>(g, cc, split) > kJmFusedLds) cc >>= 1;
+    if (jm_fused_lds<T>(g, cc, split) > kJmFusedLds) continue;
+    // every stage holds at most kPadMaxV values per thread (rows: one half of the
+    // components at a time); the halves variant keeps kJmAcc outputs per thread
+    const size_t rows = (size_t)3 * g.n2 * Mx, cols = (size_t)6 * g.M2 * cc;
+    size_t need = ((rows > cols ? rows : cols) + kPadMaxV - 1) / kPadMaxV;
+    if (split == 2) {
+      const size_t items = (size_t)6 * g.n2 * (g.M1 / 2);
+      const size_t acc = (items + kJmAcc - 1) / kJmAcc;
+      if (acc > need) need = acc;
+    }
+    int threads = (int)((need + 63) / 64) * 64;
+    if (threads < 256) threads = 256;
+    if (threads > (split == 1 ? kJmXyThreads<1> : kJmXyThreads<2>)) continue;
+    if (cc_out) *cc_out = cc;
+    if (threads_out) *threads_out = threads;
+    if (split_out) *split_out = split;
+    return true;
+  }
+  return false;
 }
 
 template <typename T>
@@ -288,7 +344,10 @@ hipError_t allow_lds_jm() {
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)k_jm_xyfwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)))
     return e;
-  if ((e = hipFuncSetAttribute((const void*)k_jm_xy<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  if ((e = hipFuncSetAttribute((const void*)k_jm_xy<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kJmFusedLds)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_jm_xy<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kJmFusedLds)))
     return e;
   return hipFuncSetAttribute((const void*)k_jm_xyinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -300,8 +359,8 @@ hipError_t launch_jm_matvec(const Geom& g, const Tune& t, const void* x, void* y
                             const void* chi_m, double kappa, bool fused, const void* const tw[3], hipStream_t s) {
   using C = cx<T>;
   if (g.M1 * g.M2 > 64 * 64) return hipErrorInvalidValue;
-  int cc = 0, threads = 0;
-  if (fused && !jm_fused_shape<T>(g, &cc, &threads)) return hipErrorInvalidValue;
+  int cc = 0, threads = 0, split = 1;
+  if (fused && !jm_fused_shape<T>(g, &cc, &threads, &split)) return hipErrorInvalidValue;
   if (!fused && !S) return hipErrorInvalidValue;
   const long n3 = 3 * g.N;
   const C* xe = static_cast<const C*>(x);
@@ -314,9 +373,13 @@ hipError_t launch_jm_matvec(const Geom& g, const Tune& t, const void* x, void* y
   if ((e = launch_pass<T>(0, g, t, xe, nullptr, nullptr, 0, Ue, goct, chi_e, tw, s))) return e;
   if ((e = launch_pass<T>(0, g, t, xm, nullptr, nullptr, 0, Um, goct, chi_m, tw, s))) return e;
   if (fused) {
-    const size_t lds = jm_fused_lds<T>(g, cc);
-    hipLaunchKernelGGL(k_jm_xy<T>, dim3(g.M3), dim3(threads), lds, s, (C*)Ue, (C*)Um, (const C*)goct,
-                       (const C*)koct, g, cc, (T)kappa, (const C*)tw[0], (const C*)tw[1]);
+    const size_t lds = jm_fused_lds<T>(g, cc, split);
+    if (split == 1)
+      hipLaunchKernelGGL((k_jm_xy<T, 1>), dim3(g.M3), dim3(threads), lds, s, (C*)Ue, (C*)Um, (const C*)goct,
+                         (const C*)koct, g, cc, (T)kappa, (const C*)tw[0], (const C*)tw[1]);
+    else
+      hipLaunchKernelGGL((k_jm_xy<T, 2>), dim3(g.M3), dim3(threads), lds, s, (C*)Ue, (C*)Um, (const C*)goct,
+                         (const C*)koct, g, cc, (T)kappa, (const C*)tw[0], (const C*)tw[1]);
     if ((e = hipGetLastError())) return e;
     if ((e = launch_pass<T>(2, g, t, xe, ye, be, mode, Ue, goct, chi_e, tw, s))) return e;
     return launch_pass<T>(2, g, t, xm, ym, bm, mode, Um, goct, chi_m, tw, s);
@@ -343,8 +406,8 @@ hipError_t launch_jm_matvec(const Geom& g, const Tune& t, const void* x, void* y
 
 template hipError_t allow_lds_jm<double>();
 template hipError_t allow_lds_jm<float>();
-template bool jm_fused_shape<double>(const Geom&, int*, int*);
-template bool jm_fused_shape<float>(const Geom&, int*, int*);
+template bool jm_fused_shape<double>(const Geom&, int*, int*, int*);
+template bool jm_fused_shape<float>(const Geom&, int*, int*, int*);
 template hipError_t launch_jm_matvec<double>(const Geom&, const Tune&, const void*, void*, const void*, int, void*,
                                              void*, void*, const void*, const void*, const void*, const void*, double,
                                              bool, const void* const[3], hipStream_t);

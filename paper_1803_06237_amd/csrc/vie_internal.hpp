@@ -72,7 +72,7 @@ size_t xy_lds_bytes(const Geom& g, int cc);
 // values.  M1 M2 <= 4096.
 size_t jm_spectrum_values(const Geom& g);
 template <typename T>
-bool jm_fused_shape(const Geom& g, int* cc, int* threads);
+bool jm_fused_shape(const Geom& g, int* cc, int* threads, int* split = nullptr);
 template <typename T>
 hipError_t allow_lds_jm();
 template <typename T>

@@ -34,9 +34,11 @@ H, K0, EPSB = 0.05, inputs.K0, inputs.EPS_B
 
 # several tiles and ragged tails: the 64 x 64 cross-section (17, 32, 6), the
 # paper's strip cross-section 30 x 12 (64 x 32), a 64 x 1 plane (32, 1, 3), z
-# circulants from 1 to 512, non-power-of-two n on every axis, single voxels
+# circulants from 1 to 512, non-power-of-two n on every axis, single voxels;
+# (17, 32, 6) and (29, 23, 5) run the FP64 fused pass in x-frequency halves
+# (column chunks of 4 and 8), (20, 18, 3) on full rows with chunks of 4
 GRIDS = [(8, 8, 32), (5, 7, 37), (17, 32, 6), (30, 12, 20), (32, 1, 3), (20, 18, 3), (2, 3, 4), (1, 1, 9),
-         (1, 1, 1), (3, 5, 200)]
+         (1, 1, 1), (3, 5, 200), (29, 23, 5)]
 
 
 def _materials(rng, n):
