@@ -120,6 +120,80 @@ def test_other_cross_section_route_matches_oracle(case, precision):
         plan.set_jm_route(precision, default)
 
 
+JM_BENCH_CASES = {
+    "guide32x32x512": lambda: _magnetic(inputs.strip_long(d=2)),
+    "strip30x12x1377": lambda: inputs.strip_paper(9.45, 2, 1e-10, magnetic=True),
+}
+
+
+def _magnetic(wg):
+    wg.magnetic = True
+    return wg
+
+
+@pytest.mark.parametrize("name", sorted(JM_BENCH_CASES))
+def test_full_size_jm_sampled_outputs(name):
+    """The JM products the bench times (32 x 32 x 512 guide: FP64 fused in x-frequency
+    halves; the paper's 30 x 12 x 1377 strip), both precisions: x has a few random
+    non-zeros among the six components and sampled outputs (half in the core) are
+    rebuilt by the oracle from the Galerkin entries of N and K at the needed offsets,
+    y_e = x_e - M_eps (N x_e + i kappa K x_m), y_m = x_m - M_mu (-i kappa K x_e + N x_m)."""
+    vie = _dev()
+    wg = JM_BENCH_CASES[name]()
+    n = wg.n
+    rng = np.random.default_rng(11)
+    kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+    eps, mu = wg.eps(), wg.mu()
+    chi_e, chi_m = mv.contrast(eps, wg.eps_b), jm.magnetic_contrast(mu)
+    assert np.abs(chi_m).max() > 0
+    plan = vie.Plan(n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    plan.set_contrast(_t(eps))
+    plan.jm_enable()
+    plan.set_permeability(_t(mu))
+    assert plan.jm_route(0) and plan.jm_route(1)
+    nnz, nout = 24, 48
+    x = np.zeros((6,) + n, complex)
+    src = np.stack([rng.integers(0, n[d], nnz) for d in range(3)], 1)
+    comp = rng.integers(0, 6, nnz)
+    vals = _cvec(rng, nnz)
+    for sv, c, v in zip(src, comp, vals):
+        x[(c,) + tuple(sv)] += v
+    core = np.argwhere(wg.core_mask())
+    outs = np.concatenate([core[rng.integers(0, len(core), nout // 2)],
+                           np.stack([rng.integers(0, n[d], nout - nout // 2) for d in range(3)], 1)])
+    offs = (outs[:, None, :] - src[None, :, :]).reshape(-1, 3)
+    Nab = green.galerkin_N(offs, kap).reshape(6, nout, nnz)
+    Kab = jm.galerkin_K(offs, kap).reshape(3, nout, nnz)
+    Nf, Kf = {}, {}
+    for ci, (a, b) in enumerate(green.COMPONENTS):
+        Nf[(a, b)] = Nf[(b, a)] = Nab[ci]
+    for a in range(3):
+        Kf[(a, a)] = np.zeros((nout, nnz), complex)
+    for ci, (a, b) in enumerate(jm.KCOMPONENTS):
+        Kf[(a, b)], Kf[(b, a)] = Kab[ci], -Kab[ci]
+    col = [np.where(comp == c, vals, 0)[None, :] for c in range(6)]
+    i = tuple(outs.T)
+    want = np.empty((nout, 6), complex)
+    for a in range(3):
+        Ne = sum((Nf[(a, b)] * col[b]).sum(axis=1) for b in range(3))
+        Nm = sum((Nf[(a, b)] * col[3 + b]).sum(axis=1) for b in range(3))
+        Ke = sum((Kf[(a, b)] * col[b]).sum(axis=1) for b in range(3))
+        Km = sum((Kf[(a, b)] * col[3 + b]).sum(axis=1) for b in range(3))
+        want[:, a] = x[(a,) + i] - chi_e[i] * (Ne + 1j * kap * Km)
+        want[:, 3 + a] = x[(3 + a,) + i] - chi_m[i] * (-1j * kap * Ke + Nm)
+    scale = np.abs(want).max()
+    y64 = plan.jm_matvec(_t(x)).cpu().numpy()
+    y32 = plan.jm_matvec_c64(_t(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    errs = []
+    for y in (y64, y32):
+        got = np.stack([y[(c,) + i] for c in range(6)], 1)
+        errs.append(np.abs(got - want).max() / scale)
+    plan.close()
+    print(f"{name} jm sampled: fp64 {errs[0]:.3e} fp32 {errs[1]:.3e}")
+    assert errs[0] < 1e-12
+    assert errs[1] < 5e-6
+
+
 def test_jm_residual_is_b_minus_matvec(case):
     n, rng = case["n"], case["rng"]
     x, b = _cvec(rng, (6,) + n), _cvec(rng, (6,) + n)
