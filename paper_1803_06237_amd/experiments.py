@@ -423,16 +423,121 @@ def strip_reflection_study(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: Seq
     return out
 
 
+def bragg_slice_field(plan: "vie.Plan", wg: inputs.Waveguide, w, e_inc: np.ndarray) -> np.ndarray:
+    """Total E on the transmission slice of a Bragg guide from its solved currents w
+    (device, 3N values), including the background voxels at the slice, where w is zero.
+
+    The discrete system reads w = M (h^{3/2} e_inc + N w) (Section III-A), so
+    f = h^{3/2} e_inc + N w is the field's Galerkin coefficient scaled by eps_r on
+    every voxel and E = f / (h^{3/2} eps_r).  N w comes from one product with a
+    uniform contrast of 1/2 (eps = 2 eps_b everywhere): y = w - N w / 2.  This
+    replaces the plan's contrast.  Returns shape (3, n1, n2)."""
+    import torch
+    z = inputs.bragg_slice(wg)
+    plan.set_contrast(torch.full(wg.n, 2.0 * wg.eps_b, dtype=torch.complex128, device="cuda"))
+    y = plan.matvec(w)
+    nw = (2.0 * (w - y))[..., z].cpu().numpy()
+    eps_r = wg.eps()[..., z] / wg.eps_b
+    return (wg.h ** 1.5 * e_inc[..., z] + nw) / (wg.h ** 1.5 * eps_r)[None]
+
+
+def band_gap(wavelengths_nm: Sequence[float], T: Sequence[float]) -> dict:
+    """Band gap read off a transmission curve: the wavelength of least transmission and
+    the contiguous range around it where the transmission stays below half of the
+    curve's maximum."""
+    lam = np.asarray(wavelengths_nm, dtype=float)
+    t = np.asarray(T, dtype=float) / max(T)
+    i = int(np.argmin(t))
+    out = {"lambda_min_nm": float(lam[i]), "T_min_over_max": float(t[i])}
+    if t[i] < 0.5:
+        lo, hi = i, i
+        while lo > 0 and t[lo - 1] < 0.5:
+            lo -= 1
+        while hi < len(t) - 1 and t[hi + 1] < 0.5:
+            hi += 1
+        out.update(gap_lo_nm=float(lam[lo]), gap_hi_nm=float(lam[hi]), gap_width_nm=float(lam[hi] - lam[lo]),
+                   gap_centre_nm=float(0.5 * (lam[lo] + lam[hi])), gap_open_at_range_end=bool(lo == 0 or hi == len(t) - 1))
+    return out
+
+
+def bragg_transmission(wavelengths_nm: Sequence[float], periods: int = 100, lead_periods: int = 10, d: int = 2,
+                       r_rt: float = 1e-10, precision: int = 1, tol: float = 1e-8, restart: int = 50,
+                       inner_restart: int = 20, inner_tol: float = 1e-3, batch: int = 8, progress=None) -> dict:
+    """Transmission through the Bragg grating of Section II-B against the free-space
+    wavelength (Section V): for each wavelength the guide with quadratic absorbers of
+    2.2 um on both ends is solved for the strip's complex-source dipole, and
+    T = sum over the slice's voxels of |E|^2 h^2 (the integral of |E|^2 over a
+    voxel-wide cross-section between the grating and the far absorber).  Each
+    wavelength has its own operator (k0 h changes), so every wavelength gets a plan;
+    `batch` of them are solved together in one vie_solve_batch call."""
+    import torch
+    out = {"wavelengths_nm": [float(v) for v in wavelengths_nm], "periods": periods, "lead_periods": lead_periods,
+           "d": d, "r_rt": r_rt, "T": [], "iters": [], "inner_iters": [], "rel_res": [], "status": [],
+           "plan_seconds": 0.0, "solve_seconds": 0.0}
+    for c0 in range(0, len(wavelengths_nm), batch):
+        lams = list(wavelengths_nm[c0:c0 + batch])
+        t0 = time.perf_counter()
+        wgs = [inputs.bragg_grating(lam * 1e-3, periods=periods, lead_periods=lead_periods, d=d, r_rt=r_rt)
+               for lam in lams]
+        plans = [vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True) for wg in wgs]
+        try:
+            eincs, bs = [], []
+            for wg, p in zip(wgs, plans):
+                p.set_contrast(torch.from_numpy(wg.eps()).cuda())
+                e = inputs.bragg_source(wg)
+                eincs.append(e)
+                bs.append(p.rhs(torch.from_numpy(e).cuda()))
+            torch.cuda.synchronize()
+            out["plan_seconds"] += time.perf_counter() - t0
+            t0 = time.perf_counter()
+            xs, infos, code = vie.solve_batch(plans, bs, tol=tol, restart=restart, precision=precision,
+                                              inner_restart=inner_restart, inner_tol=inner_tol)
+            torch.cuda.synchronize()
+            out["solve_seconds"] += time.perf_counter() - t0
+            for lam, wg, p, x, e, info in zip(lams, wgs, plans, xs, eincs, infos):
+                E = bragg_slice_field(p, wg, x, e)
+                out["T"].append(float(np.sum(np.abs(E) ** 2) * wg.h ** 2))
+                out["iters"].append(info["iters"])
+                out["inner_iters"].append(info["inner_iters"])
+                out["rel_res"].append(info["rel_res_true"])
+                out["status"].append(info["status"])
+                if progress is not None:
+                    progress(lam, out["T"][-1], info)
+            del xs, bs
+        finally:
+            for p in plans:
+                p.close()
+    out["plan_seconds"] = round(out["plan_seconds"], 3)
+    out["solve_seconds"] = round(out["solve_seconds"], 3)
+    out["T_norm"] = [t / max(out["T"]) for t in out["T"]]
+    out.update(band_gap(out["wavelengths_nm"], out["T"]))
+    return out
+
+
 if __name__ == "__main__":
     import argparse
     import json
     ap = argparse.ArgumentParser(description="experiments of the paper run on the GPU path")
-    ap.add_argument("which", choices=["strip"], help="strip: the reflection study of Section V-A")
+    ap.add_argument("which", choices=["strip", "bragg"],
+                    help="strip: the reflection study of Section V-A; bragg: the grating's transmission")
     ap.add_argument("--out", default=None, help="write the JSON result here")
     ap.add_argument("--quick", action="store_true", help="every other absorber length")
     ap.add_argument("--em", action="store_true", help="electric and magnetic currents, matched absorber")
     ap.add_argument("--r-rt", type=float, nargs="*", default=[1e-25, 1e-10], help="round-trip reflections")
+    ap.add_argument("--step", type=float, default=1.0, help="bragg: wavelength step in nm (1520..1570)")
+    ap.add_argument("--periods", type=int, default=100, help="bragg: grating periods")
     a = ap.parse_args()
+    if a.which == "bragg":
+        lams = np.arange(1520.0, 1570.0 + 1e-9, a.step)
+        res = bragg_transmission(lams, periods=a.periods,
+                                 progress=lambda lam, T, i: print(f"{lam:.1f} nm T {T:.4e} iters {i['iters']}/"
+                                                                  f"{i['inner_iters']} res {i['rel_res_true']:.1e}",
+                                                                  flush=True))
+        print({k: v for k, v in res.items() if not isinstance(v, list)}, flush=True)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(json.dumps(res, indent=1))
+        raise SystemExit(0)
     lengths = STRIP_LENGTHS[::2] if a.quick else STRIP_LENGTHS
     if lengths[-1] != STRIP_LENGTHS[-1]:
         lengths = tuple(lengths) + (STRIP_LENGTHS[-1],)

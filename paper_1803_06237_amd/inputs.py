@@ -368,3 +368,60 @@ def strip_paper_source(wg: Waveguide) -> np.ndarray:
     r0 = (0.5 * wg.n[0] * wg.h, 0.5 * wg.n[1] * wg.h, wg.core_z[0] * wg.h + lam_si / 4.0)
     kb = wg.k0 * math.sqrt(wg.eps_b)
     return complex_source_dipole_field(wg.n, wg.h, r0, (1, 0, 0), kb, (0.0, 0.0, lam_si))
+
+
+# ---- Bragg grating (Section II-B, transmission study of Section V) ----------------
+BRAGG_H = 0.02                       # 20 nm voxels: the 500 x 220 nm section exactly
+BRAGG_PERIOD = 16                    # 320 nm period in voxels, half wide, half narrow
+BRAGG_TAIL = 20                      # uniform voxels between the grating and the far absorber
+
+
+def bragg_grating(lambda0_um: float = LAMBDA0, periods: int = 100, lead_periods: int = 10, d: int = 2,
+                  r_rt: float = 1e-10, absorber_um: float = 2.2) -> Waveguide:
+    """The Bragg grating of Section II-B on 20 nm voxels: a 500 x 220 nm silicon strip
+    whose width steps between W + dW and W - dW (dW = 40 nm, one voxel per sidewall)
+    every half period (period 320 nm, wide half first) over `periods` periods, after
+    a uniform lead-in of `lead_periods` periods and followed by BRAGG_TAIL uniform
+    voxels; quadratic (degree d) absorbers of absorber_um on both ends, strength
+    from r_rt at this wavelength (Section IV-C).  The grid is the wide section's
+    bounding box, 27 x 11 voxels across; the permittivities do not depend on the
+    wavelength (silicon's dispersion is not given)."""
+    h = BRAGG_H
+    n_abs = int(round(absorber_um / h))
+    n3 = 2 * n_abs + (lead_periods + periods) * BRAGG_PERIOD + BRAGG_TAIL
+    k0 = 2.0 * math.pi / lambda0_um
+    lo = np.zeros(n3, dtype=np.int64)
+    hi = np.zeros(n3, dtype=np.int64)
+    g0 = n_abs + lead_periods * BRAGG_PERIOD
+    half = BRAGG_PERIOD // 2
+    for p in range(periods):
+        a = g0 + p * BRAGG_PERIOD
+        lo[a:a + half], hi[a:a + half] = -1, 1                        # wide: 27 voxels
+        lo[a + half:a + 2 * half], hi[a + half:a + 2 * half] = 1, -1  # narrow: 23 voxels
+    sig = sigma_max_for(r_rt, d, n_abs * h, k0=k0)
+    return Waveguide(n=(27, 11, n3), h=h, core_x=(1, 26), core_y=(0, 11), core_z=(0, n3), n_abs=n_abs, d=d,
+                     sigma_max=sig, k0=k0, rough_lo=lo, rough_hi=hi, ends="both")
+
+
+def bragg_grating_range(wg: Waveguide) -> Tuple[int, int]:
+    """z index range [lo, hi) of the corrugated part."""
+    nz = np.nonzero(wg.rough_lo)[0]
+    return int(nz[0]), int(nz[-1]) + 1
+
+
+def bragg_slice(wg: Waveguide) -> int:
+    """z index of the transmission slice: the middle of the uniform tail between the
+    grating's end and the far absorber."""
+    return wg.lossless_range()[1] - BRAGG_TAIL // 2
+
+
+def bragg_source(wg: Waveguide) -> np.ndarray:
+    """The strip's complex-source dipole (strip_paper_source) placed a quarter silicon
+    wavelength after the near absorber's inner interface, at the grid's wavelength."""
+    lam0 = 2.0 * math.pi / wg.k0
+    lam_si = lam0 / math.sqrt(wg.eps_core)
+    z0 = wg.lossless_range()[0] * wg.h + lam_si / 4.0
+    r0 = (0.5 * wg.n[0] * wg.h, 0.5 * wg.n[1] * wg.h, z0)
+    kb = wg.k0 * math.sqrt(wg.eps_b)
+    return complex_source_dipole_field(wg.n, wg.h, r0, (1, 0, 0), kb, (0.0, 0.0, lam_si))
+

@@ -1,0 +1,91 @@
+"""The Bragg-grating transmission read-out on the GPU path (Section II-B, Section V):
+the slice field from solved currents against the oracle, and a solve of a short
+grating judged by the oracle's own residual."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import green, matvec as mv, observables
+from paper_1803_06237_amd import experiments, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1803_06237_amd import vie
+    vie.lib()
+    return vie
+
+
+def _small_grating(lam=1.55):
+    """9 x 5 x 64 voxels of 20 nm: a 7-voxel strip whose sidewalls step by one voxel
+    every 8 voxels over two periods, absorbers of 8 voxels on both ends."""
+    n3 = 64
+    lo = np.zeros(n3, dtype=np.int64)
+    hi = np.zeros(n3, dtype=np.int64)
+    for p in range(2):
+        a = 12 + 16 * p
+        lo[a:a + 8], hi[a:a + 8] = -1, 1
+        lo[a + 8:a + 16], hi[a + 8:a + 16] = 1, -1
+    k0 = 2 * math.pi / lam
+    return inputs.Waveguide(n=(9, 5, n3), h=0.02, core_x=(1, 8), core_y=(0, 5), core_z=(0, n3), n_abs=8, d=2,
+                            sigma_max=inputs.sigma_max_for(1e-10, 2, 0.16, k0=k0), k0=k0, rough_lo=lo,
+                            rough_hi=hi, ends="both")
+
+
+def test_slice_field_matches_oracle():
+    """E on the transmission slice (background voxels included) from arbitrary currents:
+    the GPU read-out (one product with a uniform contrast of 1/2) against the oracle's
+    (h^{3/2} e_inc + N w) / (h^{3/2} eps_r) with N w by its own FFT product."""
+    vie = _dev()
+    wg = _small_grating()
+    z = inputs.bragg_slice(wg)
+    assert z == 46 and (~wg.core_mask()[:, :, z]).any()
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal((3,) + wg.n) + 1j * rng.standard_normal((3,) + wg.n)
+    e = inputs.bragg_source(wg)
+    plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    got = experiments.bragg_slice_field(plan, wg, torch.from_numpy(w).cuda(), e)
+    plan.close()
+    spec = mv.spectrum(green.green_table(wg.n, mv.kappa_of(wg.h, wg.k0, wg.eps_b)))
+    want = observables.total_field(w, mv.apply_N_fft(spec, w), e, wg.eps(), wg.eps_b, wg.h)[..., z]
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"slice field rel err {err:.3e}")
+    assert err < 1e-12
+    T = observables.slice_transmission(got, wg.h)
+    assert abs(T - observables.slice_transmission(want, wg.h)) < 1e-10 * T
+
+
+@pytest.mark.parametrize("lam", [1.52, 1.55])
+def test_short_grating_solve_and_transmission(lam):
+    """Ten periods behind a two-period lead-in (27 x 11 x 432 voxels), at two
+    wavelengths: the batched mixed solve reaches 1e-8, the FP64 residual recomputed
+    with the plan's FP64 product (oracle-parity tested on its own) agrees, and a
+    single FP64 GMRES solve gives the same transmitted power."""
+    vie = _dev()
+    res = experiments.bragg_transmission([lam * 1e3], periods=10, lead_periods=2, batch=1)
+    assert res["status"] == [0] and res["rel_res"][0] <= 1e-8
+    T = res["T"][0]
+    assert np.isfinite(T) and T > 0
+    wg = inputs.bragg_grating(lam, periods=10, lead_periods=2)
+    assert wg.n == (27, 11, 432)
+    plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    try:
+        plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+        e = inputs.bragg_source(wg)
+        b = plan.rhs(torch.from_numpy(e).cuda())
+        x, info = plan.solve(b, tol=1e-9, precision=0)
+        assert info["status"] == 0
+        r = plan.residual(x, b)
+        rel = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
+        assert rel <= 1.5e-9
+        T64 = observables.slice_transmission(experiments.bragg_slice_field(plan, wg, x, e), wg.h)
+    finally:
+        plan.close()
+    print(f"lambda {lam} T {T:.6e} fp64 {T64:.6e} iters {res['iters'][0]}/{res['inner_iters'][0]} fp64 {info['iters']}")
+    assert abs(T - T64) <= 1e-6 * T64
