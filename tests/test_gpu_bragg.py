@@ -89,3 +89,15 @@ def test_short_grating_solve_and_transmission(lam):
         plan.close()
     print(f"lambda {lam} T {T:.6e} fp64 {T64:.6e} iters {res['iters'][0]}/{res['inner_iters'][0]} fp64 {info['iters']}")
     assert abs(T - T64) <= 1e-6 * T64
+
+
+def test_full_grating_reflects_in_its_band_gap():
+    """The 100-period grating at the edge of the sweep and at the centre of its band gap
+    (1547.5 nm in the full 1520-1570 nm sweep with these permittivities): the
+    transmitted power there is below a third of that at 1520 nm."""
+    _dev()
+    res = experiments.bragg_transmission([1520.0, 1547.5], batch=2)
+    assert res["status"] == [0, 0] and max(res["rel_res"]) <= 1e-8
+    ratio = res["T"][1] / res["T"][0]
+    print(f"T(1547.5) / T(1520) = {ratio:.3f}, outer steps {res['iters']}")
+    assert ratio < 1 / 3
