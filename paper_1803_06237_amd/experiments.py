@@ -514,12 +514,71 @@ def bragg_transmission(wavelengths_nm: Sequence[float], periods: int = 100, lead
     return out
 
 
+def bragg_axis_field(wg: inputs.Waveguide, w: np.ndarray) -> np.ndarray:
+    """E on the core's centre line (the voxel column through the grid's centre, inside
+    the core over the whole length) over the lossless part: E = J / (eps_r - 1) with
+    J = w h^{-3/2}.  Shape (3, length)."""
+    i1, i2 = wg.n[0] // 2, wg.n[1] // 2
+    lo, hi = wg.lossless_range()
+    eps_r = wg.eps_core / wg.eps_b
+    return w[:, i1, i2, lo:hi] / (wg.h ** 1.5 * (eps_r - 1.0))
+
+
+def bragg_slow_light_study(wavelengths_nm: Sequence[float] = (1520.0, 1538.0),
+                           absorber_periods: Sequence[int] = (3, 5, 10, 20, 40), ref_periods: int = 90,
+                           d: int = 2, r_rt: float = 1e-10, precision: int = 1, tol: float = 1e-8,
+                           restart: int = 50, inner_restart: int = 20, inner_tol: float = 1e-3,
+                           progress=None) -> dict:
+    """Absorbers inside the periodic region (Section V, slow light): R(L) on the centre
+    line of the lossless part against a ref_periods absorber, for the corrugated
+    guide and for the uniform strip of the same lengths, at each wavelength.  All
+    lengths of one (wavelength, guide) are solved in one vie_solve_batch call
+    (uneven grids)."""
+    import torch
+    lengths = list(absorber_periods) + [ref_periods]
+    out = {"absorber_periods": list(absorber_periods), "ref_periods": ref_periods, "d": d, "r_rt": r_rt,
+           "period_um": inputs.BRAGG_PERIOD * inputs.BRAGG_H, "runs": {}}
+    for lam in wavelengths_nm:
+        for corrugated in (True, False):
+            t0 = time.perf_counter()
+            wgs = [inputs.bragg_slow_light(lam * 1e-3, P, d=d, r_rt=r_rt, corrugated=corrugated) for P in lengths]
+            plans = [vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True) for wg in wgs]
+            try:
+                bs = []
+                for wg, p in zip(wgs, plans):
+                    p.set_contrast(torch.from_numpy(wg.eps()).cuda())
+                    bs.append(p.rhs(torch.from_numpy(inputs.bragg_source(wg)).cuda()))
+                torch.cuda.synchronize()
+                setup_s = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                xs, infos, code = vie.solve_batch(plans, bs, tol=tol, restart=restart, precision=precision,
+                                                  inner_restart=inner_restart, inner_tol=inner_tol)
+                torch.cuda.synchronize()
+                solve_s = time.perf_counter() - t0
+                fields = {P: bragg_axis_field(wg, x.cpu().numpy()) for P, wg, x in zip(lengths, wgs, xs)}
+                del xs, bs
+            finally:
+                for p in plans:
+                    p.close()
+            Ls, R = _reflection(fields, lengths)
+            fit = np.polyfit(np.log(np.asarray(Ls, float)), np.log(np.asarray(R)), 1)[0] if len(Ls) >= 2 else None
+            run = {"lambda_nm": float(lam), "corrugated": corrugated, "status": code,
+                   "setup_seconds": round(setup_s, 3), "solve_seconds": round(solve_s, 3),
+                   "max_rel_res": max(i["rel_res_true"] for i in infos), "outer_iters": [i["iters"] for i in infos],
+                   "R": R, "loglog_slope": None if fit is None else float(fit), "predicted_slope": -2 * (d + 1)}
+            out["runs"][f"{lam:g}/{'grating' if corrugated else 'strip'}"] = run
+            if progress is not None:
+                progress(run)
+    return out
+
+
 if __name__ == "__main__":
     import argparse
     import json
     ap = argparse.ArgumentParser(description="experiments of the paper run on the GPU path")
-    ap.add_argument("which", choices=["strip", "bragg"],
-                    help="strip: the reflection study of Section V-A; bragg: the grating's transmission")
+    ap.add_argument("which", choices=["strip", "bragg", "slowlight"],
+                    help="strip: the reflection study of Section V-A; bragg: the grating's transmission; "
+                         "slowlight: absorbers inside the grating")
     ap.add_argument("--out", default=None, help="write the JSON result here")
     ap.add_argument("--quick", action="store_true", help="every other absorber length")
     ap.add_argument("--em", action="store_true", help="electric and magnetic currents, matched absorber")
@@ -527,6 +586,12 @@ if __name__ == "__main__":
     ap.add_argument("--step", type=float, default=1.0, help="bragg: wavelength step in nm (1520..1570)")
     ap.add_argument("--periods", type=int, default=100, help="bragg: grating periods")
     a = ap.parse_args()
+    if a.which == "slowlight":
+        res = bragg_slow_light_study(progress=lambda r: print(r, flush=True))
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(json.dumps(res, indent=1))
+        raise SystemExit(0)
     if a.which == "bragg":
         lams = np.arange(1520.0, 1570.0 + 1e-9, a.step)
         res = bragg_transmission(lams, periods=a.periods,

@@ -72,6 +72,10 @@ class Waveguide:
     # magnetic conductivity alongside the electric one, impedance matched
     # (Section IV-B: mu'' = eps''/eps' in the absorber); False keeps mu_r = 1
     magnetic: bool = False
+    # length (voxels) and strength of the low-z absorber when they differ from the
+    # high-z one (None: n_abs and sigma_max); used with ends == "both"
+    n_abs_left: Optional[int] = None
+    sigma_left: Optional[float] = None
 
     def __post_init__(self):
         if self.ends not in ("both", "right"):
@@ -81,34 +85,44 @@ class Waveguide:
     def N(self) -> int:
         return self.n[0] * self.n[1] * self.n[2]
 
+    def _left(self) -> int:
+        if self.ends != "both":
+            return 0
+        return self.n_abs if self.n_abs_left is None else self.n_abs_left
+
     def absorber_u(self) -> np.ndarray:
         """u in (0,1) per z index (0 outside absorbers); u grows toward the domain end."""
         n3 = self.n[2]
         u = np.zeros(n3)
         z0, z1 = self.core_z
-        L = self.n_abs
-        if L > 0:
-            if self.ends == "both":
-                for k in range(z0, z0 + L):      # left absorber: inner interface at z0+L
-                    u[k] = (z0 + L - k - 0.5) / L
-            for k in range(z1 - L, z1):          # right absorber: inner interface at z1-L
-                u[k] = (k - (z1 - L) + 0.5) / L
+        Ll, L = self._left(), self.n_abs
+        for k in range(z0, z0 + Ll):             # left absorber: inner interface at z0+Ll
+            u[k] = (z0 + Ll - k - 0.5) / Ll
+        for k in range(z1 - L, z1):              # right absorber: inner interface at z1-L
+            u[k] = (k - (z1 - L) + 0.5) / L
         return u
 
     def in_absorber(self) -> np.ndarray:
         n3 = self.n[2]
         m = np.zeros(n3, dtype=bool)
         z0, z1 = self.core_z
+        m[z0:z0 + self._left()] = True
         if self.n_abs > 0:
-            if self.ends == "both":
-                m[z0:z0 + self.n_abs] = True
             m[z1 - self.n_abs:z1] = True
         return m
+
+    def absorber_sigma(self) -> np.ndarray:
+        """sigma_max per z index (that of the absorber the index lies in, 0 elsewhere)."""
+        sig = np.where(self.in_absorber(), self.sigma_max, 0.0)
+        if self.sigma_left is not None:
+            z0 = self.core_z[0]
+            sig[z0:z0 + self._left()] = self.sigma_left
+        return sig
 
     def lossless_range(self) -> Tuple[int, int]:
         """z index range [lo, hi) of the core outside the absorbers."""
         z0, z1 = self.core_z
-        return (z0 + (self.n_abs if self.ends == "both" else 0), z1 - self.n_abs)
+        return (z0 + self._left(), z1 - self.n_abs)
 
     def core_mask(self) -> np.ndarray:
         n1, n2, n3 = self.n
@@ -133,7 +147,7 @@ class Waveguide:
         absz = self.in_absorber()
         prof = np.where(absz, u ** self.d if self.d > 0 else 1.0, 0.0)
         prof = np.where(absz, prof, 0.0)
-        core_val = self.eps_core + 1j * self.sigma_max * prof   # per z
+        core_val = self.eps_core + 1j * self.absorber_sigma() * prof   # per z
         eps[mask] = np.broadcast_to(core_val, self.n)[mask]
         return eps
 
@@ -424,4 +438,31 @@ def bragg_source(wg: Waveguide) -> np.ndarray:
     r0 = (0.5 * wg.n[0] * wg.h, 0.5 * wg.n[1] * wg.h, z0)
     kb = wg.k0 * math.sqrt(wg.eps_b)
     return complex_source_dipole_field(wg.n, wg.h, r0, (1, 0, 0), kb, (0.0, 0.0, lam_si))
+
+
+def bragg_slow_light(lambda0_um: float, absorber_periods: int, lossless_periods: int = 20, lead_periods: int = 10,
+                     d: int = 2, r_rt: float = 1e-10, corrugated: bool = True,
+                     left_absorber_um: float = 2.2) -> Waveguide:
+    """The "infinite" Bragg grating of Section V: after a uniform lead-in of
+    `lead_periods` periods (behind a uniform absorber of left_absorber_um) the grating
+    of Section II-B runs for `lossless_periods` periods and then continues, with the
+    same corrugation, through an absorber of `absorber_periods` periods (degree d,
+    strength from r_rt for its own length).  corrugated=False gives the uniform
+    500 x 220 nm strip with the same lengths, the reference case of Section V-A."""
+    h = BRAGG_H
+    n_left = int(round(left_absorber_um / h))
+    n_abs = absorber_periods * BRAGG_PERIOD
+    g0 = n_left + lead_periods * BRAGG_PERIOD
+    n3 = g0 + lossless_periods * BRAGG_PERIOD + n_abs
+    k0 = 2.0 * math.pi / lambda0_um
+    lo = np.zeros(n3, dtype=np.int64)
+    hi = np.zeros(n3, dtype=np.int64)
+    if corrugated:
+        half = BRAGG_PERIOD // 2
+        for a in range(g0, n3, BRAGG_PERIOD):
+            lo[a:a + half], hi[a:a + half] = -1, 1
+            lo[a + half:a + 2 * half], hi[a + half:a + 2 * half] = 1, -1
+    return Waveguide(n=(27, 11, n3), h=h, core_x=(1, 26), core_y=(0, 11), core_z=(0, n3), n_abs=n_abs, d=d,
+                     sigma_max=sigma_max_for(r_rt, d, n_abs * h, k0=k0), k0=k0, rough_lo=lo, rough_hi=hi,
+                     ends="both", n_abs_left=n_left, sigma_left=sigma_max_for(r_rt, d, n_left * h, k0=k0))
 

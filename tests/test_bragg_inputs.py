@@ -115,3 +115,25 @@ def test_total_field_without_scatterer_is_the_incident_field():
     assert np.abs(E - e).max() < 1e-15
     assert abs(observables.slice_transmission(e[:, :, :, 1], 0.02)
                - 4e-4 * np.sum(np.abs(e[:, :, :, 1]) ** 2)) < 1e-15
+
+
+def test_slow_light_geometry():
+    """The grating continues, in phase, through an absorber of its own shape; the
+    lossless part and the left absorber do not depend on the absorber's length."""
+    ref = inputs.bragg_slow_light(1.52, 90)
+    assert ref.n == (27, 11, 2030) and ref.n[2] <= 2048
+    for P in (3, 5, 10, 20, 40, 90):
+        wg = inputs.bragg_slow_light(1.52, P)
+        assert wg.lossless_range() == (110, 590) and wg.n_abs == 16 * P
+        assert abs(wg.sigma_left - inputs.sigma_max_for(1e-10, 2, 2.2, k0=wg.k0)) < 1e-12
+        assert abs(wg.sigma_max - inputs.sigma_max_for(1e-10, 2, 0.32 * P, k0=wg.k0)) < 1e-12
+        widths = wg.core_mask()[:, 5, :].sum(axis=0)
+        assert (widths[:270] == 25).all()
+        per = widths[270:].reshape(-1, 16)
+        assert (per[:, :8] == 27).all() and (per[:, 8:] == 23).all()    # through the absorber too
+        eps = wg.eps()
+        assert np.array_equal(eps[:, :, :590], ref.eps()[:, :, :590])   # left absorber and lossless part
+        assert (eps[13, 5, 110:590].imag == 0).all() and (eps[13, 5, 590:].imag > 0).all()
+        flat = inputs.bragg_slow_light(1.52, P, corrugated=False)
+        assert (flat.core_mask()[:, 5, :].sum(axis=0) == 25).all()
+        assert np.array_equal(flat.eps()[13, 5], eps[13, 5])            # same absorber profile on the axis

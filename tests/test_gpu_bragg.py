@@ -101,3 +101,18 @@ def test_full_grating_reflects_in_its_band_gap():
     ratio = res["T"][1] / res["T"][0]
     print(f"T(1547.5) / T(1520) = {ratio:.3f}, outer steps {res['iters']}")
     assert ratio < 1 / 3
+
+
+def test_absorber_inside_the_grating_stagnates():
+    """Section V, slow light, at reduced length (absorbers of 3 and 10 periods against
+    30): inside the grating the reflection barely falls with the absorber's length,
+    while on the uniform strip it falls by orders of magnitude, as O(L^{-2(d+1)})."""
+    _dev()
+    res = experiments.bragg_slow_light_study(wavelengths_nm=(1520.0,), absorber_periods=(3, 10), ref_periods=30)
+    g, s = res["runs"]["1520/grating"], res["runs"]["1520/strip"]
+    for r in (g, s):
+        assert r["status"] == 0 and r["max_rel_res"] <= 1e-8
+    print(f"grating R {g['R']} strip R {s['R']}")
+    assert g["R"][1] / g["R"][0] > 0.5
+    assert s["R"][1] / s["R"][0] < 1e-2
+    assert g["R"][0] > 100 * s["R"][0]
