@@ -66,7 +66,8 @@ def test_short_grating_solve_and_transmission(lam):
     """Ten periods behind a two-period lead-in (27 x 11 x 432 voxels), at two
     wavelengths: the batched mixed solve reaches 1e-8, the FP64 residual recomputed
     with the plan's FP64 product (oracle-parity tested on its own) agrees, and a
-    single FP64 GMRES solve gives the same transmitted power."""
+    single FP64 GMRES solve and a block-circulant preconditioned one give the same
+    transmitted power."""
     vie = _dev()
     res = experiments.bragg_transmission([lam * 1e3], periods=10, lead_periods=2, batch=1)
     assert res["status"] == [0] and res["rel_res"][0] <= 1e-8
@@ -89,6 +90,10 @@ def test_short_grating_solve_and_transmission(lam):
         plan.close()
     print(f"lambda {lam} T {T:.6e} fp64 {T64:.6e} iters {res['iters'][0]}/{res['inner_iters'][0]} fp64 {info['iters']}")
     assert abs(T - T64) <= 1e-6 * T64
+    # the block-circulant preconditioned solve gives the same transmission
+    rc = experiments.bragg_transmission([lam * 1e3], periods=10, lead_periods=2, batch=1, circulant=True)
+    assert rc["status"] == [0] and rc["rel_res"][0] <= 1e-8
+    assert abs(rc["T"][0] - T64) <= 1e-6 * T64
 
 
 def test_full_grating_reflects_in_its_band_gap():
