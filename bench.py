@@ -174,6 +174,47 @@ def cpu_baseline(n, seconds_budget=30.0):
                       f"{el:.1f} s"}
 
 
+def cpu_tuned_matvec(spec, chi, x, workers):
+    """The same FFT matvec with scipy.fft on `workers` threads (FP64): zero-padded 3-D
+    transforms of the three components, the symmetric 3 x 3 product with the full
+    spectrum (components xx, xy, xz, yy, yz, zz), inverse transforms, crop, contrast."""
+    import numpy as np
+    import scipy.fft as sf
+    n = x.shape[1:]
+    M = spec.shape[1:]
+    X = sf.fftn(x, s=M, axes=(1, 2, 3), workers=workers)
+    Y = np.empty_like(X)
+    Y[0] = spec[0] * X[0] + spec[1] * X[1] + spec[2] * X[2]
+    Y[1] = spec[1] * X[0] + spec[3] * X[1] + spec[4] * X[2]
+    Y[2] = spec[2] * X[0] + spec[4] * X[1] + spec[5] * X[2]
+    u = sf.ifftn(Y, axes=(1, 2, 3), workers=workers)[:, :n[0], :n[1], :n[2]]
+    return x - chi[None] * u
+
+
+def cpu_tuned_baseline(n, seconds_budget=10.0):
+    """The FFT matvec on all host cores with scipy.fft (the tuned CPU baseline beside
+    the oracle's own FFT), at the same grid, bounded sample."""
+    import numpy as np
+    workers = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(0)
+    M = tuple(2 * v for v in n)
+    spec = rng.standard_normal((6,) + M) + 1j * rng.standard_normal((6,) + M)
+    chi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x = rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)
+    cpu_tuned_matvec(spec, chi, x, workers)            # plans and page-in
+    t0 = time.perf_counter()
+    runs = 0
+    while True:
+        cpu_tuned_matvec(spec, chi, x, workers)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el > seconds_budget / 2 or runs >= 10:
+            break
+    return {"value": runs / el, "unit": "matvecs/s", "cores": workers, "kind": "scipy.fft",
+            "sample": f"{runs} FFT matvec(s) at {n[0]}x{n[1]}x{n[2]} with scipy.fft on {workers} threads "
+                      f"(products and contrast in numpy), synthetic spectrum of the full circulant shape; {el:.1f} s"}
+
+
 def learned_comparison(n_geom: int = 32, epochs: int = 4):
     """Train the network on seeded rough guides (32x32x256) and compare time to 1e-8 of FP64
     GMRES(50), mixed FGMRES and learned FGMRES on two unseen guides."""
@@ -391,6 +432,7 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)
+        out["cpu_tuned"] = cpu_tuned_baseline(n)
     print(json.dumps(out), flush=True)
 
 
