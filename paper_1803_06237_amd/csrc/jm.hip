@@ -329,7 +329,9 @@ bool jm_fused_shape(const Geom& g, int* cc_out, int* threads_out, int* split_out
     }
     int threads = (int)((need + 63) / 64) * 64;
     if (threads < 256) threads = 256;
-    if (split == 2) threads = kJmXyThreads<2>;   // more waves to hide the LDS stages' latency
+    // at least 512 threads: more waves hide the latency of the LDS stages (with
+    // more, the FP32 strip's workgroups no longer fit two to a CU)
+    if (threads < 512) threads = 512;
     if (threads > (split == 1 ? kJmXyThreads<1> : kJmXyThreads<2>)) continue;
     if (cc_out) *cc_out = cc;
     if (threads_out) *threads_out = threads;
