@@ -234,7 +234,7 @@ bool pick_tune(const Geom& g, size_t budget, size_t zbudget, Tune* t) {
   if (3 * g.M2 * cc > need) need = 3 * g.M2 * cc;
   int xt = (need + 7) / 8;
   xt = ((xt + 63) / 64) * 64;
-  if (xt < 256) xt = 256;
+  if (xt < 512) xt = 512;
   if (xt > 1024) return false;
   t->xythreads = xt;
   const size_t z4 = z4_lds_bytes<T>(g.M3);
