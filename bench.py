@@ -262,8 +262,8 @@ def main():
                     help="profiler run: the JM-VIE products only (both grids, both precisions)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver in this build is "
-              "single-GPU; see DESIGN.md for how the path would shard.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver is single-GPU.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
