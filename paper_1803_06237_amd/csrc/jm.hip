@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kJmXyThreads<SPLIT>) void k_jm_xy(cx<T>* __restrict
   cx<T>* W2 = C + 6 * M2p * cc;                         // twiddles of M2
   cx<T>* W1 = W2 + g.M2;                                // twiddles of M1 (the twist W^n)
   cx<T>* Wx = SPLIT == 1 ? W1 : W1 + g.M1;              // twiddles of the row length
-  const int kz = blockIdx.x;
+  const int kz = paired_plane(blockIdx.x, g.M3);
   const int plane = 3 * g.n1 * g.n2;
   cx<T>* Pe = Ue + (long)kz * plane;
   cx<T>* Pm = Um + (long)kz * plane;

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(1024) void k_xyp(cx<T>* __restrict__ U, const cx<T>
   cx<T>* C = A + 3 * g.n2 * pitch;                     // [3][M2p][cc]
   cx<T>* W1 = C + 3 * M2p * cc;                        // twiddles of M1, then of M2
   cx<T>* W2 = W1 + g.M1;
-  const int kz = blockIdx.x;
+  const int kz = paired_plane(blockIdx.x, g.M3);
   cx<T>* P = U + (long)kz * 3 * g.n1 * g.n2;
   // rows r < 3 n2, x < n1: lanes along x with a power-of-two row width
   const int wlog = g.L1 > 0 ? g.L1 - 1 : 0;
