@@ -34,14 +34,19 @@ __device__ __forceinline__ int xslot(int p, int M, int k1, int a) {
   return p * M + k1 * A + ((a + k1) & (A - 1));
 }
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD b % 8).
-// Pencil blocks 2q and 2q+1 touch the two halves of the same cache lines of the
-// intermediate, so map them to workgroups b and b + 8: same XCD (same L2),
-// dispatched one after the other.  Identity on a tail shorter than 16.
-__device__ __forceinline__ int xcd_pair(int b, int nblocks) {
-  const int base = (b / 16) * 16;
-  if (base + 16 > nblocks) return b;
+// Consecutive pencil blocks touch parts of the same 128-byte cache lines of the
+// intermediate (P values of each line per block), so the G = 128 / (P value
+// bytes) blocks of a line, at least 2 and at most 8, go to workgroups b, b + 8,
+// ..., b + 8 (G - 1): same XCD (same L2), dispatched close together.  A bijection
+// on every full group of 8 G workgroups; identity on a shorter tail.
+template <typename T>
+__device__ __forceinline__ int xcd_group(int b, int nblocks, int P) {
+  int G = 128 / (P * (int)sizeof(cx<T>));
+  G = G < 2 ? 2 : (G > 8 ? 8 : G);
+  const int base = (b / (8 * G)) * (8 * G);
+  if (base + 8 * G > nblocks) return b;
   const int r = b - base;
-  return base + 2 * (r % 8) + r / 8;
+  return base + (r % 8) * G + r / 8;
 }
 
 // Pencils exchange real and imaginary parts separately and stage half of the
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(256) void k_zfwd4(const cx<T>* __restrict__ x, cx<T
                                                 int P, const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   zfwd4_body<T, A, B>((gptr<const cx<T>>)x, (gptr<cx<T>>)U, g, P, (gptr<const cx<T>>)tw,
-                      xcd_pair(blockIdx.x, gridDim.x), reinterpret_cast<cx<T>*>(smem_raw), threadIdx.x);
+                      xcd_group<T>(blockIdx.x, gridDim.x, P), reinterpret_cast<cx<T>*>(smem_raw), threadIdx.x);
 }
 
 template <typename T, int A, int B, int MODE>
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(256) void k_zinv4(const cx<T>* __restrict__ U, cons
                                                 const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   zinv4_body<T, A, B, MODE>((gptr<const cx<T>>)U, (gptr<const cx<T>>)x, (gptr<cx<T>>)y, (gptr<const cx<T>>)bvec,
-                            (gptr<const cx<T>>)chi, g, P, (gptr<const cx<T>>)tw, xcd_pair(blockIdx.x, gridDim.x),
+                            (gptr<const cx<T>>)chi, g, P, (gptr<const cx<T>>)tw, xcd_group<T>(blockIdx.x, gridDim.x, P),
                             reinterpret_cast<cx<T>*>(smem_raw), threadIdx.x);
 }
 
