@@ -232,7 +232,8 @@ int vie_circulant_apply(vie_plan_t plan, const vie_c128* r, vie_c128* z);
 /*
  * Launch-shape tuning.  Unless VIE_NO_AUTOTUNE is given, vie_plan times the
  * candidate shapes of the product's kernels on the plan's own buffers (two
- * untimed and five timed launches each, HIP events) and keeps the fastest:
+ * untimed and five timed launches each, HIP events, in three interleaved rounds
+ * of which each candidate keeps its best) and keeps the fastest:
  * pencils per workgroup of the four-step z passes, or the generic z passes
  * (forward and inverse timed together; circulant lengths 512 to 4096 have
  * four-step shapes) and, for 64 x 64 circulant cross-sections, the xy pass variant

@@ -290,50 +290,57 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
   hipError_t e = hipMalloc(&x, bytes);
   if (!e) e = hipMalloc(&y, bytes);
   if (!e) e = hipMemsetAsync(x, 0, bytes, s);
+  // Every candidate is timed in three interleaved rounds and keeps its best
+  // round: single rounds let launch noise decide between shapes within 1 % of
+  // each other, and the choice then changed from one process to the next.
+  constexpr int kRounds = 3;
   if (!e && t->z4) {
     int opts[8];
     const int n = z4_pencil_options<T>(g.M3, opts, 8);
-    float best = INFINITY;
-    int bestp = 0;
-    for (int i = 0; i < n && !e; ++i) {
-      Tune c = *t;
-      c.zp = opts[i];
-      float ms = 0;
-      e = time_passes<T>(g, c, 0, 0, x, y, U, goct, chi, tw, s, &ms);
-      float ms2 = 0;
-      if (!e) e = time_passes<T>(g, c, 2, 2, x, y, U, goct, chi, tw, s, &ms2);
-      if (!e && ms + ms2 < best) {
-        best = ms + ms2;
-        bestp = opts[i];
+    // candidates: the four-step pencil counts, then the generic LDS passes (the
+    // 64-value shapes of long pencils run at low occupancy in FP64)
+    float best[9];
+    for (int i = 0; i <= n; ++i) best[i] = INFINITY;
+    for (int r = 0; r < kRounds && !e; ++r) {
+      for (int i = 0; i <= n && !e; ++i) {
+        Tune c = *t;
+        if (i < n) {
+          c.zp = opts[i];
+        } else {
+          c.z4 = 0;
+          c.zp = 0;
+        }
+        float ms = 0, ms2 = 0;
+        e = time_passes<T>(g, c, 0, 0, x, y, U, goct, chi, tw, s, &ms);
+        if (!e) e = time_passes<T>(g, c, 2, 2, x, y, U, goct, chi, tw, s, &ms2);
+        if (!e && ms + ms2 < best[i]) best[i] = ms + ms2;
       }
     }
-    t->zp = bestp;
-    // the generic LDS passes as one more candidate (the 64-value shapes of long
-    // pencils run at low occupancy in FP64)
-    Tune c = *t;
-    c.z4 = 0;
-    float ms = 0, ms2 = 0;
-    if (!e) e = time_passes<T>(g, c, 0, 0, x, y, U, goct, chi, tw, s, &ms);
-    if (!e) e = time_passes<T>(g, c, 2, 2, x, y, U, goct, chi, tw, s, &ms2);
-    if (!e && ms + ms2 < best) {
+    int bi = 0;
+    for (int i = 1; i <= n; ++i)
+      if (best[i] < best[bi]) bi = i;
+    if (bi < n) {
+      t->zp = opts[bi];
+    } else {
       t->z4 = 0;
       t->zp = 0;
     }
   }
   if (!e && g.M1 == 64 && g.M2 == 64) {
-    float best = INFINITY;
-    int bestv = t->xyv;
-    for (int v = 0; v < 3 && !e; ++v) {
-      Tune c = *t;
-      c.xyv = v;
-      float ms = 0;
-      e = time_passes<T>(g, c, 1, 1, x, y, U, goct, chi, tw, s, &ms);
-      if (!e && ms < best) {
-        best = ms;
-        bestv = v;
+    float best[3] = {INFINITY, INFINITY, INFINITY};
+    for (int r = 0; r < kRounds && !e; ++r) {
+      for (int v = 0; v < 3 && !e; ++v) {
+        Tune c = *t;
+        c.xyv = v;
+        float ms = 0;
+        e = time_passes<T>(g, c, 1, 1, x, y, U, goct, chi, tw, s, &ms);
+        if (!e && ms < best[v]) best[v] = ms;
       }
     }
-    t->xyv = bestv;
+    int bv = 0;
+    for (int v = 1; v < 3; ++v)
+      if (best[v] < best[bv]) bv = v;
+    t->xyv = bv;
   }
   if (x) (void)hipFree(x);
   if (y) (void)hipFree(y);
