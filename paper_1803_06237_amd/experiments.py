@@ -579,6 +579,44 @@ def bragg_slow_light_study(wavelengths_nm: Sequence[float] = (1520.0, 1538.0),
     return out
 
 
+def bragg_slow_light_spectrum(wavelengths_nm: Sequence[float], absorber_periods: int = 40, ref_periods: int = 90,
+                              d: int = 2, r_rt: float = 1e-10, tol: float = 1e-8, progress=None) -> dict:
+    """R against the free-space wavelength for an absorber inside the grating (Section
+    V, slow light): at each wavelength the guide with an absorber of absorber_periods
+    and the reference with ref_periods are solved (block-circulant preconditioned
+    FGMRES) and R = |E_ref - E|^2 / |E_ref|^2 on the centre line of the lossless part."""
+    import torch
+    out = {"wavelengths_nm": [float(v) for v in wavelengths_nm], "absorber_periods": absorber_periods,
+           "ref_periods": ref_periods, "d": d, "r_rt": r_rt, "R": [], "iters": [], "rel_res": [], "status": []}
+    t0 = time.perf_counter()
+    for lam in wavelengths_nm:
+        fields, its, res, st = {}, [], [], []
+        for P in (absorber_periods, ref_periods):
+            wg = inputs.bragg_slow_light(lam * 1e-3, P, d=d, r_rt=r_rt)
+            plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+            try:
+                plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+                b = plan.rhs(torch.from_numpy(inputs.bragg_source(wg)).cuda())
+                plan.build_circulant()
+                x, info = plan.solve(b, tol=tol, precision=3)
+                fields[P] = bragg_axis_field(wg, x.cpu().numpy())
+            finally:
+                plan.close()
+            its.append(info["iters"])
+            res.append(info["rel_res_true"])
+            st.append(info["status"])
+        ref = fields[ref_periods]
+        R = float(np.sum(np.abs(ref - fields[absorber_periods]) ** 2) / np.sum(np.abs(ref) ** 2))
+        out["R"].append(R)
+        out["iters"].append(its)
+        out["rel_res"].append(max(res))
+        out["status"].append(max(abs(v) for v in st))
+        if progress is not None:
+            progress(lam, R, its)
+    out["seconds"] = round(time.perf_counter() - t0, 3)
+    return out
+
+
 if __name__ == "__main__":
     import argparse
     import json
@@ -596,6 +634,9 @@ if __name__ == "__main__":
     a = ap.parse_args()
     if a.which == "slowlight":
         res = bragg_slow_light_study(progress=lambda r: print(r, flush=True))
+        res["spectrum"] = bragg_slow_light_spectrum(
+            np.arange(1520.0, 1570.0 + 1e-9, a.step),
+            progress=lambda lam, R, its: print(f"{lam:.1f} nm R {R:.3e} outer steps {its}", flush=True))
         if a.out:
             with open(a.out, "w") as f:
                 f.write(json.dumps(res, indent=1))
