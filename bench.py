@@ -111,6 +111,45 @@ def jm_measurement(steps: int):
     return out
 
 
+def strip_measurement(steps: int):
+    """J-VIE products on the paper's strip with its longest absorber (30 x 12 x 1377,
+    circulant 64 x 32 x 4096: generic cross-section pass, long z pencils), FP64 and
+    FP32, timed with HIP events on the plan's stream after one device copy of a
+    3N-value FP64 vector (counter calibration, bytes known)."""
+    import numpy as np
+    import torch
+
+    from paper_1803_06237_amd import inputs, vie
+    wg = inputs.strip_paper(9.45, 2)
+    plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=True)
+    plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+    rng = np.random.default_rng(2)
+    x = torch.from_numpy(rng.standard_normal(3 * wg.N) + 1j * rng.standard_normal(3 * wg.N)).cuda()
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    M = circulant(wg.n)
+    out = {"grid": list(wg.n), "circulant": list(M), "calibration_copy_bytes_each_way": 3 * wg.N * 16}
+    for prec, label in ((0, "fp64"), (1, "fp32")):
+        xx = x if prec == 0 else x.to(torch.complex64)
+        yy = torch.empty_like(xx)
+        f = plan.matvec if prec == 0 else plan.matvec_c64
+        for _ in range(5):
+            f(xx, yy)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            f(xx, yy)
+        t1.record()
+        t1.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        by = pass_bytes(wg.n, M, 16 if prec == 0 else 8)
+        out[label] = {"avg_us": round(ms * 1e3, 2), "modelled_bytes": sum(by), "bytes_by_pass": by,
+                      "frac": round(sum(by) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "tune": plan.tune(prec)}
+    plan.close()
+    return out
+
+
 KERNEL_SOURCES = {
     "k_xy64<double, 0>": ["xy64.hip", "fft_device.hpp"],
     "k_xy64<double, 1>": ["xy64.hip", "fft_device.hpp"],
@@ -260,6 +299,8 @@ def main():
                          "timed FP64 products only")
     ap.add_argument("--profile-jm", action="store_true",
                     help="profiler run: the JM-VIE products only (both grids, both precisions)")
+    ap.add_argument("--profile-strip", action="store_true",
+                    help="profiler run: J-VIE products on the paper's strip 30x12x1377 only (FP64, FP32)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver is single-GPU.",
@@ -273,6 +314,9 @@ def main():
     torch.cuda.set_device(0)
     if args.profile_jm:
         print(json.dumps({"jm_matvec": jm_measurement(args.steps)}), flush=True)
+        return
+    if args.profile_strip:
+        print(json.dumps({"strip_matvec": strip_measurement(args.steps)}), flush=True)
         return
     wg = inputs.strip_long(d=2)
     n = wg.n
