@@ -76,12 +76,16 @@ def test_band_gap_read_out():
     assert "gap_width_nm" not in flat
 
 
+@pytest.mark.parametrize("h", [1.0, 0.05, 0.02])
 @pytest.mark.parametrize("comp", [0, 2])
-def test_total_field_outside_a_small_voxel_is_its_dipole_field(comp):
-    """One silicon voxel in a uniform field, kh -> 0: in the background voxels along z the
-    scattered field is the quasi-static dipole field (3 n (n.p) - p)/(4 pi r^3) of
-    p = (eps_r - 1) E_in h^3; a uniformly polarised cube has no quadrupole moment, so
-    the difference falls as (h/r)^4."""
+def test_total_field_outside_a_small_voxel_is_its_dipole_field(comp, h):
+    """One silicon voxel of edge h in a uniform field, kh -> 0: in the background voxels
+    along z the scattered field is the quasi-static dipole field (3 n (n.p) - p)/(4 pi r^3)
+    of p = (eps_r - 1) E_in h^3 at r = m h; a uniformly polarised cube has no quadrupole
+    moment, so the difference falls as (h/r)^4.  Neither E_in nor the field at r = m h
+    may depend on h (scale invariance at fixed kh), which pins the powers of h that the
+    normalised basis P_i = h^{-3/2} 1_{V_i} (Section III-A) brings into the right-hand
+    side, the field read-out inside the voxel and the total field outside it."""
     eps_b, eps_s, kh = 2.085, 12.11, 1e-3
     n = (1, 1, 7)
     T = green.green_table(n, kh)
@@ -90,12 +94,15 @@ def test_total_field_outside_a_small_voxel_is_its_dipole_field(comp):
     A = mv.dense_A(T, mv.contrast(eps, eps_b))
     e = np.zeros((3,) + n, complex)
     e[comp] = 1.0
-    w = np.linalg.solve(A, mv.rhs_from_field(eps, eps_b, e, 1.0).ravel()).reshape((3,) + n)
-    E = observables.total_field(w, mv.apply_N_direct(T, w), e, eps, eps_b, 1.0)
+    w = np.linalg.solve(A, mv.rhs_from_field(eps, eps_b, e, h).ravel()).reshape((3,) + n)
+    E = observables.total_field(w, mv.apply_N_direct(T, w), e, eps, eps_b, h)
     # inside the dielectric voxel the two read-outs agree (w = M (e_inc + N w))
-    E_in = observables.field_from_current(w, eps, eps_b, 1.0)[:, 0, 0, 0]
+    E_in = observables.field_from_current(w, eps, eps_b, h)[:, 0, 0, 0]
     assert np.abs(E[:, 0, 0, 0] - E_in).max() < 1e-13
-    p = (eps_s / eps_b - 1.0) * E_in
+    # Clausius-Mossotti value inside, independent of h
+    er = eps_s / eps_b
+    assert abs(E_in[comp] - 3.0 / (er + 2.0)) < 5 * kh ** 2
+    p = (er - 1.0) * E_in                # times h^3, which cancels against r^3 = (m h)^3
     nv = np.array([0.0, 0.0, 1.0])
     errs = []
     for m in range(2, 7):

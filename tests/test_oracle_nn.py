@@ -96,3 +96,34 @@ def test_adam_first_step_is_a_sign_step():
     g = RNG.standard_normal(20)
     w1, m, v = nn.adam_step(w, g, np.zeros(20), np.zeros(20), 1, lr=1e-3)
     assert np.allclose(w1, w - 1e-3 * np.sign(g), atol=1e-9)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the moments are m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected moments equal g and g^2 at every step t
+    and each step moves w by exactly lr g / (|g| + eps) (Kingma & Ba, Algorithm 1).
+    A bias-correction exponent off by one fails here from the second step on."""
+    w0 = RNG.standard_normal(16)
+    g = RNG.standard_normal(16) * 10.0 ** RNG.uniform(-3, 2, 16)
+    lr, b1, b2, eps = 3e-3, 0.9, 0.999, 1e-8
+    w, m, v = w0.copy(), np.zeros(16), np.zeros(16)
+    for t in range(1, 41):
+        w, m, v = nn.adam_step(w, g, m, v, t, lr, b1, b2, eps)
+        assert np.allclose(m, (1 - b1 ** t) * g, rtol=1e-13, atol=0)
+        assert np.allclose(v, (1 - b2 ** t) * g * g, rtol=1e-12, atol=0)
+        want = w0 - t * lr * g / (np.abs(g) + eps)
+        assert np.allclose(w, want, rtol=0, atol=1e-12 * t), t
+
+
+def test_adam_two_gradients_closed_form():
+    """Two steps with gradients g1 then g2: m_2 = b1 (1 - b1) g1 + (1 - b1) g2 and
+    v_2 = b2 (1 - b2) g1^2 + (1 - b2) g2^2, corrected by 1 - b1^2 and 1 - b2^2."""
+    w0 = RNG.standard_normal(8)
+    g1, g2 = RNG.standard_normal(8), RNG.standard_normal(8)
+    lr, b1, b2, eps = 1e-2, 0.8, 0.99, 1e-8
+    w1, m, v = nn.adam_step(w0, g1, np.zeros(8), np.zeros(8), 1, lr, b1, b2, eps)
+    w2, m, v = nn.adam_step(w1, g2, m, v, 2, lr, b1, b2, eps)
+    m2 = (b1 * (1 - b1) * g1 + (1 - b1) * g2) / (1 - b1 ** 2)
+    v2 = (b2 * (1 - b2) * g1 ** 2 + (1 - b2) * g2 ** 2) / (1 - b2 ** 2)
+    want = w0 - lr * g1 / (np.abs(g1) + eps) - lr * m2 / (np.sqrt(v2) + eps)
+    assert np.allclose(w2, want, rtol=0, atol=1e-13)
