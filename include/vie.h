@@ -356,6 +356,17 @@ int vie_jm_residual(vie_plan_t plan, const vie_c128* x, const vie_c128* b, vie_c
 int vie_jm_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts* opts,
                  vie_solve_info* info);
 
+/*
+ * vie_check_block_maps -- host-only diagnostic.  Runs the product's workgroup-to-work
+ * maps (z-pass pencil blocks and their XCD grouping, cross-section plane pairs) over
+ * every shape the library accepts and checks that each is a bijection onto its work
+ * items and that every write derived from an item lies inside its buffer.  msg (may be
+ * NULL) receives "ok: ..." or the first violation, cap bytes at most.  planted = 1
+ * checks a deliberately broken map instead (the checker must report it).
+ * Returns VIE_OK when every map passes, VIE_EINVAL otherwise.
+ */
+int vie_check_block_maps(char* msg, size_t cap, int planted);
+
 /* Message for the last failing call on this plan (plan = NULL: on this thread). */
 const char* vie_last_error(vie_plan_t plan);
 

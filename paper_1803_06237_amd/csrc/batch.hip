@@ -442,7 +442,7 @@ struct BatchLevel {         // one Krylov level (outer FP64 or inner FP32) for t
   std::vector<void*> allocs;
 
   hipError_t alloc(void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = dmalloc(p, bytes);
     if (!e) allocs.push_back(*p);
     return e;
   }
@@ -554,7 +554,7 @@ template <typename T>
 hipError_t build_passes(vie_batch_s* B, PassSet& PS, const BatchLevel<T>& L, std::vector<void*>& allocs) {
   const bool dbl = sizeof(T) == 8;
   auto alloc = [&](void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = dmalloc(p, bytes);
     if (!e) allocs.push_back(*p);
     return e;
   };
@@ -827,17 +827,17 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
       return VIE_EDEVICE;           \
     }                               \
   } while (0)
-  BTRY(hipMalloc(&act, sizeof(int) * count));
+  BTRY(dmalloc(&act, sizeof(int) * count));
   extra.push_back(act);
   // every system gets its own intermediate buffers, so one plan may serve
   // several right-hand sides of the batch
   for (int i = 0; i < count; ++i) {
     SysPlan& P = B.sp[i];
     const size_t u = (size_t)3 * P.g.n1 * P.g.n2 * P.g.M3;
-    BTRY(hipMalloc(&P.U64, sizeof(double2) * u));
+    BTRY(dmalloc(&P.U64, sizeof(double2) * u));
     extra.push_back(P.U64);
     if (B.mixed) {
-      BTRY(hipMalloc(&P.U32, sizeof(float2) * u));
+      BTRY(dmalloc(&P.U32, sizeof(float2) * u));
       extra.push_back(P.U32);
     }
   }
@@ -848,9 +848,9 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
     std::vector<void*> ix(count);
     for (int i = 0; i < count; ++i) {
       void *bb = nullptr, *xx = nullptr;
-      BTRY(hipMalloc(&bb, sizeof(float2) * n[i]));
+      BTRY(dmalloc(&bb, sizeof(float2) * n[i]));
       extra.push_back(bb);
-      BTRY(hipMalloc(&xx, sizeof(float2) * n[i]));
+      BTRY(dmalloc(&xx, sizeof(float2) * n[i]));
       extra.push_back(xx);
       ib[i] = bb;
       ix[i] = xx;

@@ -599,15 +599,15 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
   double2* Wh = nullptr;
   int* piv = nullptr;
   int* bad = nullptr;
-  CTRY(hipMalloc(&c->col, sizeof(int) * c->s));
-  CTRY(hipMalloc(&c->tw, sizeof(double2) * P));
-  CTRY(hipMalloc(&S_d, sizeof(int2) * c->s));
+  CTRY(dmalloc(&c->col, sizeof(int) * c->s));
+  CTRY(dmalloc(&c->tw, sizeof(double2) * P));
+  CTRY(dmalloc(&S_d, sizeof(int2) * c->s));
   tmp.push_back(S_d);
-  CTRY(hipMalloc(&ucum_d, sizeof(double2) * ucum.size()));
+  CTRY(dmalloc(&ucum_d, sizeof(double2) * ucum.size()));
   tmp.push_back(ucum_d);
-  CTRY(hipMalloc(&table_d, sizeof(double2) * 6 * g.N));
+  CTRY(dmalloc(&table_d, sizeof(double2) * 6 * g.N));
   tmp.push_back(table_d);
-  CTRY(hipMalloc(&Wt, blk));
+  CTRY(dmalloc(&Wt, blk));
   tmp.push_back(Wt);
   CTRY(hipMemcpyAsync(c->col, cols.data(), sizeof(int) * c->s, hipMemcpyHostToDevice, s));
   CTRY(hipMemcpyAsync(c->tw, tw.data(), sizeof(double2) * P, hipMemcpyHostToDevice, s));
@@ -618,7 +618,7 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
   hipLaunchKernelGGL(k_circ_blocks, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, Wt,
                      table_d, S_d, ucum_d, c->s, g.n1, g.n2, n3, P, total);
   CTRY(hipGetLastError());
-  CTRY(hipMalloc(&Wh, blk));
+  CTRY(dmalloc(&Wh, blk));
   tmp.push_back(Wh);
   const size_t wh_slot = tmp.size() - 1;
   CTRY(hipFuncSetAttribute((const void*)k_circ_fft<double, false, IoBlocks>,
@@ -630,9 +630,9 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
   CTRY(hipFree(table_d));
   tmp[2] = nullptr;
   // Gauss-Jordan on every frequency block
-  CTRY(hipMalloc(&piv, sizeof(int) * (size_t)P * m));
+  CTRY(dmalloc(&piv, sizeof(int) * (size_t)P * m));
   tmp.push_back(piv);
-  CTRY(hipMalloc(&bad, sizeof(int)));
+  CTRY(dmalloc(&bad, sizeof(int)));
   tmp.push_back(bad);
   CTRY(hipMemsetAsync(bad, 0, sizeof(int), s));
   const int nb = m <= 600 ? 16 : (m <= 1200 ? 8 : 4);
@@ -662,14 +662,14 @@ int circ_build(Circ** out, const Geom& g, const std::complex<double>* table, con
     c->inv64 = Wh;
     tmp[wh_slot] = nullptr;
   } else {
-    CTRY(hipMalloc(&c->inv32, sizeof(float2) * (size_t)P * m2));
+    CTRY(dmalloc(&c->inv32, sizeof(float2) * (size_t)P * m2));
     hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, Wh,
                        c->inv32, total);
     CTRY(hipGetLastError());
     CTRY(hipStreamSynchronize(s));
   }
-  CTRY(hipMalloc(&c->xhat, es * (size_t)m * P));
-  CTRY(hipMalloc(&c->yhat, es * (size_t)m * P));
+  CTRY(dmalloc(&c->xhat, es * (size_t)m * P));
+  CTRY(dmalloc(&c->yhat, es * (size_t)m * P));
   const int lds_need = (int)(3 * (size_t)P * es);
   const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
   if (fp64) {

@@ -42,32 +42,14 @@ hipError_t launch_xy64_batch(const PassDesc* d, const int* prefix, int nsys, int
 
 constexpr int kMaxV = 16;   // complex values per thread per FFT stage
 
-// Workgroup b runs on XCD b % 8 (round-robin dispatch).  Pencil blocks next to
-// each other along i1 read and write the same cache lines of the kz-plane-major
-// intermediate, so eight consecutive pencil blocks go to workgroups b, b + 8, ...,
-// b + 56: one XCD, one L2, dispatched close together.  A bijection on every full
-// group of 64 workgroups; identity on a tail shorter than 64.
-__device__ __forceinline__ int xcd_group8(int b, int nblocks) {
-  const int base = (b / 64) * 64;
-  if (base + 64 > nblocks) return b;
-  const int r = b - base;
-  return base + (r % 8) * 8 + r / 8;
-}
-
 // ------------------------------------------------------------------ pass 1
 template <typename T>
 __global__ __launch_bounds__(1024) void k_zfwd(const cx<T>* __restrict__ x, cx<T>* __restrict__ U, Geom g,
                                                 int tp, const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int nb1 = (g.n1 + tp - 1) / tp;
-  int b = xcd_group8(blockIdx.x, gridDim.x);
-  const int ib1 = b % nb1;
-  b /= nb1;
-  const int i2 = b % g.n2;
-  const int c = b / g.n2;
-  const int i1_0 = ib1 * tp;
-  const int np = min(tp, g.n1 - i1_0);
+  const PencilBlock pb = pencil_block(xcd_group8(blockIdx.x, gridDim.x), g.n1, g.n2, tp);
+  const int i2 = pb.i2, c = pb.c, i1_0 = pb.i1_0, np = pb.np;
   const int ld = g.M3 + 1;
   for (int p = 0; p < np; ++p) {
     const cx<T>* src = x + (((long)c * g.n1 + i1_0 + p) * g.n2 + i2) * g.n3;
@@ -91,14 +73,8 @@ __global__ __launch_bounds__(1024) void k_zinv(const cx<T>* __restrict__ U, cons
                                                 const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int nb1 = (g.n1 + tp - 1) / tp;
-  int b = xcd_group8(blockIdx.x, gridDim.x);
-  const int ib1 = b % nb1;
-  b /= nb1;
-  const int i2 = b % g.n2;
-  const int c = b / g.n2;
-  const int i1_0 = ib1 * tp;
-  const int np = min(tp, g.n1 - i1_0);
+  const PencilBlock pb = pencil_block(xcd_group8(blockIdx.x, gridDim.x), g.n1, g.n2, tp);
+  const int i2 = pb.i2, c = pb.c, i1_0 = pb.i1_0, np = pb.np;
   const int ld = g.M3 + 1;
   const long plane = 3L * g.n1 * g.n2;
   const cx<T>* src = U + ((long)c * g.n2 + i2) * g.n1 + i1_0;

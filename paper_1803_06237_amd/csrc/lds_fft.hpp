@@ -21,24 +21,12 @@
 // hoisted across iterations).
 #pragma once
 
+#include "block_maps.hpp"
 #include "fft_device.hpp"
 
 namespace vie {
 
 __device__ __forceinline__ int pad8(int k) { return k + (k >> 3); }
-
-// kz plane of workgroup b in the cross-section passes.  Planes kz and M3 - kz
-// read the same slab of the folded spectra; workgroup b runs on XCD b % 8
-// (round-robin dispatch), so pair p = (p, M3 - p) ((0, M3/2) for p = 0) goes to
-// workgroups 16 (p / 8) + p % 8 and that + 8: one XCD, one after the other.
-// Identity when M3 is not a multiple of 16.
-__device__ __forceinline__ int paired_plane(int b, int M3) {
-  if (M3 % 16 != 0) return b;
-  const int base = (b / 16) * 16, r = b - base;
-  const int p = base / 2 + (r % 8);
-  if (r < 8) return p;
-  return p == 0 ? M3 / 2 : M3 - p;
-}
 
 constexpr int kPadMaxV = 8;   // values per thread per stage
 

@@ -401,7 +401,7 @@ struct vie_net_s {
 namespace {
 
 hipError_t nalloc(vie_net_s* n, void** p, size_t bytes) {
-  hipError_t e = hipMalloc(p, bytes);
+  hipError_t e = dmalloc(p, bytes);
   if (!e) n->allocs.push_back(*p);
   return e;
 }
@@ -643,6 +643,8 @@ int vie_net_get_params(vie_net_t N, float* host, size_t count) {
 int vie_net_set_params(vie_net_t N, const float* host, size_t count) {
   size_t c = 0;
   if (!N || !host || vie_net_num_params(N, &c) || c != count) return VIE_EINVAL;
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(host[i])) return nfail(N, VIE_EINVAL, "weight " + std::to_string(i) + " is not finite");
   size_t off = 0;
   for (auto& L : N->L) {
     if (hipMemcpy(L.w, host + off, sizeof(float) * L.n(), hipMemcpyHostToDevice)) return VIE_EDEVICE;
@@ -703,7 +705,7 @@ int vie_nn_conv_test(int mode, const int dims[3], int taps, int cin, int cout, c
   std::vector<void*> tmp;
   auto al = [&](size_t b) {
     void* p = nullptr;
-    if (hipMalloc(&p, b)) return (void*)nullptr;
+    if (dmalloc(&p, b)) return (void*)nullptr;
     tmp.push_back(p);
     return p;
   };

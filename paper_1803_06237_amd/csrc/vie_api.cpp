@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -107,19 +108,19 @@ struct GmresWs {
     flex = flex_;
     const long nb = partial_blocks(n);
     hipError_t e;
-    if ((e = hipMalloc(&V, sizeof(cx<T>) * (size_t)n * (m + 1)))) return e;
-    if (flex && (e = hipMalloc(&Z, sizeof(cx<T>) * (size_t)n * m))) return e;
-    if ((e = hipMalloc(&partial, sizeof(double2) * (size_t)nb * (m + 1)))) return e;
-    if ((e = hipMalloc(&h1, sizeof(double2) * (m + 2)))) return e;
-    if ((e = hipMalloc(&h2, sizeof(double2) * (m + 2)))) return e;
-    if ((e = hipMalloc(&sumsq, sizeof(double2) * 2))) return e;
-    if ((e = hipMalloc(&gate, sizeof(int)))) return e;
-    if ((e = hipMalloc(&H, sizeof(double2) * (size_t)(m + 1) * m))) return e;
-    if ((e = hipMalloc(&sn, sizeof(double2) * (m + 1)))) return e;
-    if ((e = hipMalloc(&g, sizeof(double2) * (m + 1)))) return e;
-    if ((e = hipMalloc(&y, sizeof(double2) * (m + 1)))) return e;
-    if ((e = hipMalloc(&cs, sizeof(double) * (m + 1)))) return e;
-    if ((e = hipMalloc(&state, sizeof(double) * 4))) return e;
+    if ((e = dmalloc(&V, sizeof(cx<T>) * (size_t)n * (m + 1)))) return e;
+    if (flex && (e = dmalloc(&Z, sizeof(cx<T>) * (size_t)n * m))) return e;
+    if ((e = dmalloc(&partial, sizeof(double2) * (size_t)nb * (m + 1)))) return e;
+    if ((e = dmalloc(&h1, sizeof(double2) * (m + 2)))) return e;
+    if ((e = dmalloc(&h2, sizeof(double2) * (m + 2)))) return e;
+    if ((e = dmalloc(&sumsq, sizeof(double2) * 2))) return e;
+    if ((e = dmalloc(&gate, sizeof(int)))) return e;
+    if ((e = dmalloc(&H, sizeof(double2) * (size_t)(m + 1) * m))) return e;
+    if ((e = dmalloc(&sn, sizeof(double2) * (m + 1)))) return e;
+    if ((e = dmalloc(&g, sizeof(double2) * (m + 1)))) return e;
+    if ((e = dmalloc(&y, sizeof(double2) * (m + 1)))) return e;
+    if ((e = dmalloc(&cs, sizeof(double) * (m + 1)))) return e;
+    if ((e = dmalloc(&state, sizeof(double) * 4))) return e;
     if ((e = hipHostMalloc(&state_h, sizeof(double) * 8, hipHostMallocDefault))) return e;
     for (hipEvent_t& ev_i : ev)
       if ((e = hipEventCreateWithFlags(&ev_i, hipEventDisableTiming))) return e;
@@ -287,8 +288,8 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
   const size_t bytes = sizeof(cx<T>) * 3 * (size_t)g.N;
   void* x = nullptr;
   void* y = nullptr;
-  hipError_t e = hipMalloc(&x, bytes);
-  if (!e) e = hipMalloc(&y, bytes);
+  hipError_t e = dmalloc(&x, bytes);
+  if (!e) e = dmalloc(&y, bytes);
   if (!e) e = hipMemsetAsync(x, 0, bytes, s);
   // Every candidate is timed in three interleaved rounds and keeps its best
   // round: single rounds let launch noise decide between shapes within 1 % of
@@ -358,7 +359,7 @@ hipError_t make_twiddles(int M, cx<T>** out) {
     long double a = -2.0L * 3.14159265358979323846264338327950288L * k / M;
     h[k] = cx<T>{(T)std::cos(a), (T)std::sin(a)};
   }
-  hipError_t e = hipMalloc(out, sizeof(cx<T>) * M);
+  hipError_t e = dmalloc(out, sizeof(cx<T>) * M);
   if (e) return e;
   return hipMemcpy(*out, h.data(), sizeof(cx<T>) * M, hipMemcpyHostToDevice);
 }
@@ -615,6 +616,17 @@ int vie::plan_export(vie_plan_t p, Geom* g, Tune* t64, Tune* t32, void** U64, vo
 
 vie::Circ* vie::plan_circ(vie_plan_t p) { return p ? p->circ : nullptr; }
 
+hipError_t vie::dmalloc_bytes(void** p, size_t bytes) {
+  static const bool nanfill = [] {
+    const char* v = std::getenv("VIE_DEBUG_NANFILL");
+    return v && v[0] == '1';
+  }();
+  hipError_t e = hipMalloc(p, bytes);
+  if (e || !nanfill || bytes == 0) return e;
+  if ((e = hipMemset(*p, 0xFF, bytes))) return e;
+  return hipDeviceSynchronize();
+}
+
 size_t vie::lds_budget(int device) {
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
@@ -709,18 +721,18 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
     PLANTRY(make_twiddles<double>(Ms[d], &p->tw64[d]));
     PLANTRY(make_twiddles<float>(Ms[d], &p->tw32[d]));
   }
-  PLANTRY(hipMalloc(&p->goct64, sizeof(double2) * 6 * H));
-  if (f32) PLANTRY(hipMalloc(&p->goct32, sizeof(float2) * 6 * H));
-  PLANTRY(hipMalloc(&p->chi64, sizeof(double2) * g.N));
-  PLANTRY(hipMalloc(&p->chi32, sizeof(float2) * g.N));
-  PLANTRY(hipMalloc(&p->U64, sizeof(double2) * 3 * (size_t)g.n1 * g.n2 * g.M3));
-  if (f32) PLANTRY(hipMalloc(&p->U32, sizeof(float2) * 3 * (size_t)g.n1 * g.n2 * g.M3));
-  PLANTRY(hipMalloc(&p->rvec, sizeof(double2) * 3 * g.N));
-  PLANTRY(hipMalloc(&p->flag, sizeof(int)));
-  PLANTRY(hipMalloc(&p->colflag, sizeof(int) * (size_t)g.n1 * g.n2));
-  PLANTRY(hipMalloc(&p->scol, sizeof(int) * (size_t)g.n1 * g.n2));
-  PLANTRY(hipMalloc(&table_dev, sizeof(double2) * 6 * g.N));
-  PLANTRY(hipMalloc(&full, sizeof(double2) * P));
+  PLANTRY(dmalloc(&p->goct64, sizeof(double2) * 6 * H));
+  if (f32) PLANTRY(dmalloc(&p->goct32, sizeof(float2) * 6 * H));
+  PLANTRY(dmalloc(&p->chi64, sizeof(double2) * g.N));
+  PLANTRY(dmalloc(&p->chi32, sizeof(float2) * g.N));
+  PLANTRY(dmalloc(&p->U64, sizeof(double2) * 3 * (size_t)g.n1 * g.n2 * g.M3));
+  if (f32) PLANTRY(dmalloc(&p->U32, sizeof(float2) * 3 * (size_t)g.n1 * g.n2 * g.M3));
+  PLANTRY(dmalloc(&p->rvec, sizeof(double2) * 3 * g.N));
+  PLANTRY(dmalloc(&p->flag, sizeof(int)));
+  PLANTRY(dmalloc(&p->colflag, sizeof(int) * (size_t)g.n1 * g.n2));
+  PLANTRY(dmalloc(&p->scol, sizeof(int) * (size_t)g.n1 * g.n2));
+  PLANTRY(dmalloc(&table_dev, sizeof(double2) * 6 * g.N));
+  PLANTRY(dmalloc(&full, sizeof(double2) * P));
   PLANTRY(hipMemcpyAsync(table_dev, table->data(), sizeof(double2) * 6 * g.N, hipMemcpyHostToDevice, p->stream));
   {
     const double2* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
@@ -876,18 +888,18 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
   const Support u{p->scol, p->ns, (long)p->g.n1 * p->g.n2, p->g.n3};
   const long n = u.size();
   if (!p->fx) {
-    HIPTRY(p, hipMalloc(&p->fx, sizeof(double2) * nfull));
-    HIPTRY(p, hipMalloc(&p->fy, sizeof(double2) * nfull));
-    HIPTRY(p, hipMalloc(&p->bc, sizeof(double2) * nfull));
-    HIPTRY(p, hipMalloc(&p->xc, sizeof(double2) * nfull));
-    HIPTRY(p, hipMalloc(&p->partial_full, sizeof(double2) * (partial_blocks(nfull) + 1)));
-    HIPTRY(p, hipMalloc(&p->sumsq_full, sizeof(double2) * 2));
+    HIPTRY(p, dmalloc(&p->fx, sizeof(double2) * nfull));
+    HIPTRY(p, dmalloc(&p->fy, sizeof(double2) * nfull));
+    HIPTRY(p, dmalloc(&p->bc, sizeof(double2) * nfull));
+    HIPTRY(p, dmalloc(&p->xc, sizeof(double2) * nfull));
+    HIPTRY(p, dmalloc(&p->partial_full, sizeof(double2) * (partial_blocks(nfull) + 1)));
+    HIPTRY(p, dmalloc(&p->sumsq_full, sizeof(double2) * 2));
   }
   if (o.precision == 1 && !p->fx32) {
-    HIPTRY(p, hipMalloc(&p->fx32, sizeof(float2) * nfull));
-    HIPTRY(p, hipMalloc(&p->fy32, sizeof(float2) * nfull));
-    HIPTRY(p, hipMalloc(&p->v32a, sizeof(float2) * nfull));
-    HIPTRY(p, hipMalloc(&p->v32b, sizeof(float2) * nfull));
+    HIPTRY(p, dmalloc(&p->fx32, sizeof(float2) * nfull));
+    HIPTRY(p, dmalloc(&p->fy32, sizeof(float2) * nfull));
+    HIPTRY(p, dmalloc(&p->v32a, sizeof(float2) * nfull));
+    HIPTRY(p, dmalloc(&p->v32b, sizeof(float2) * nfull));
   }
   using K = KrylovOps<double>;
   HIPTRY(p, K::zero(p->fx, nfull, s));
@@ -954,8 +966,11 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
                                            o.use_x0 != 0, true, st);
   } else if (o.precision == 2) {
     // learned tier: x0 = net(b), FGMRES with z = net(v) (full-grid network around
-    // the compressed vectors); a cycle that reduces the true residual by less
-    // than half switches to plain GMRES for the rest
+    // the compressed vectors).  Plain GMRES takes over for the rest of the solve
+    // when a cycle reduces the true residual by less than half, when the guess
+    // net(b) is not finite (x0 = 0 then), or when a network output poisons an
+    // Arnoldi step with a non-finite value (the iterate of that cycle's start is
+    // restored: gmres_core leaves x untouched when it stops inside a cycle).
     net_set_stream(p->net, s);
     int napply = 0;
     struct Pc {
@@ -970,20 +985,40 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
         return gather<double>(u, p->fy, reinterpret_cast<double2*>(z), nullptr, p->stream);
       }
     } pc{p, u, &napply};
-    if (!o.use_x0) HIPTRY(p, pc(p->bc, p->xc, st));
+    bool fell_back = false;
+    bool have_x0 = o.use_x0 != 0;
+    if (!o.use_x0) {
+      HIPTRY(p, pc(p->bc, p->xc, st));
+      double xsq = 0;
+      HIPTRY(p, read_norm2(p->xc, n, &xsq));
+      if (std::isfinite(xsq)) {
+        have_x0 = true;
+      } else {
+        HIPTRY(p, K::zero(p->xc, n, s));
+        fell_back = true;
+      }
+    }
     double prev = INFINITY;
     status = VIE_ENOCONV;
-    bool fell_back = false;
     while (st.iters < o.maxit) {
       const int budget = fell_back ? o.maxit : std::min(o.maxit, st.iters + o.restart);
-      if (fell_back)
+      if (fell_back) {
         status = gmres_core<double, Op64c, NoPrecond>(p, p->ws64, A, nullptr, n, p->bc, p->xc, tolc, o.restart,
-                                                      budget, true, true, st);
-      else
-        status = gmres_core<double, Op64c, Pc>(p, p->ws64, A, &pc, n, p->bc, p->xc, tolc, o.restart, budget, true,
-                                               true, st);
-      if (status != VIE_OK && status != VIE_ENOCONV) break;
-      if (status == VIE_OK || fell_back) break;
+                                                      budget, have_x0, true, st);
+        break;
+      }
+      // the cycle's starting iterate, kept in the full-length scratch vector
+      HIPTRY(p, hipMemcpyAsync(p->rvec, p->xc, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+      status = gmres_core<double, Op64c, Pc>(p, p->ws64, A, &pc, n, p->bc, p->xc, tolc, o.restart, budget, have_x0,
+                                             true, st);
+      have_x0 = true;
+      if (status == VIE_ENUMERIC) {
+        HIPTRY(p, hipMemcpyAsync(p->xc, p->rvec, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+        p->err.clear();
+        fell_back = true;
+        continue;
+      }
+      if (status != VIE_ENOCONV) break;
       if (!(st.rel_true < 0.5 * prev)) fell_back = true;
       prev = st.rel_true;
     }
@@ -1176,22 +1211,22 @@ int vie_jm_enable(vie_plan_t p) {
   } while (0)
   JMTRY(allow_lds_jm<double>());
   JMTRY(allow_lds_jm<float>());
-  JMTRY(hipMalloc(&p->koct64, sizeof(double2) * 3 * H));
-  if (f32) JMTRY(hipMalloc(&p->koct32, sizeof(float2) * 3 * H));
-  JMTRY(hipMalloc(&p->chim64, sizeof(double2) * g.N));
-  JMTRY(hipMalloc(&p->chim32, sizeof(float2) * g.N));
+  JMTRY(dmalloc(&p->koct64, sizeof(double2) * 3 * H));
+  if (f32) JMTRY(dmalloc(&p->koct32, sizeof(float2) * 3 * H));
+  JMTRY(dmalloc(&p->chim64, sizeof(double2) * g.N));
+  JMTRY(dmalloc(&p->chim32, sizeof(float2) * g.N));
   JMTRY(hipMemsetAsync(p->chim64, 0, sizeof(double2) * g.N, p->stream));
   JMTRY(hipMemsetAsync(p->chim32, 0, sizeof(float2) * g.N, p->stream));
-  JMTRY(hipMalloc(&p->Um64, sizeof(double2) * nU));
+  JMTRY(dmalloc(&p->Um64, sizeof(double2) * nU));
   p->jm_fused64 = jm_fused_shape<double>(g, nullptr, nullptr);
   p->jm_fused32 = f32 && jm_fused_shape<float>(g, nullptr, nullptr);
-  if (!p->jm_fused64) JMTRY(hipMalloc(&p->S64, sizeof(double2) * jm_spectrum_values(g)));
+  if (!p->jm_fused64) JMTRY(dmalloc(&p->S64, sizeof(double2) * jm_spectrum_values(g)));
   if (f32) {
-    JMTRY(hipMalloc(&p->Um32, sizeof(float2) * nU));
-    if (!p->jm_fused32) JMTRY(hipMalloc(&p->S32, sizeof(float2) * jm_spectrum_values(g)));
+    JMTRY(dmalloc(&p->Um32, sizeof(float2) * nU));
+    if (!p->jm_fused32) JMTRY(dmalloc(&p->S32, sizeof(float2) * jm_spectrum_values(g)));
   }
-  JMTRY(hipMalloc(&kdev, sizeof(double2) * 3 * g.N));
-  JMTRY(hipMalloc(&full, sizeof(double2) * P));
+  JMTRY(dmalloc(&kdev, sizeof(double2) * 3 * g.N));
+  JMTRY(dmalloc(&full, sizeof(double2) * P));
   JMTRY(hipMemcpyAsync(kdev, kt->data(), sizeof(double2) * 3 * g.N, hipMemcpyHostToDevice, p->stream));
   {
     const double2* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
@@ -1214,7 +1249,7 @@ int vie_jm_set_route(vie_plan_t p, int precision, int fused) {
   if (!fused) {
     void** S = precision == 0 ? (void**)&p->S64 : (void**)&p->S32;
     const size_t cs = precision == 0 ? sizeof(double2) : sizeof(float2);
-    if (!*S) HIPTRY(p, hipMalloc(S, cs * jm_spectrum_values(p->g)));
+    if (!*S) HIPTRY(p, dmalloc(S, cs * jm_spectrum_values(p->g)));
   }
   (precision == 0 ? p->jm_fused64 : p->jm_fused32) = fused != 0;
   return VIE_OK;
@@ -1314,8 +1349,8 @@ int vie_jm_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const
                                                    o.use_x0 != 0, true, st);
   } else {
     if (!p->jm32a) {
-      HIPTRY(p, hipMalloc(&p->jm32a, sizeof(float2) * n));
-      HIPTRY(p, hipMalloc(&p->jm32b, sizeof(float2) * n));
+      HIPTRY(p, dmalloc(&p->jm32a, sizeof(float2) * n));
+      HIPTRY(p, dmalloc(&p->jm32b, sizeof(float2) * n));
     }
     OpJM32 A32{p};
     // right preconditioner: z = inner FP32 GMRES solve of A z = v

@@ -140,6 +140,16 @@ hipError_t circ_apply_rows(Circ* c, const double2* r, double2* z, hipStream_t s)
 void circ_destroy(Circ* c);
 const CircInfo& circ_info(const Circ* c);
 
+// Device allocation used throughout the library.  With VIE_DEBUG_NANFILL=1 in the
+// environment every fresh allocation is filled with all-ones bytes (a NaN in FP32
+// and FP64), so a kernel that reads memory nothing has written shows NaN in its
+// results instead of stale zeros.
+hipError_t dmalloc_bytes(void** p, size_t bytes);
+template <typename P>
+inline hipError_t dmalloc(P** p, size_t bytes) {
+  return dmalloc_bytes(reinterpret_cast<void**>(p), bytes);
+}
+
 // LDS budget the kernels may use per workgroup (queried once per device)
 size_t lds_budget(int device);
 

@@ -49,6 +49,7 @@
 // slot i ^ (q & 3), rotated by i.
 #include <hip/hip_runtime.h>
 
+#include "block_maps.hpp"
 #include "fft_device.hpp"
 #include "vie_internal.hpp"
 
@@ -534,12 +535,6 @@ __device__ __forceinline__ void xy64_wide(cx<T>* __restrict__ U, const cx<T>* __
   }
 }
 
-// plane pair p: (0, M3/2) for p = 0, (p, M3 - p) otherwise
-__device__ __forceinline__ void pair_planes(int p, int M3, int* a, int* b) {
-  *a = p == 0 ? 0 : p;
-  *b = p == 0 ? M3 / 2 : M3 - p;
-}
-
 // V = 0: full-plane variant; V = 1: x-frequency halves; V = 2: wide
 template <typename T, int V>
 __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
@@ -570,11 +565,7 @@ __global__ __launch_bounds__(kXyThreads<V>, kXyWaves<V>) void k_xy64(cx<T>* __re
                                                                     const cx<T>* __restrict__ goct, Geom g,
                                                                     const cx<T>* __restrict__ tw64) {
   extern __shared__ unsigned char smem_raw[];
-  const int b = blockIdx.x;
-  const int base = (b / 16) * 16, r = b - base;
-  int pa, pb;
-  pair_planes(base / 2 + (r % 8), g.M3, &pa, &pb);
-  xy64_planes<T, V>(U, goct, g, tw64, r < 8 ? pa : pb, 1, 0, reinterpret_cast<cx<T>*>(smem_raw));
+  xy64_planes<T, V>(U, goct, g, tw64, paired_plane(blockIdx.x, g.M3), 1, 0, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 template <typename T, int V>

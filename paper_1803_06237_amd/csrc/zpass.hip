@@ -21,6 +21,7 @@
 // and a half rounds of workgroups.
 #include <hip/hip_runtime.h>
 
+#include "block_maps.hpp"
 #include "dft_reg.hpp"
 #include "vie_internal.hpp"
 
@@ -33,22 +34,6 @@ template <int A>
 __device__ __forceinline__ int xslot(int p, int M, int k1, int a) {
   return p * M + k1 * A + ((a + k1) & (A - 1));
 }
-// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD b % 8).
-// Consecutive pencil blocks touch parts of the same 128-byte cache lines of the
-// intermediate (P values of each line per block), so the G = 128 / (P value
-// bytes) blocks of a line, at least 2 and at most 8, go to workgroups b, b + 8,
-// ..., b + 8 (G - 1): same XCD (same L2), dispatched close together.  A bijection
-// on every full group of 8 G workgroups; identity on a shorter tail.
-template <typename T>
-__device__ __forceinline__ int xcd_group(int b, int nblocks, int P) {
-  int G = 128 / (P * (int)sizeof(cx<T>));
-  G = G < 2 ? 2 : (G > 8 ? 8 : G);
-  const int base = (b / (8 * G)) * (8 * G);
-  if (base + 8 * G > nblocks) return b;
-  const int r = b - base;
-  return base + (r % 8) * G + r / 8;
-}
-
 // Pencils exchange real and imaginary parts separately and stage half of the
 // kz range at a time (both precisions: it halves the LDS of a workgroup, so
 // twice as many are resident; FP32 forward pass 21.4 -> 15.6 us at 32x32x512)
@@ -115,13 +100,8 @@ __device__ __forceinline__ void zfwd4_body(gptr<const cx<T>> __restrict__ x, gpt
                                            const Geom& g, int P, gptr<const cx<T>> __restrict__ tw, int blk,
                                            cx<T>* S, int tid) {
   constexpr int M = A * B;
-  const int nb1 = (g.n1 + P - 1) / P;
-  const int ib1 = blk % nb1;
-  blk /= nb1;
-  const int i2 = blk % g.n2;
-  const int c = blk / g.n2;
-  const int i1_0 = ib1 * P;
-  const int np = min(P, g.n1 - i1_0);
+  const PencilBlock pb = pencil_block(blk, g.n1, g.n2, P);
+  const int i2 = pb.i2, c = pb.c, i1_0 = pb.i1_0, np = pb.np;
   const int p = tid / A, a = tid % A;
   const int ld = P + 1;
   cx<T> v[B];
@@ -185,7 +165,7 @@ __global__ __launch_bounds__(256) void k_zfwd4(const cx<T>* __restrict__ x, cx<T
                                                 int P, const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   zfwd4_body<T, A, B>((gptr<const cx<T>>)x, (gptr<cx<T>>)U, g, P, (gptr<const cx<T>>)tw,
-                      xcd_group<T>(blockIdx.x, gridDim.x, P), reinterpret_cast<cx<T>*>(smem_raw), threadIdx.x);
+                      xcd_group(blockIdx.x, gridDim.x, P, (int)sizeof(cx<T>)), reinterpret_cast<cx<T>*>(smem_raw), threadIdx.x);
 }
 
 template <typename T, int A, int B, int MODE>
@@ -194,13 +174,8 @@ __device__ __forceinline__ void zinv4_body(gptr<const cx<T>> __restrict__ U, gpt
                                            gptr<const cx<T>> __restrict__ chi, const Geom& g, int P,
                                            gptr<const cx<T>> __restrict__ tw, int blk, cx<T>* S, int tid) {
   constexpr int M = A * B;
-  const int nb1 = (g.n1 + P - 1) / P;
-  const int ib1 = blk % nb1;
-  blk /= nb1;
-  const int i2 = blk % g.n2;
-  const int c = blk / g.n2;
-  const int i1_0 = ib1 * P;
-  const int np = min(P, g.n1 - i1_0);
+  const PencilBlock pb = pencil_block(blk, g.n1, g.n2, P);
+  const int i2 = pb.i2, c = pb.c, i1_0 = pb.i1_0, np = pb.np;
   const int p = tid / A, a = tid % A;
   const int ld = P + 1;
   const long plane = 3L * g.n1 * g.n2;
@@ -278,7 +253,7 @@ __global__ __launch_bounds__(256) void k_zinv4(const cx<T>* __restrict__ U, cons
                                                 const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   zinv4_body<T, A, B, MODE>((gptr<const cx<T>>)U, (gptr<const cx<T>>)x, (gptr<cx<T>>)y, (gptr<const cx<T>>)bvec,
-                            (gptr<const cx<T>>)chi, g, P, (gptr<const cx<T>>)tw, xcd_group<T>(blockIdx.x, gridDim.x, P),
+                            (gptr<const cx<T>>)chi, g, P, (gptr<const cx<T>>)tw, xcd_group(blockIdx.x, gridDim.x, P, (int)sizeof(cx<T>)),
                             reinterpret_cast<cx<T>*>(smem_raw), threadIdx.x);
 }
 

@@ -94,3 +94,18 @@ def test_plan_rejects_bad_arguments_before_touching_the_device():
     assert L.vie_jm_residual(None, None, None, None) == vie.VIE_EINVAL
     assert L.vie_jm_solve(None, None, None, 1e-8, None, None) == vie.VIE_EINVAL
     L.vie_destroy(None)
+
+
+def test_block_maps_are_bijections_with_writes_in_bounds():
+    """Every workgroup-to-work map of the product's pass kernels (z-pass pencil blocks
+    with their XCD grouping, cross-section plane pairs) is a bijection onto its work
+    items over all accepted shapes, and every write derived from an item fits its
+    buffer; the checker itself refuses a planted non-injective map."""
+    L = vie.lib()
+    L.vie_check_block_maps.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int]
+    buf = ctypes.create_string_buffer(512)
+    rc = L.vie_check_block_maps(buf, 512, 0)
+    assert rc == 0, buf.value.decode()
+    assert buf.value.startswith(b"ok:")
+    assert L.vie_check_block_maps(buf, 512, 1) != 0
+    assert b"not injective" in buf.value

@@ -96,3 +96,51 @@ def test_learned_tier_reaches_fp64_tolerance_even_with_an_untrained_net():
     print(info, rr)
     assert info["status"] == 0 and rr <= 1.01e-8
     assert info["inner_iters"] >= 1
+
+
+def _small_system(vie):
+    wg = inputs.Waveguide(n=(8, 8, 32), h=0.05, core_x=(2, 6), core_y=(2, 6), core_z=(0, 32), n_abs=8, d=2,
+                          sigma_max=2.0)
+    kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+    op = mv.Operator(green.green_table(wg.n, kap), mv.contrast(wg.eps(), wg.eps_b))
+    plan = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b, fp32=False)
+    plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+    b = mv.rhs_from_field(wg.eps(), wg.eps_b, inputs.strip_small_dipole_rhs_field(wg), wg.h)
+    return wg, op, plan, b
+
+
+def test_non_finite_weights_are_rejected():
+    vie = _dev()
+    net = vie.Net((8, 8, 32), seed=1)
+    w = net.get_params()
+    before = net.get_params()
+    for bad in (np.nan, np.inf, -np.inf):
+        w2 = w.copy()
+        w2[12345] = bad
+        with pytest.raises(vie.VieError):
+            net.set_params(w2)
+    assert np.array_equal(net.get_params(), before)
+
+
+@pytest.mark.parametrize("use_x0", [False, True], ids=["x0-from-net", "x0-given"])
+def test_broken_network_falls_back_to_plain_gmres(use_x0):
+    """Finite weights of 1e30 overflow the FP32 accumulators: every network output is
+    non-finite.  Without a caller's guess, the guess net(b) is dropped; with one, the
+    first preconditioned Arnoldi step turns non-finite.  Either way the solve must go on
+    as plain GMRES from the last finite iterate and reach the tolerance, judged by the
+    oracle's own product."""
+    vie = _dev()
+    wg, op, plan, b = _small_system(vie)
+    net = vie.Net(wg.n, seed=1)
+    net.set_params(np.full(net.num_params(), 1e30, np.float32))
+    chi = _chi(wg)
+    z = net.apply(torch.from_numpy(b).cuda(), chi)
+    assert not torch.isfinite(z).all()
+    plan.set_preconditioner(net)
+    x = torch.zeros((3,) + wg.n, dtype=torch.complex128, device="cuda")
+    x, info = plan.solve(torch.from_numpy(b).cuda(), x=x, tol=1e-8, restart=30, precision=2, use_x0=use_x0)
+    xs = x.cpu().numpy()
+    assert np.isfinite(xs).all()
+    rr = np.linalg.norm(b.ravel() - op(xs.ravel())) / np.linalg.norm(b)
+    print(info, rr)
+    assert info["status"] == 0 and info["fallback"] == 1 and rr <= 1.01e-8
