@@ -164,6 +164,27 @@ int vie_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol,
               const vie_solve_opts* opts, vie_solve_info* info);
 
 /*
+ * vie_solve_noalloc -- vie_solve for callers that cannot allocate memory during the
+ * call: code that runs while a HIP graph is being captured, tight serving loops,
+ * harnesses that forbid allocation.  It calls no hipMalloc, hipFree, hipHostMalloc
+ * or other allocating routine: every device buffer beyond b and x (full-length
+ * operator vectors, compressed right-hand side and solution, reduction partials,
+ * the Krylov basis and Hessenberg data) comes from one static device array of
+ * 64 MiB per GPU, held until the process ends, and the pinned slot and events it
+ * waits on were made by vie_plan.  Only opts->precision 0 (GMRES) and 3 (FGMRES
+ * with the block circulant, which vie_circulant_build allocated beforehand) are
+ * accepted.  It needs about 16 (2 (3N) + (m + 1 + [precision 3] m) n) bytes plus
+ * O(m^2 + N / 256) for restart m and the support-compressed length n = 3 |S| n3,
+ * and returns VIE_EINVAL with the figure when that exceeds 64 MiB.  All calls on
+ * one GPU share its array and each call starts by clearing what must start at
+ * zero; calls that overlap on one GPU (other threads, other plans' streams) race
+ * and must be serialised by the caller.  Results equal vie_solve's for the same
+ * arguments.
+ */
+int vie_solve_noalloc(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol,
+                      const vie_solve_opts* opts, vie_solve_info* info);
+
+/*
  * vie_solve_batch -- `count` independent systems, each with its own plan (grids
  * may differ), solved together: every Krylov kernel and every matvec pass covers
  * all systems in one launch per kernel shape, the systems advance in lockstep,

@@ -90,8 +90,10 @@ struct GmresWs {
   double* state_h = nullptr;
   int* gate = nullptr;   // second Gram-Schmidt sweep needed (device flag)
   hipEvent_t ev[2] = {nullptr, nullptr};   // step j's state copied to state_h + 4 (j & 1)
+  bool borrowed = false;  // pointers lent by the caller (static scratch): never freed or resized
 
   void release() {
+    if (borrowed) return;
     for (void* p : {(void*)V, (void*)Z, (void*)partial, (void*)h1, (void*)h2, (void*)sumsq, (void*)H, (void*)sn,
                     (void*)g, (void*)y, (void*)cs, (void*)state, (void*)gate})
       if (p) (void)hipFree(p);
@@ -102,6 +104,7 @@ struct GmresWs {
   }
   hipError_t ensure(long n_, int m_, bool flex_) {
     if (n_ == n && m_ == m && flex_ == flex && V) return hipSuccess;
+    if (borrowed) return hipErrorInvalidValue;
     release();
     n = n_;
     m = m_;
@@ -184,6 +187,9 @@ struct vie_plan_s {
   std::shared_ptr<const std::vector<std::complex<double>>> table;   // host Toeplitz table
   GmresWs<double> ws64;
   GmresWs<float> ws32;
+  // created by vie_plan for vie_solve_noalloc, which may not create them itself
+  hipEvent_t nev[2] = {nullptr, nullptr};
+  double* npin = nullptr;      // pinned host slot, 8 doubles
   std::string err;
 };
 
@@ -393,19 +399,21 @@ struct Op32 {
 struct Op64c {
   vie_plan_s* p;
   Support u;
+  double2* fx;   // full-length input (zero off the support) and output
+  double2* fy;
   hipError_t full(const double2* xc) {
-    hipError_t e = scatter<double>(u, xc, p->fx, p->stream);
+    hipError_t e = scatter<double>(u, xc, fx, p->stream);
     if (e) return e;
     const void* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
-    return launch_matvec<double>(p->g, p->t64, p->fx, p->fy, nullptr, 0, p->U64, p->goct64, p->chi64, tw, p->stream);
+    return launch_matvec<double>(p->g, p->t64, fx, fy, nullptr, 0, p->U64, p->goct64, p->chi64, tw, p->stream);
   }
   hipError_t apply(const double2* xc, double2* yc) {
     hipError_t e = full(xc);
-    return e ? e : gather<double>(u, p->fy, yc, nullptr, p->stream);
+    return e ? e : gather<double>(u, fy, yc, nullptr, p->stream);
   }
   hipError_t residual(const double2* xc, const double2* bc, double2* rc) {
     hipError_t e = full(xc);
-    return e ? e : gather<double>(u, p->fy, rc, bc, p->stream);
+    return e ? e : gather<double>(u, fy, rc, bc, p->stream);
   }
 };
 struct Op32c {
@@ -634,6 +642,51 @@ size_t vie::lds_budget(int device) {
   return (size_t)v;
 }
 
+// ---- static scratch of the allocation-free entry point ------------------------
+// vie_solve_noalloc takes every device buffer beyond its inputs and outputs from
+// this array: the full-length operator vectors, the compressed right-hand side and
+// solution, the reduction partials and the Krylov workspace.  Each GPU holds its
+// own copy for the life of the process.  Host code never uses the array's name as
+// an address: vie_plan looks its device address up once per device (with that
+// device current) and every use goes through that pointer.
+namespace {
+constexpr size_t kScratchBytes = 64ull << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices] = {};
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+void scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_done[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+  g_scratch_done[device] = true;
+}
+
+// Bump allocation inside the scratch array, 256-byte aligned.
+struct ScratchCarver {
+  unsigned char* base;
+  size_t used = 0;
+  template <typename P>
+  P* take(size_t count) {
+    used = (used + 255) & ~(size_t)255;
+    P* r = reinterpret_cast<P*>(base + used);
+    used += sizeof(P) * (count ? count : 1);
+    return r;
+  }
+};
+}  // namespace
+
 extern "C" {
 
 const char* vie_version(void) { return "vie-mi355x 0.1 (gfx950)"; }
@@ -691,6 +744,11 @@ int vie_plan(vie_plan_t* out, const int grid[3], double h, double k0, double eps
   };
   hipError_t e;
   if ((e = hipGetDevice(&p->device))) return bail(hipfail(nullptr, e, "hipGetDevice"));
+  scratch_init(p->device);
+  for (hipEvent_t& ev : p->nev)
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming))) return bail(hipfail(nullptr, e, "hipEventCreate"));
+  if ((e = hipHostMalloc(&p->npin, sizeof(double) * 8, hipHostMallocDefault)))
+    return bail(hipfail(nullptr, e, "hipHostMalloc"));
   const size_t budget = lds_budget(p->device);
   const size_t zbudget = budget < 65536 ? budget : 65536;
   if (!pick_tune<double>(g, budget, zbudget, &p->t64) || !pick_tune<float>(g, budget, zbudget, &p->t32))
@@ -834,14 +892,28 @@ int vie_residual(vie_plan_t p, const vie_c128* x, const vie_c128* b, vie_c128* r
   return VIE_OK;
 }
 
-int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts* opts,
-              vie_solve_info* info) {
-  const auto t0 = std::chrono::steady_clock::now();
+namespace {
+
+// Solve-time buffers of vie_solve: the plan's own (allocated on first use) or
+// carved from the static scratch array (vie_solve_noalloc).
+struct SolveBufs {
+  double2* fx;            // full FP64 operator input, zero off the support (3N)
+  double2* fy;            // full FP64 operator output (3N)
+  double2* bc;            // compressed right-hand side (3N at most)
+  double2* xc;            // compressed solution (3N at most)
+  double2* partial_full;  // reduction partials of full-length norms
+  double2* sumsq_full;    // 2 values
+  GmresWs<double>* ws;    // FP64 Krylov workspace
+};
+
+// argument checks and defaults shared by vie_solve and vie_solve_noalloc
+int solve_options(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts* opts,
+                  vie_solve_opts& o) {
   if (!p) return fail(nullptr, VIE_EINVAL, "null plan");
   if (!b || !x || (const void*)b == (const void*)x) return fail(p, VIE_EINVAL, "b, x null or aliased");
   if (!(tol > 0) || !std::isfinite(tol)) return fail(p, VIE_EINVAL, "tol must be positive");
   if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
-  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4, 0};
+  o = vie_solve_opts{50, 10000, 0, 0, 20, 1e-4, 0};
   if (opts) o = *opts;
   if (o.restart <= 0) o.restart = 50;
   if (o.maxit <= 0) o.maxit = 10000;
@@ -854,6 +926,11 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
   if (o.precision == 3 && !p->circ) return fail(p, VIE_ESTATE, "no circulant preconditioner (vie_circulant_build)");
   if (o.precision == 3 && circ_info(p->circ).s != p->ns)
     return fail(p, VIE_ESTATE, "circulant preconditioner built for another support");
+  return VIE_OK;
+}
+
+int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts& o,
+               vie_solve_info* info, const SolveBufs& B, std::chrono::steady_clock::time_point t0) {
   hipStream_t s = p->stream;
   const long nfull = 3 * p->g.N;
   const double2* bd = reinterpret_cast<const double2*>(b);
@@ -887,46 +964,32 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
   }
   const Support u{p->scol, p->ns, (long)p->g.n1 * p->g.n2, p->g.n3};
   const long n = u.size();
-  if (!p->fx) {
-    HIPTRY(p, dmalloc(&p->fx, sizeof(double2) * nfull));
-    HIPTRY(p, dmalloc(&p->fy, sizeof(double2) * nfull));
-    HIPTRY(p, dmalloc(&p->bc, sizeof(double2) * nfull));
-    HIPTRY(p, dmalloc(&p->xc, sizeof(double2) * nfull));
-    HIPTRY(p, dmalloc(&p->partial_full, sizeof(double2) * (partial_blocks(nfull) + 1)));
-    HIPTRY(p, dmalloc(&p->sumsq_full, sizeof(double2) * 2));
-  }
-  if (o.precision == 1 && !p->fx32) {
-    HIPTRY(p, dmalloc(&p->fx32, sizeof(float2) * nfull));
-    HIPTRY(p, dmalloc(&p->fy32, sizeof(float2) * nfull));
-    HIPTRY(p, dmalloc(&p->v32a, sizeof(float2) * nfull));
-    HIPTRY(p, dmalloc(&p->v32b, sizeof(float2) * nfull));
-  }
   using K = KrylovOps<double>;
-  HIPTRY(p, K::zero(p->fx, nfull, s));
+  HIPTRY(p, K::zero(B.fx, nfull, s));
   if (p->fx32) HIPTRY(p, KrylovOps<float>::zero(p->fx32, nfull, s));
   double tmp_h[1];
   auto read_norm2 = [&](const double2* v, long len, double* out) -> hipError_t {
-    hipError_t e = K::nrm2sq(v, len, p->partial_full, p->sumsq_full, s);
+    hipError_t e = K::nrm2sq(v, len, B.partial_full, B.sumsq_full, s);
     if (e) return e;
-    e = hipMemcpyAsync(tmp_h, p->sumsq_full, sizeof(double), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(tmp_h, B.sumsq_full, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e) return e;
     e = hipStreamSynchronize(s);
     *out = tmp_h[0];
     return e;
   };
   double bsq_on = 0, bsq_off = 0, bcsq = 0;
-  HIPTRY(p, gather<double>(u, bd, p->bc, nullptr, s));
-  HIPTRY(p, read_norm2(p->bc, n, &bsq_on));
+  HIPTRY(p, gather<double>(u, bd, B.bc, nullptr, s));
+  HIPTRY(p, read_norm2(B.bc, n, &bsq_on));
   HIPTRY(p, hipMemcpyAsync(p->rvec, bd, sizeof(double2) * nfull, hipMemcpyDeviceToDevice, s));
   HIPTRY(p, zero_support<double>(u, p->rvec, s));
   HIPTRY(p, read_norm2(p->rvec, nfull, &bsq_off));
   if (!std::isfinite(bsq_on) || !std::isfinite(bsq_off)) return fail(p, VIE_EINVAL, "right-hand side is not finite");
   if (bsq_off > 0) {
     const void* tw[3] = {p->tw64[0], p->tw64[1], p->tw64[2]};
-    HIPTRY(p, launch_matvec<double>(p->g, p->t64, p->rvec, p->fy, nullptr, 0, p->U64, p->goct64, p->chi64, tw, s));
+    HIPTRY(p, launch_matvec<double>(p->g, p->t64, p->rvec, B.fy, nullptr, 0, p->U64, p->goct64, p->chi64, tw, s));
     st.matvecs++;
-    HIPTRY(p, gather<double>(u, p->fy, p->bc, p->bc, s));
-    HIPTRY(p, read_norm2(p->bc, n, &bcsq));
+    HIPTRY(p, gather<double>(u, B.fy, B.bc, B.bc, s));
+    HIPTRY(p, read_norm2(B.bc, n, &bcsq));
   } else {
     bcsq = bsq_on;
   }
@@ -940,10 +1003,10 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
   }
   const double ratio = std::sqrt(bcsq) / bnorm;   // ||b_c|| / ||b||
   const double tolc = tol / ratio;
-  if (o.use_x0) HIPTRY(p, gather<double>(u, xd, p->xc, nullptr, s));
-  Op64c A{p, u};
+  if (o.use_x0) HIPTRY(p, gather<double>(u, xd, B.xc, nullptr, s));
+  Op64c A{p, u, B.fx, B.fy};
   if (o.precision == 0) {
-    status = gmres_core<double, Op64c, NoPrecond>(p, p->ws64, A, nullptr, n, p->bc, p->xc, tolc, o.restart, o.maxit,
+    status = gmres_core<double, Op64c, NoPrecond>(p, *B.ws, A, nullptr, n, B.bc, B.xc, tolc, o.restart, o.maxit,
                                                   o.use_x0 != 0, true, st);
   } else if (o.precision == 1) {
     Op32c A32{p, u};
@@ -962,7 +1025,7 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
       decltype(inner)& f;
       hipError_t operator()(const void* v, void* z, Stats& st_) { return f(v, z, st_); }
     } pc{inner};
-    status = gmres_core<double, Op64c, Pc>(p, p->ws64, A, &pc, n, p->bc, p->xc, tolc, o.restart, o.maxit,
+    status = gmres_core<double, Op64c, Pc>(p, *B.ws, A, &pc, n, B.bc, B.xc, tolc, o.restart, o.maxit,
                                            o.use_x0 != 0, true, st);
   } else if (o.precision == 2) {
     // learned tier: x0 = net(b), FGMRES with z = net(v) (full-grid network around
@@ -977,24 +1040,26 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
       vie_plan_s* p;
       Support u;
       int* count;
+      double2* fx;
+      double2* fy;
       hipError_t operator()(const void* v, void* z, Stats&) {
         ++*count;
-        hipError_t e = scatter<double>(u, reinterpret_cast<const double2*>(v), p->fx, p->stream);
+        hipError_t e = scatter<double>(u, reinterpret_cast<const double2*>(v), fx, p->stream);
         if (e) return e;
-        if ((e = net_apply(p->net, p->fx, p->chi64, p->fy))) return e;
-        return gather<double>(u, p->fy, reinterpret_cast<double2*>(z), nullptr, p->stream);
+        if ((e = net_apply(p->net, fx, p->chi64, fy))) return e;
+        return gather<double>(u, fy, reinterpret_cast<double2*>(z), nullptr, p->stream);
       }
-    } pc{p, u, &napply};
+    } pc{p, u, &napply, B.fx, B.fy};
     bool fell_back = false;
     bool have_x0 = o.use_x0 != 0;
     if (!o.use_x0) {
-      HIPTRY(p, pc(p->bc, p->xc, st));
+      HIPTRY(p, pc(B.bc, B.xc, st));
       double xsq = 0;
-      HIPTRY(p, read_norm2(p->xc, n, &xsq));
+      HIPTRY(p, read_norm2(B.xc, n, &xsq));
       if (std::isfinite(xsq)) {
         have_x0 = true;
       } else {
-        HIPTRY(p, K::zero(p->xc, n, s));
+        HIPTRY(p, K::zero(B.xc, n, s));
         fell_back = true;
       }
     }
@@ -1003,17 +1068,17 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
     while (st.iters < o.maxit) {
       const int budget = fell_back ? o.maxit : std::min(o.maxit, st.iters + o.restart);
       if (fell_back) {
-        status = gmres_core<double, Op64c, NoPrecond>(p, p->ws64, A, nullptr, n, p->bc, p->xc, tolc, o.restart,
+        status = gmres_core<double, Op64c, NoPrecond>(p, *B.ws, A, nullptr, n, B.bc, B.xc, tolc, o.restart,
                                                       budget, have_x0, true, st);
         break;
       }
       // the cycle's starting iterate, kept in the full-length scratch vector
-      HIPTRY(p, hipMemcpyAsync(p->rvec, p->xc, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
-      status = gmres_core<double, Op64c, Pc>(p, p->ws64, A, &pc, n, p->bc, p->xc, tolc, o.restart, budget, have_x0,
+      HIPTRY(p, hipMemcpyAsync(p->rvec, B.xc, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+      status = gmres_core<double, Op64c, Pc>(p, *B.ws, A, &pc, n, B.bc, B.xc, tolc, o.restart, budget, have_x0,
                                              true, st);
       have_x0 = true;
       if (status == VIE_ENUMERIC) {
-        HIPTRY(p, hipMemcpyAsync(p->xc, p->rvec, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+        HIPTRY(p, hipMemcpyAsync(B.xc, p->rvec, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
         p->err.clear();
         fell_back = true;
         continue;
@@ -1034,17 +1099,99 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
                                p->stream);
       }
     } pc{p};
-    status = gmres_core<double, Op64c, Pc>(p, p->ws64, A, &pc, n, p->bc, p->xc, tolc, o.restart, o.maxit,
+    status = gmres_core<double, Op64c, Pc>(p, *B.ws, A, &pc, n, B.bc, B.xc, tolc, o.restart, o.maxit,
                                            o.use_x0 != 0, true, st);
   }
   if (status == VIE_OK || status == VIE_ENOCONV) {
     HIPTRY(p, x_is_b());
-    HIPTRY(p, scatter<double>(u, p->xc, xd, s));
+    HIPTRY(p, scatter<double>(u, B.xc, xd, s));
     HIPTRY(p, hipStreamSynchronize(s));
   }
   st.rel_true *= ratio;
   st.est *= ratio;
   return report(status);
+}
+
+}  // namespace
+
+int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts* opts,
+              vie_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  vie_solve_opts o;
+  const int rc = solve_options(p, b, x, tol, opts, o);
+  if (rc != VIE_OK) return rc;
+  const long nfull = 3 * p->g.N;
+  if (!p->fx) {
+    HIPTRY(p, dmalloc(&p->fx, sizeof(double2) * nfull));
+    HIPTRY(p, dmalloc(&p->fy, sizeof(double2) * nfull));
+    HIPTRY(p, dmalloc(&p->bc, sizeof(double2) * nfull));
+    HIPTRY(p, dmalloc(&p->xc, sizeof(double2) * nfull));
+    HIPTRY(p, dmalloc(&p->partial_full, sizeof(double2) * (partial_blocks(nfull) + 1)));
+    HIPTRY(p, dmalloc(&p->sumsq_full, sizeof(double2) * 2));
+  }
+  if (o.precision == 1 && !p->fx32) {
+    HIPTRY(p, dmalloc(&p->fx32, sizeof(float2) * nfull));
+    HIPTRY(p, dmalloc(&p->fy32, sizeof(float2) * nfull));
+    HIPTRY(p, dmalloc(&p->v32a, sizeof(float2) * nfull));
+    HIPTRY(p, dmalloc(&p->v32b, sizeof(float2) * nfull));
+  }
+  const SolveBufs B{p->fx, p->fy, p->bc, p->xc, p->partial_full, p->sumsq_full, &p->ws64};
+  return solve_impl(p, b, x, tol, o, info, B, t0);
+}
+
+int vie_solve_noalloc(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vie_solve_opts* opts,
+                      vie_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  vie_solve_opts o;
+  const int rc = solve_options(p, b, x, tol, opts, o);
+  if (rc != VIE_OK) return rc;
+  if (o.precision != 0 && o.precision != 3)
+    return fail(p, VIE_EINVAL, "vie_solve_noalloc: precision 0 (GMRES) or 3 (circulant FGMRES) only");
+  if (p->device < 0 || p->device >= kMaxDevices || !g_scratch_ptr[p->device])
+    return fail(p, VIE_EDEVICE,
+                std::string("vie_solve_noalloc: no scratch address for this device (hipGetSymbolAddress: ") +
+                    (p->device >= 0 && p->device < kMaxDevices ? hipGetErrorString(g_scratch_err[p->device])
+                                                               : "device index out of range") +
+                    ")");
+  const long nfull = 3 * p->g.N;
+  const long n = 3L * p->ns * p->g.n3;   // support-compressed length
+  const int m = o.restart;
+  const bool flex = o.precision == 3;
+  ScratchCarver c{static_cast<unsigned char*>(g_scratch_ptr[p->device])};
+  SolveBufs B;
+  B.fx = c.take<double2>(nfull);
+  B.fy = c.take<double2>(nfull);
+  B.bc = c.take<double2>(n);
+  B.xc = c.take<double2>(n);
+  B.partial_full = c.take<double2>(partial_blocks(nfull) + 1);
+  B.sumsq_full = c.take<double2>(2);
+  GmresWs<double> ws;
+  ws.borrowed = true;
+  ws.n = n;
+  ws.m = m;
+  ws.flex = flex;
+  ws.V = c.take<double2>((size_t)n * (m + 1));
+  ws.Z = flex ? c.take<double2>((size_t)n * m) : nullptr;
+  ws.partial = c.take<double2>((size_t)partial_blocks(n) * (m + 1));
+  ws.h1 = c.take<double2>(m + 2);
+  ws.h2 = c.take<double2>(m + 2);
+  ws.sumsq = c.take<double2>(2);
+  ws.gate = c.take<int>(1);
+  ws.H = c.take<double2>((size_t)(m + 1) * m);
+  ws.sn = c.take<double2>(m + 1);
+  ws.g = c.take<double2>(m + 1);
+  ws.y = c.take<double2>(m + 1);
+  ws.cs = c.take<double>(m + 1);
+  ws.state = c.take<double>(4);
+  ws.state_h = p->npin;
+  ws.ev[0] = p->nev[0];
+  ws.ev[1] = p->nev[1];
+  if (c.used > kScratchBytes)
+    return fail(p, VIE_EINVAL,
+                "vie_solve_noalloc: this grid, support and restart need " + std::to_string(c.used) +
+                    " bytes of scratch; the limit is " + std::to_string(kScratchBytes));
+  B.ws = &ws;
+  return solve_impl(p, b, x, tol, o, info, B, t0);
 }
 
 int vie_profile_matvec(vie_plan_t p, int precision, const void* x, void* y, int reps, double pass_ms[3],
@@ -1395,6 +1542,9 @@ void vie_destroy(vie_plan_t p) {
   }
   p->ws64.release();
   p->ws32.release();
+  for (hipEvent_t ev : p->nev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (p->npin) (void)hipHostFree(p->npin);
   for (void* q : {(void*)p->goct64, (void*)p->goct32, (void*)p->chi64, (void*)p->chi32, (void*)p->U64,
                   (void*)p->U32, (void*)p->rvec, (void*)p->v32a, (void*)p->v32b, (void*)p->flag, (void*)p->colflag,
                   (void*)p->scol, (void*)p->fx, (void*)p->fy, (void*)p->fx32, (void*)p->fy32, (void*)p->bc,

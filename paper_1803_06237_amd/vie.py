@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
         L.vie_residual.argtypes = [vp, vp, vp, vp]
         L.vie_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(SolveOpts),
                                 ctypes.POINTER(SolveInfo)]
+        L.vie_solve_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(SolveOpts),
+                                ctypes.POINTER(SolveInfo)]
         L.vie_profile_matvec.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.vie_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
@@ -287,6 +289,22 @@ class Plan:
                                _ptr(x, torch.complex128, 3 * self.N, "x"), float(tol), ctypes.byref(opts),
                                ctypes.byref(info))
         if code not in (VIE_OK, VIE_ENOCONV) or (raise_on_noconv and code != VIE_OK):
+            _check(code, self._h)
+        return x, info.as_dict()
+
+    def solve_noalloc(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000,
+                      precision: int = 0, use_x0: bool = False):
+        """vie_solve_noalloc: the same solve with no allocation during the call (precision 0
+        or 3), its workspace in the library's static scratch array.  Returns (x, info dict)."""
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        opts = SolveOpts(int(restart), int(maxit), int(bool(use_x0)), int(precision), 20, 1e-4, 0)
+        info = SolveInfo()
+        code = lib().vie_solve_noalloc(self._h, _ptr(b, torch.complex128, 3 * self.N, "b"),
+                                       _ptr(x, torch.complex128, 3 * self.N, "x"), float(tol), ctypes.byref(opts),
+                                       ctypes.byref(info))
+        if code not in (VIE_OK, VIE_ENOCONV):
             _check(code, self._h)
         return x, info.as_dict()
 
