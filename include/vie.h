@@ -293,6 +293,25 @@ int vie_profile_matvec(vie_plan_t plan, int precision, const void* x, void* y, i
  * Activations are bfloat16, convolutions run on the matrix cores with FP32
  * accumulation, master weights and Adam moments are FP32.
  *
+ * Architecture (levels 0..3 at grid / 2^l, voxel v = (i1 n2 + i2) n3 + i3 at
+ * level 0, channels last, every channel count padded to a multiple of 16):
+ *   input X0 (16 ch): Re, Im of r_x, r_y, r_z times s, Re, Im of chi, then zeros;
+ *   L0  3x3x3  16 -> 16  (8 real inputs)   E1a = relu(L0 X0)
+ *   L1  3x3x3  16 -> 16                     E1b = relu(L1 E1a)
+ *   P1 = avgpool2(E1b);  L2 16 -> 32: E2a;  L3 32 -> 32: E2b
+ *   P2 = avgpool2(E2b);  L4 32 -> 48: E3a;  L5 48 -> 48: E3b
+ *   P3 = avgpool2(E3b);  L6 48 -> 64: E4a;  L7 64 -> 64: E4b
+ *   L8  112 -> 48 on [up(E4b), E3b]:  D3a;  L9  48 -> 48: D3b
+ *   L10  80 -> 32 on [up(D3b), E2b]:  D2a;  L11 32 -> 32: D2b
+ *   L12  48 -> 16 on [up(D2b), E1b]:  D1a;  L13 16 -> 16: D1b
+ *   L14 1x1x1 16 -> 16 (6 real outputs), no ReLU, FP32 output "out"
+ * ([a, b] = channel concatenation, a first; up = nearest upsampling x2; every
+ * relu(.) output and every pooled value is stored in bfloat16, rounded to
+ * nearest even; the convolutions use bfloat16 weights, the master copies are
+ * FP32).  Weights of layer l are [taps][cout][cin] with tap t = (dz+1) 9 +
+ * (dy+1) 3 + (dx+1) shifting along (i1, i2, i3); vie_net_get_params lists
+ * L0..L14 in order.  z_c = r_c + (out[2c] + i out[2c+1]) / s.
+ *
  * vie_net_create: grid dims must be multiples of 8 (three poolings).  Weights
  *   are He-initialised from `seed` (deterministic).  hip_stream as in vie_plan.
  * vie_net_num_params / get / set: the FP32 master weights, host buffer of
@@ -323,6 +342,26 @@ int vie_set_preconditioner(vie_plan_t plan, vie_net_t net);
 int vie_nn_conv_test(int mode, const int dims[3], int taps, int cin, int cout, const float* x, const float* w,
                      float* out, int relu, void* hip_stream);
 const char* vie_net_last_error(vie_net_t net);
+/*
+ * Diagnostics for parity tests.
+ * vie_net_get_grads: the FP32 weight gradients of the last vie_net_train_step (summed
+ *   over its samples), host buffer of vie_net_num_params floats in the layout of
+ *   vie_net_get_params.  Synchronises.
+ * vie_nn_op_test: one pooling or upsampling kernel on FP32 device buffers (inputs
+ *   rounded to bfloat16, bfloat16 results widened to FP32), C channels per voxel
+ *   (channels last), dims = the fine grid (even sizes): op 0 average pooling
+ *   x[fine] -> out[coarse]; 1 its gradient x = dY[coarse] -> out[fine] = dY/8 at the
+ *   parent, zero where mask[fine] <= 0 (mask may be NULL), added to acc[fine] (may be
+ *   NULL) with one bfloat16 rounding; 2 nearest upsampling x[coarse] -> out[fine];
+ *   3 its gradient x = dY[fine] -> out[coarse] = sum over the 8 children.  Synchronises.
+ * vie_nn_adam_test: Adam step t >= 1 (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ *   corrections 1 - beta^t) on n FP32 device values w, m, v in place with gradient g,
+ *   learning rate lr, as the training step applies it.  Synchronises.
+ */
+int vie_net_get_grads(vie_net_t net, float* host, size_t count);
+int vie_nn_op_test(int op, const int dims[3], int C, const float* x, const float* mask, const float* acc,
+                   float* out, void* hip_stream);
+int vie_nn_adam_test(long n, float* w, float* m, float* v, const float* g, int t, float lr, void* hip_stream);
 
 /*
  * JM-VIE: electric and magnetic currents (Section III, the coupled system

@@ -300,15 +300,30 @@ def parity(a: int, b: int, d: int) -> int:
     return -1 if ((a == d) != (b == d)) else 1
 
 
-def green_table(n: Iterable[int], kappa: float) -> np.ndarray:
+def _galerkin_chunk(args):
+    m, kappa = args
+    return galerkin_N(m, kappa)
+
+
+def green_table(n: Iterable[int], kappa: float, workers: int = 1) -> np.ndarray:
     """Toeplitz table N^{ab}(m) for all non-negative offsets 0 <= m_d < n_d.
 
     Returns complex128 array of shape (6, n1, n2, n3) (components in COMPONENTS order).
-    Entries for negative offsets follow from ``parity``."""
+    Entries for negative offsets follow from ``parity``.  workers > 1 evaluates
+    slices of offsets along the first axis in that many processes; every entry is
+    computed by the same code either way (the vectorised quadrature sums may round
+    differently in the last bit with the batch size; tests check agreement to 1e-15)."""
     n1, n2, n3 = n
     g = np.stack(np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3), indexing="ij"), -1)
-    vals = galerkin_N(g.reshape(-1, 3), kappa)
-    return vals.reshape(6, n1, n2, n3)
+    if workers <= 1 or n1 < 2:
+        vals = galerkin_N(g.reshape(-1, 3), kappa)
+        return vals.reshape(6, n1, n2, n3)
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    jobs = [(g[i].reshape(-1, 3), kappa) for i in range(n1)]
+    with cf.ProcessPoolExecutor(max_workers=min(workers, n1), mp_context=mp.get_context("fork")) as ex:
+        parts = list(ex.map(_galerkin_chunk, jobs))
+    return np.stack([p.reshape(6, n2, n3) for p in parts], axis=1)
 
 
 def entry(table: np.ndarray, a: int, b: int, m: Tuple[int, int, int]) -> complex:

@@ -289,18 +289,25 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, con
 
 // Adam on the FP32 master weights; refresh the BF16 copies for the forward
 // ([t][o][i]) and input-gradient ([26 - t][i][o]) convolutions.
+// The constants come from the host, formed in FP64 and rounded once: k.omb1 = 1 - beta1,
+// k.omb2 = 1 - beta2 and the bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t
+// (1 - 0.999f in FP32 would carry a relative error of 1.3e-5).
+struct AdamK {
+  float lr, b1, omb1, b2, omb2, eps, c1, c2;
+};
+
 __global__ void k_adam(float* __restrict__ w, float* __restrict__ mo, float* __restrict__ ve,
-                       const float* __restrict__ g, long n, float lr, float b1, float b2, float eps, float c1, float c2,
-                       int taps, int Cout, int Cin, bf16_t* __restrict__ wbf, bf16_t* __restrict__ wtbf, int update) {
+                       const float* __restrict__ g, long n, AdamK k, int taps, int Cout, int Cin,
+                       bf16_t* __restrict__ wbf, bf16_t* __restrict__ wtbf, int update) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     float wi = w[i];
     if (update) {
       const float gi = g[i];
-      const float m1 = b1 * mo[i] + (1.f - b1) * gi;
-      const float v1 = b2 * ve[i] + (1.f - b2) * gi * gi;
+      const float m1 = k.b1 * mo[i] + k.omb1 * gi;
+      const float v1 = k.b2 * ve[i] + k.omb2 * gi * gi;
       mo[i] = m1;
       ve[i] = v1;
-      wi -= lr * (m1 / c1) / (sqrtf(v1 / c2) + eps);
+      wi -= k.lr * (m1 / k.c1) / (sqrtf(v1 / k.c2) + k.eps);
       w[i] = wi;
     }
     const int ci = (int)(i % Cin);
@@ -316,8 +323,27 @@ __global__ void k_f2bf(const float* a, bf16_t* b, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) b[i] = f2bf(a[i]);
 }
 
+__global__ void k_bf2f(const bf16_t* a, float* b, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) b[i] = bf2f(a[i]);
+}
+
 __global__ void k_fill_bf(bf16_t* p, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Adam (Kingma & Ba) constants of step t and learning rate lr
+static inline AdamK adam_constants(int t, float lr) {
+  const double b1 = 0.9, b2 = 0.999;
+  AdamK k;
+  k.lr = lr;
+  k.b1 = (float)b1;
+  k.omb1 = (float)(1.0 - b1);
+  k.b2 = (float)b2;
+  k.omb2 = (float)(1.0 - b2);
+  k.eps = 1e-8f;
+  k.c1 = (float)(1.0 - std::pow(b1, (double)t));
+  k.c2 = (float)(1.0 - std::pow(b2, (double)t));
+  return k;
 }
 
 static inline int gblocks(long n) { return (int)std::min<long>(4096, (n + 255) / 256); }
@@ -506,13 +532,11 @@ hipError_t net_backward(vie_net_s* N, int accumulate) {
 }
 
 hipError_t refresh_weights(vie_net_s* N, int update, float lr) {
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   if (update) N->step++;
-  const float c1 = 1.f - std::pow(b1, (float)std::max(1, N->step));
-  const float c2 = 1.f - std::pow(b2, (float)std::max(1, N->step));
+  const AdamK k = adam_constants(std::max(1, N->step), lr);
   for (auto& L : N->L)
-    hipLaunchKernelGGL(k_adam, dim3(gblocks(L.n())), dim3(256), 0, N->stream, L.w, L.m, L.v, L.g, L.n(), lr, b1, b2,
-                       eps, c1, c2, L.taps, L.cout, L.cin, L.wbf, L.wtbf, update);
+    hipLaunchKernelGGL(k_adam, dim3(gblocks(L.n())), dim3(256), 0, N->stream, L.w, L.m, L.v, L.g, L.n(), k, L.taps,
+                       L.cout, L.cin, L.wbf, L.wtbf, update);
   return hipGetLastError();
 }
 
@@ -735,14 +759,96 @@ int vie_nn_conv_test(int mode, const int dims[3], int taps, int cin, int cout, c
   bf16_t* wtbf = (bf16_t*)al(sizeof(bf16_t) * nw);
   if (!w32 || !dummy || !wbf || !wtbf) return fin(VIE_ENOMEM);
   if (hipMemcpyAsync(w32, w, sizeof(float) * nw, hipMemcpyDeviceToDevice, s)) return fin(VIE_EDEVICE);
-  hipLaunchKernelGGL(k_adam, dim3(gblocks(nw)), dim3(256), 0, s, w32, dummy, dummy, dummy, nw, 0.f, 0.f, 0.f, 0.f, 1.f,
-                     1.f, taps, cout, cin, wbf, wtbf, 0);
+  hipLaunchKernelGGL(k_adam, dim3(gblocks(nw)), dim3(256), 0, s, w32, dummy, dummy, dummy, nw, adam_constants(1, 0.f),
+                     taps, cout, cin, wbf, wtbf, 0);
   hipError_t e;
   if (mode == 0)
     e = conv_launch(taps, xb, cin, 0, cin, wbf, cout, nullptr, 0, 0, out, vol, relu, nullptr, 0, 0, s);
   else
     e = conv_launch(taps, xb, cout, 0, cout, wtbf, cin, nullptr, 0, 0, out, vol, 0, nullptr, 0, 0, s);
   return fin(e ? VIE_EDEVICE : VIE_OK);
+}
+
+int vie_net_get_grads(vie_net_t N, float* host, size_t count) {
+  size_t c = 0;
+  if (!N || !host || vie_net_num_params(N, &c) || c != count) return VIE_EINVAL;
+  if (hipStreamSynchronize(N->stream)) return VIE_EDEVICE;
+  size_t off = 0;
+  for (auto& L : N->L) {
+    if (hipMemcpy(host + off, L.g, sizeof(float) * L.n(), hipMemcpyDeviceToHost)) return VIE_EDEVICE;
+    off += L.n();
+  }
+  return VIE_OK;
+}
+
+// Diagnostic pooling / upsampling on FP32 device buffers (rounded to bfloat16 on
+// entry, bfloat16 results widened to FP32), C channels per voxel, fine grid dims:
+// op 0 pool x[fine] -> out[coarse]; 1 pool gradient x = dY[coarse] -> out[fine],
+// masked by mask[fine] > 0 when mask != NULL and added to acc[fine] when acc != NULL;
+// 2 upsampling x[coarse] -> out[fine]; 3 its gradient x = dY[fine] -> out[coarse].
+int vie_nn_op_test(int op, const int dims[3], int C, const float* x, const float* mask, const float* acc,
+                   float* out, void* hip_stream) {
+  if (!dims || !x || !out || C < 1 || op < 0 || op > 3) return VIE_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (dims[d] < 2 || dims[d] % 2) return VIE_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const Vol fine{dims[0], dims[1], dims[2]};
+  const long Vf = fine.V(), Vc = Vf / 8;
+  const long nin = (op == 0 || op == 3) ? Vf * C : Vc * C;
+  const long nout = (op == 0 || op == 3) ? Vc * C : Vf * C;
+  std::vector<void*> tmp;
+  auto al = [&](size_t b) {
+    void* p = nullptr;
+    if (dmalloc(&p, b)) return (void*)nullptr;
+    tmp.push_back(p);
+    return p;
+  };
+  auto fin = [&](int c) {
+    (void)hipStreamSynchronize(s);
+    for (void* p : tmp) (void)hipFree(p);
+    return c;
+  };
+  bf16_t* xb = (bf16_t*)al(sizeof(bf16_t) * nin);
+  bf16_t* ob = (bf16_t*)al(sizeof(bf16_t) * nout);
+  if (!xb || !ob) return fin(VIE_ENOMEM);
+  hipLaunchKernelGGL(k_f2bf, dim3(gblocks(nin)), dim3(256), 0, s, x, xb, nin);
+  bf16_t* mb = nullptr;
+  if (op == 1 && mask) {
+    if (!(mb = (bf16_t*)al(sizeof(bf16_t) * nout))) return fin(VIE_ENOMEM);
+    hipLaunchKernelGGL(k_f2bf, dim3(gblocks(nout)), dim3(256), 0, s, mask, mb, nout);
+  }
+  if (op == 1 && acc) hipLaunchKernelGGL(k_f2bf, dim3(gblocks(nout)), dim3(256), 0, s, acc, ob, nout);
+  if (op == 0)
+    hipLaunchKernelGGL(k_pool, dim3(gblocks(nout)), dim3(256), 0, s, xb, C, 0, ob, C, 0, C, fine);
+  else if (op == 1)
+    hipLaunchKernelGGL(k_pool_grad, dim3(gblocks(nout)), dim3(256), 0, s, xb, C, 0, ob, C, 0, C, fine, mb, C, 0,
+                       acc ? 1 : 0);
+  else if (op == 2)
+    hipLaunchKernelGGL(k_up, dim3(gblocks(nout)), dim3(256), 0, s, xb, C, 0, ob, C, 0, C, fine);
+  else
+    hipLaunchKernelGGL(k_up_grad, dim3(gblocks(nout)), dim3(256), 0, s, xb, C, 0, ob, C, 0, C, fine);
+  hipLaunchKernelGGL(k_bf2f, dim3(gblocks(nout)), dim3(256), 0, s, ob, out, nout);
+  return fin(hipGetLastError() ? VIE_EDEVICE : VIE_OK);
+}
+
+// Diagnostic Adam step t (t >= 1) on n FP32 device values in place: w, m, v updated
+// with gradient g as the training step does.
+int vie_nn_adam_test(long n, float* w, float* m, float* v, const float* g, int t, float lr, void* hip_stream) {
+  if (n < 1 || !w || !m || !v || !g || t < 1 || !(lr >= 0)) return VIE_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  bf16_t *wb = nullptr, *wtb = nullptr;
+  if (dmalloc(&wb, sizeof(bf16_t) * n)) return VIE_ENOMEM;
+  if (dmalloc(&wtb, sizeof(bf16_t) * n)) {
+    (void)hipFree(wb);
+    return VIE_ENOMEM;
+  }
+  hipLaunchKernelGGL(k_adam, dim3(gblocks(n)), dim3(256), 0, s, w, m, v, g, n, adam_constants(t, lr), 1, 1, (int)n,
+                     wb, wtb, 1);
+  const hipError_t e = hipGetLastError();
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(wb);
+  (void)hipFree(wtb);
+  return e ? VIE_EDEVICE : VIE_OK;
 }
 
 const char* vie_net_last_error(vie_net_t N) { return N ? N->err.c_str() : ""; }

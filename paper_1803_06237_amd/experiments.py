@@ -366,14 +366,16 @@ def strip_reflection_study_em(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: 
 def strip_reflection_study(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: Sequence[int] = DEGREES,
                            lengths: Sequence[float] = STRIP_LENGTHS, precision: int = 1, tol: float = 1e-8,
                            restart: int = 50, inner_restart: int = 20, inner_tol: float = 1e-3,
-                           strip_len: int = inputs.STRIP_LEN, progress=None) -> dict:
+                           strip_len: int = inputs.STRIP_LEN, progress=None, keep: Sequence[float] = ()) -> dict:
     """Section V-A on the strip of Section II-A: for each round-trip reflection and profile
     degree, the guide with every absorber length is solved in one vie_solve_batch call
     (complex-source dipole, electric currents only); R(L) against the longest absorber on
     the centre line, the fitted log-log slope (predicted -2(d+1), Section IV-C) and the
     length that gives R = 1e-8 in silicon wavelengths (the paper's table).  The grid
     depends on L only, so one plan per length serves every (R_rt, d) with its own
-    contrast.  progress, if given, is called with each finished run."""
+    contrast.  progress, if given, is called with each finished run.  For the lengths in
+    keep, each run also returns the guide and the solution (host arrays) under
+    "solutions" {L: (guide, b, x)}, for checks outside the library."""
     import torch
 
     def guide(L, d, r_rt):
@@ -413,6 +415,9 @@ def strip_reflection_study(r_rts: Sequence[float] = (1e-25, 1e-10), degrees: Seq
                        "outer_iters": [i["iters"] for i in infos], "inner_iters": [i["inner_iters"] for i in infos],
                        "R": R, "paper_length_for_1e-8_lambda": PAPER_LENGTH_FOR_1E8.get(r_rt, {}).get(d)}
                 run.update(analyse_reflection(Ls, R, d, r_rt, Lref))
+                if keep:
+                    run["solutions"] = {L: (wg, b.cpu().numpy(), x.cpu().numpy())
+                                        for L, wg, b, x in zip(lengths, wgs, bs, xs) if L in keep}
                 out["runs"][f"{r_rt:g}/{d}"] = run
                 if progress is not None:
                     progress(run)

@@ -100,6 +100,9 @@ def lib() -> ctypes.CDLL:
         L.vie_circulant_apply.argtypes = [vp, vp, vp]
         L.vie_nn_conv_test.argtypes = [ctypes.c_int, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                        ctypes.c_int, vp]
+        L.vie_net_get_grads.argtypes = [vp, vp, ctypes.c_size_t]
+        L.vie_nn_op_test.argtypes = [ctypes.c_int, ip, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.vie_nn_adam_test.argtypes = [ctypes.c_long, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp]
         L.vie_net_last_error.restype = ctypes.c_char_p
         L.vie_net_last_error.argtypes = [vp]
         L.vie_curl_table.argtypes = [ip, ctypes.c_double, vp, ctypes.c_int]
@@ -447,6 +450,13 @@ class Net:
         if lib().vie_net_set_params(self._h, w.ctypes.data, w.size) != VIE_OK:
             raise VieError(VIE_EINVAL, "vie_net_set_params failed")
 
+    def get_grads(self) -> np.ndarray:
+        """FP32 weight gradients of the last train_step (vie_net_get_grads)."""
+        out = np.empty(self.num_params(), dtype=np.float32)
+        if lib().vie_net_get_grads(self._h, out.ctypes.data, out.size) != VIE_OK:
+            raise VieError(VIE_EDEVICE, "vie_net_get_grads failed")
+        return out
+
     def apply(self, r, chi, z=None):
         import torch
         if z is None:
@@ -488,3 +498,29 @@ def conv_test(mode: int, dims, taps: int, cin: int, cout: int, x, w, relu: bool 
     if code != VIE_OK:
         raise VieError(code, "vie_nn_conv_test failed")
     return out
+
+
+def nn_op_test(op: int, fine_dims, C: int, x, mask=None, acc=None):
+    """Diagnostic pooling (0) / pooling gradient (1) / upsampling (2) / upsampling
+    gradient (3) kernel on FP32 device tensors (vie_nn_op_test)."""
+    import torch
+    Vf = int(np.prod(fine_dims))
+    nout = (Vf // 8 if op in (0, 3) else Vf) * C
+    out = torch.empty(nout, dtype=torch.float32, device=x.device)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+    code = lib().vie_nn_op_test(int(op), _grid(fine_dims), int(C), ptr(x), ptr(mask), ptr(acc), ptr(out),
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if code != VIE_OK:
+        raise VieError(code, "vie_nn_op_test failed")
+    return out
+
+
+def nn_adam_test(w, m, v, g, t: int, lr: float):
+    """Diagnostic Adam step t on FP32 device tensors, in place (vie_nn_adam_test)."""
+    import torch
+    code = lib().vie_nn_adam_test(ctypes.c_long(w.numel()), ctypes.c_void_p(w.data_ptr()),
+                                  ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                  ctypes.c_void_p(g.data_ptr()), int(t), ctypes.c_float(lr),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if code != VIE_OK:
+        raise VieError(code, "vie_nn_adam_test failed")

@@ -144,3 +144,166 @@ def test_broken_network_falls_back_to_plain_gmres(use_x0):
     rr = np.linalg.norm(b.ravel() - op(xs.ravel())) / np.linalg.norm(b)
     print(info, rr)
     assert info["status"] == 0 and info["fallback"] == 1 and rr <= 1.01e-8
+
+
+# ---------------------------------------------------------------- non-convolution kernels
+
+def _bf16_equal_frac(got, want):
+    """Fraction of bitwise-equal values and the largest difference in bfloat16 ulps."""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    eq = np.mean(got == want)
+    scale = np.maximum(np.abs(want), 1e-30)
+    ulps = np.max(np.abs(got - want) / scale) / 2.0 ** -8
+    return eq, ulps
+
+
+@pytest.mark.parametrize("dims,C", [((4, 6, 8), 16), ((2, 2, 34), 48), ((6, 4, 2), 20)])
+def test_pool_and_upsample_kernels_match_oracle(dims, C):
+    """Average pooling, nearest upsampling and their gradients (the pooling gradient
+    masked by the ReLU of the pooled tensor and added to the skip gradient) against
+    the oracle's, on bfloat16-rounded inputs: bitwise equal but for rare last-ulp
+    cases where the FP32 sum of eight values is inexact."""
+    vie = _dev()
+    rng = np.random.default_rng(sum(dims) + C)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda()
+    cd = tuple(d // 2 for d in dims)
+    Xf = nn.bf16_round(rng.standard_normal(dims + (C,)))
+    Xc = nn.bf16_round(rng.standard_normal(cd + (C,)))
+    mask = nn.bf16_round(rng.standard_normal(dims + (C,)))
+    acc = nn.bf16_round(rng.standard_normal(dims + (C,)))
+    cases = [
+        (0, Xf, None, None, nn.bf16_round(nn.avgpool2(Xf))),
+        (1, Xc, None, None, nn.bf16_round(nn.avgpool2_grad(Xc))),
+        (1, Xc, mask, acc, nn.bf16_round(acc + np.where(mask > 0, nn.avgpool2_grad(Xc), 0.0))),
+        (2, Xc, None, None, nn.upsample2(Xc)),
+        (3, Xf, None, None, nn.bf16_round(nn.upsample2_grad(Xf))),
+    ]
+    for op, x, m, a, want in cases:
+        got = vie.nn_op_test(op, dims, C, t(x), None if m is None else t(m), None if a is None else t(a))
+        got = got.cpu().numpy().reshape(want.shape)
+        eq, ulps = _bf16_equal_frac(got, want)
+        assert eq >= 0.999 and ulps <= 1.0, (op, eq, ulps)
+
+
+@pytest.mark.parametrize("t", [1, 2, 10, 1000])
+def test_adam_kernel_matches_oracle(t):
+    """One Adam step from arbitrary moments (FP32 on the GPU) against the oracle's FP64
+    step, each to 1e-6 of the size of the terms it sums (the new first moment can cancel):
+    m to 1e-6 (b1 |m| + (1 - b1) |g|), v to 1e-6 v, and the weight change to what those
+    errors allow plus the FP32 rounding of the weight."""
+    vie = _dev()
+    rng = np.random.default_rng(t)
+    n = 10_000
+    w = rng.standard_normal(n).astype(np.float32)
+    g = (rng.standard_normal(n) * 10.0 ** rng.uniform(-4, 1, n)).astype(np.float32)
+    m = (rng.standard_normal(n) * 0.1).astype(np.float32)
+    v = (rng.uniform(0, 1, n) * 0.01).astype(np.float32)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    dw, dm, dv, dg = (torch.from_numpy(a.copy()).cuda() for a in (w, m, v, g))
+    vie.nn_adam_test(dw, dm, dv, dg, t, lr)
+    f = lambda a: a.astype(np.float64)
+    w1, m1, v1 = nn.adam_step(f(w), f(g), f(m), f(v), t, lr, b1, b2, eps)
+    gm, gv, gw = f(dm.cpu().numpy()), f(dv.cpu().numpy()), f(dw.cpu().numpy())
+    mscale = b1 * np.abs(f(m)) + (1 - b1) * np.abs(f(g))
+    assert np.max(np.abs(gm - m1) / mscale) < 1e-6
+    assert np.max(np.abs(gv - v1) / v1) < 1e-6
+    c1, c2 = 1 - b1 ** t, 1 - b2 ** t
+    den = np.sqrt(v1 / c2) + eps
+    allowed = 1e-6 * lr * (mscale / c1) / den + 1e-6 * np.abs(w1 - f(w)) + 2.0 ** -24 * np.abs(w1)
+    assert np.max(np.abs(gw - w1) / allowed) < 1.0
+
+
+# ---------------------------------------------------------------- the whole network
+
+def _integer_network(net, seed, n, count):
+    """Weights in {-1, 0, 1} (sparse, mostly +1), residuals of modulus one (s = 1) and
+    contrasts in {0, 1}: every sum of the forward and backward passes is a short sum of
+    dyadic numbers, exact in FP32 and FP64 alike, so both sides round to bfloat16
+    identically.  Targets put out - (target - r) s in {-1, 0, 1}."""
+    rng = np.random.default_rng(seed)
+    W = []
+    for i, (t, ci, co, cr) in enumerate(nn.LAYERS):
+        p = 4.0 / (t * cr)
+        u = rng.uniform(0, 1, (t, co, ci))
+        w = np.where(u < 0.8 * p, 1.0, np.where(u < p, -1.0, 0.0))
+        w[:, :, cr:] = 0.0
+        if i == 14:
+            w[:, 6:, :] = 0.0
+        W.append(w)
+    net.set_params(np.concatenate([w.ravel() for w in W]).astype(np.float32))
+    samples = []
+    for _ in range(count):
+        sg = np.where(rng.uniform(0, 1, (3,) + n) < 0.5, 1.0, -1.0)
+        r = np.where(rng.uniform(0, 1, (3,) + n) < 0.5, sg, 1j * sg)
+        chi = (rng.uniform(0, 1, n) < 0.5).astype(complex)
+        X0, s = nn.pack_input(r, chi)
+        assert s == 1.0
+        out = nn.unet_forward(W, X0)["out"]
+        want = out[..., :6] + rng.integers(-1, 2, n + (6,))
+        tgt = np.array(r)
+        for c in range(3):
+            tgt[c] = r[c] + want[..., 2 * c] + 1j * want[..., 2 * c + 1]
+        samples.append((r, chi, tgt))
+    return W, samples
+
+
+def test_network_apply_is_bit_exact_on_the_integer_case():
+    vie = _dev()
+    n = (8, 8, 16)
+    net = vie.Net(n, seed=0)
+    W, samples = _integer_network(net, 11, n, 2)
+    for r, chi, _ in samples:
+        want = nn.unet_apply(W, r, chi)
+        assert np.abs(want - r).max() > 0            # the network is not dead
+        got = net.apply(torch.from_numpy(r).cuda(), torch.from_numpy(chi).cuda()).cpu().numpy()
+        assert np.array_equal(got, want)
+
+
+def test_network_apply_matches_oracle_with_he_weights():
+    """The network's own initial weights: FP32 accumulation against the oracle's FP64
+    sums changes some bfloat16 roundings of stored activations, and those propagate;
+    emulating FP32 accumulation in the oracle composition on random weights moves the
+    correction by up to 2.4e-3 (rel-L2), hence the 1e-2 bound."""
+    vie = _dev()
+    n = (8, 8, 16)
+    net = vie.Net(n, seed=7)
+    W = nn.split_params(net.get_params())
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)
+    chi = (rng.uniform(0, 1, n) < 0.5) * (0.8 + 0.05j)
+    want = nn.unet_apply(W, r, chi)
+    got = net.apply(torch.from_numpy(r).cuda(), torch.from_numpy(chi).cuda()).cpu().numpy()
+    err = np.linalg.norm(got - want) / np.linalg.norm(want - r)
+    print("he-weights correction rel-L2", err)
+    assert err < 1e-2
+
+
+def test_train_step_loss_and_gradients_match_oracle():
+    """One training step over two samples on the integer case: the loss equals the
+    oracle's, the weight gradients (summed over the samples) match to 1e-5 of each
+    layer's largest entry (FP32 rounding of the split-K sums), and the Adam step moves
+    each weight by lr sign(g) where the oracle's gradient is clearly non-zero and
+    leaves it where the gradient is exactly zero."""
+    vie = _dev()
+    n = (8, 8, 16)
+    net = vie.Net(n, seed=0)
+    W, samples = _integer_network(net, 14, n, 2)
+    w0 = net.get_params()
+    loss_o, grads_o = nn.unet_loss_grads(W, samples)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    lr = 1e-3
+    loss = net.train_step([dev(r) for r, _, _ in samples], [dev(c) for _, c, _ in samples],
+                          [dev(t) for _, _, t in samples], lr=lr)
+    assert abs(loss - loss_o) <= 1e-12 * loss_o, (loss, loss_o)
+    g = nn.split_params(net.get_grads())
+    for i, (a, b) in enumerate(zip(g, grads_o)):
+        scale = np.abs(b).max()
+        assert scale > 0, i
+        assert np.abs(a - b).max() <= 1e-5 * scale, (i, np.abs(a - b).max() / scale)
+    w1 = net.get_params()
+    go = np.concatenate([x.ravel() for x in grads_o])
+    big = np.abs(go) > 1e-3 * np.abs(go).max()
+    want = w0[big] - lr * go[big] / (np.abs(go[big]) + 1e-8)
+    assert np.allclose(w1[big], want, rtol=0, atol=1e-5 * lr + 2.0 ** -24)
+    assert np.array_equal(w1[go == 0], w0[go == 0])

@@ -194,3 +194,10 @@ def test_table_entries_match_pointwise_evaluation():
     assert green.entry(T, 0, 1, (-1, 2, 0)) == -T[1, 1, 2, 0]
     assert green.entry(T, 2, 0, (1, 0, -3)) == -T[2, 1, 0, 3]
     assert green.entry(T, 1, 1, (-2, -3, -4)) == T[3, 2, 3, 4]
+
+
+def test_table_in_worker_processes_equals_the_serial_table():
+    for n, kap in (((5, 2, 7), 0.3), ((4, 3, 3), 1.1)):
+        a = green.green_table(n, kap)
+        b = green.green_table(n, kap, workers=3)
+        assert np.abs(a - b).max() <= 1e-15 * np.abs(a).max()

@@ -127,3 +127,57 @@ def test_adam_two_gradients_closed_form():
     v2 = (b2 * (1 - b2) * g1 ** 2 + (1 - b2) * g2 ** 2) / (1 - b2 ** 2)
     want = w0 - lr * g1 / (np.abs(g1) + eps) - lr * m2 / (np.sqrt(v2) + eps)
     assert np.allclose(w2, want, rtol=0, atol=1e-13)
+
+
+def _unet_case(seed, n=(8, 8, 8)):
+    rng = np.random.default_rng(seed)
+    flat = np.concatenate([rng.standard_normal(t * ci * co) * np.sqrt(2.0 / (t * cr))
+                           for (t, ci, co, cr) in nn.LAYERS])
+    W = nn.split_params(flat)
+    r = rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)
+    chi = (rng.uniform(0, 1, n) > 0.4) * (0.8 + 0.05j)
+    tgt = r + 0.5 * (rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n))
+    return W, r, chi, tgt
+
+
+def test_unet_gradient_matches_central_differences():
+    """The composed backward pass equals the derivative of the composed loss (exact FP64
+    mode, no bfloat16 rounding) for weights of every kind of layer: the first and last
+    convolutions, encoder layers whose outputs feed both a skip and a pooling path,
+    the bottom, a decoder layer on a concatenation and the 1x1x1 output layer."""
+    W, r, chi, tgt = _unet_case(3)
+    samples = [(r, chi, tgt)]
+    loss, grads = nn.unet_loss_grads(W, samples, bf16=False)
+    assert abs(loss - nn.unet_loss(W, samples, bf16=False)) < 1e-12 * loss
+    rng = np.random.default_rng(4)
+    eps = 1e-5
+    for layer in (0, 1, 3, 5, 7, 8, 10, 12, 14):
+        gmax = np.abs(grads[layer]).max()
+        assert gmax > 0, layer
+        # the largest-gradient entry and two random ones
+        picks = [np.unravel_index(np.argmax(np.abs(grads[layer])), W[layer].shape)]
+        picks += [tuple(rng.integers(0, s) for s in W[layer].shape) for _ in range(2)]
+        for idx in picks:
+            Wp = [w.copy() for w in W]
+            Wm = [w.copy() for w in W]
+            Wp[layer][idx] += eps
+            Wm[layer][idx] -= eps
+            fd = (nn.unet_loss(Wp, samples, bf16=False) - nn.unet_loss(Wm, samples, bf16=False)) / (2 * eps)
+            assert abs(fd - grads[layer][idx]) <= 1e-5 * gmax, (layer, idx, fd, grads[layer][idx])
+
+
+def test_unet_with_zero_weights_is_the_identity_and_rounding_is_exact_on_integers():
+    W, r, chi, _ = _unet_case(5)
+    zero = [np.zeros_like(w) for w in W]
+    assert np.array_equal(nn.unet_apply(zero, r, chi), r)
+    # integer weights and inputs: the rounded and the exact composition agree while
+    # every stored value is representable in bfloat16
+    rng = np.random.default_rng(6)
+    Wi = [np.where(rng.uniform(0, 1, w.shape) < 1.0 / w[0].size, 1.0, 0.0) for w in W]
+    ri = np.where(rng.uniform(0, 1, r.shape) < 0.5, 1.0, -1.0).astype(complex)
+    ci = (chi != 0).astype(float)
+    a = nn.unet_forward(Wi, nn.pack_input(ri, ci, True)[0], True)
+    b = nn.unet_forward(Wi, nn.pack_input(ri, ci, False)[0], False)
+    for k in a:
+        if np.abs(b[k]).max() < 256:
+            assert np.array_equal(a[k], b[k]), k
