@@ -254,35 +254,33 @@ def cpu_tuned_baseline(n, seconds_budget=10.0):
                       f"(products and contrast in numpy), synthetic spectrum of the full circulant shape; {el:.1f} s"}
 
 
-def learned_comparison(n_geom: int = 32, epochs: int = 4):
-    """Train the network on seeded rough guides (32x32x256) and compare time to 1e-8 of FP64
-    GMRES(50), mixed FGMRES and learned FGMRES on two unseen guides."""
+def learned_comparison(n_train: int = 96, epochs: int = 3, n_test: int = 4):
+    """The learned preconditioner as a correction of the block circulant on seeded rough
+    guides (32x32x256): n_train solver-generated pairs (training seeds 0..), a few
+    epochs, then time to 1e-8 on unseen guides (test seeds 10000..) for FP64 GMRES(50),
+    mixed FGMRES, circulant FGMRES and the network correcting the circulant.  A reduced
+    version of the study `python -m paper_1803_06237_amd.experiments learned` (2000
+    pairs, 100 test guides)."""
     import numpy as np
-    import torch
 
-    from paper_1803_06237_amd import inputs, learned
+    from paper_1803_06237_amd import learned
     t0 = time.perf_counter()
-    tr = learned.Trainer((32, 32, 256), 0.025, seed=0)
-    for s in range(n_geom):
-        tr.add_geometry(inputs.rough_strip(s), n_operator_pairs=8)
-    losses = tr.train(epochs=epochs, lr=2e-3, batch=4, lr_decay=0.6)
+    st = learned.CirculantCorrectionStudy(seed=0)
+    gen = st.generate(range(n_train))
+    losses = st.train(epochs)
     train_s = time.perf_counter() - t0
-    res = {}
-    for seed in (10000, 10001):
-        wg = inputs.rough_strip(seed)
-        tr.plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
-        b = tr.plan.rhs(torch.from_numpy(inputs.transverse_dipole_field(wg)).cuda())
-        cmp_ = learned.compare_tiers(tr.plan, tr.net, b)
-        res[str(seed)] = {k: {"seconds": round(v["wall"], 4), "outer_iters": v["iters"],
-                              "inner_or_net_applications": v["inner_iters"], "fallback": v["fallback"],
-                              "rel_res_fp64": v["rel_res_fp64"]} for k, v in cmp_.items()}
-    sp = [v["fp64"]["seconds"] / v["learned"]["seconds"] for v in res.values()]
-    spm = [v["fp64"]["seconds"] / v["mixed"]["seconds"] for v in res.values()]
+    ev = st.evaluate(range(10000, 10000 + n_test))
+    m = ev["mean"]
     return {"workload": "32x32x256 rough-sidewall guides (sigma 1 voxel, corr 8), quadratic 1 um absorbers; "
-                        f"trained on {n_geom} geometries x 8 operator pairs, {epochs} epochs",
-            "train_seconds": round(train_s, 2), "loss_first": round(losses[0], 4), "loss_last": round(losses[-1], 4),
-            "test": res, "learned_speedup_vs_fp64": round(float(np.mean(sp)), 3),
-            "mixed_speedup_vs_fp64": round(float(np.mean(spm)), 3)}
+                        f"network correcting the block circulant, {gen['pairs']} solver-generated pairs, "
+                        f"{epochs} epochs, {n_test} test guides",
+            "generate_and_train_seconds": round(train_s, 2), "losses": [round(x, 4) for x in losses],
+            "test_mean": m,
+            "learned_circulant_speedup_vs_fp64": round(m["fp64"]["seconds_mean"] /
+                                                       m["learned_circulant"]["seconds_mean"], 3),
+            "learned_circulant_speedup_vs_circulant": round(m["circulant"]["seconds_mean"] /
+                                                            m["learned_circulant"]["seconds_mean"], 3),
+            "mixed_speedup_vs_fp64": round(m["fp64"]["seconds_mean"] / m["mixed"]["seconds_mean"], 3)}
 
 
 def main():

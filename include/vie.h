@@ -133,7 +133,10 @@ typedef struct {
   int precision;      /* 0: FP64 GMRES; 1: mixed (FP32 inner GMRES, FP64 outer FGMRES);
                          2: learned (FP64 FGMRES with the attached network, plain GMRES fallback);
                          3: FP64 FGMRES right-preconditioned by the block circulant of
-                            vie_circulant_build */
+                            vie_circulant_build;
+                         4: FP64 FGMRES preconditioned by the attached network correcting
+                            the block circulant, z = W^{-1} v + net(v, W^{-1} v), x0 from
+                            the same map of b; the circulant FGMRES is its fallback */
   int inner_restart;  /* mixed tier: inner GMRES dimension; <= 0 -> 20 */
   double inner_tol;   /* mixed tier: inner relative tolerance; <= 0 -> 1e-4 */
   int use_graph;      /* vie_solve_batch: 1 = capture one restart cycle as a HIP graph and replay it */
@@ -295,8 +298,10 @@ int vie_profile_matvec(vie_plan_t plan, int precision, const void* x, void* y, i
  *
  * Architecture (levels 0..3 at grid / 2^l, voxel v = (i1 n2 + i2) n3 + i3 at
  * level 0, channels last, every channel count padded to a multiple of 16):
- *   input X0 (16 ch): Re, Im of r_x, r_y, r_z times s, Re, Im of chi, then zeros;
- *   L0  3x3x3  16 -> 16  (8 real inputs)   E1a = relu(L0 X0)
+ *   input X0 (16 ch): Re, Im of r_x, r_y, r_z times s, Re, Im of chi, Re, Im of
+ *     w_x, w_y, w_z times s (the base vector of vie_net_apply_base; zeros
+ *     without one), two zeros;
+ *   L0  3x3x3  16 -> 16  (14 real inputs)  E1a = relu(L0 X0)
  *   L1  3x3x3  16 -> 16                     E1b = relu(L1 E1a)
  *   P1 = avgpool2(E1b);  L2 16 -> 32: E2a;  L3 32 -> 32: E2b
  *   P2 = avgpool2(E2b);  L4 32 -> 48: E3a;  L5 48 -> 48: E3b
@@ -310,7 +315,7 @@ int vie_profile_matvec(vie_plan_t plan, int precision, const void* x, void* y, i
  * nearest even; the convolutions use bfloat16 weights, the master copies are
  * FP32).  Weights of layer l are [taps][cout][cin] with tap t = (dz+1) 9 +
  * (dy+1) 3 + (dx+1) shifting along (i1, i2, i3); vie_net_get_params lists
- * L0..L14 in order.  z_c = r_c + (out[2c] + i out[2c+1]) / s.
+ * L0..L14 in order.  z_c = base_c + (out[2c] + i out[2c+1]) / s, base = w or r.
  *
  * vie_net_create: grid dims must be multiples of 8 (three poolings).  Weights
  *   are He-initialised from `seed` (deterministic).  hip_stream as in vie_plan.
@@ -338,6 +343,16 @@ int vie_net_set_params(vie_net_t net, const float* host, size_t count);
 int vie_net_apply(vie_net_t net, const vie_c128* r, const vie_c128* chi, vie_c128* z);
 int vie_net_train_step(vie_net_t net, int count, const vie_c128* const* r, const vie_c128* const* chi,
                        const vie_c128* const* target, float lr, double* loss);
+/*
+ * The same with a base vector w (device, 3N values; NULL = r): the network also sees
+ * w and predicts the correction A^{-1} r - w, so z = w + net(r s, chi, w s) / s.  With
+ * w = W^{-1} r from the block-circulant preconditioner (vie_circulant_apply) the
+ * network corrects that preconditioner (vie_solve precision 4).  train_step_base:
+ * w is an array of count device pointers or NULL.
+ */
+int vie_net_apply_base(vie_net_t net, const vie_c128* r, const vie_c128* w, const vie_c128* chi, vie_c128* z);
+int vie_net_train_step_base(vie_net_t net, int count, const vie_c128* const* r, const vie_c128* const* w,
+                            const vie_c128* const* chi, const vie_c128* const* target, float lr, double* loss);
 int vie_set_preconditioner(vie_plan_t plan, vie_net_t net);
 int vie_nn_conv_test(int mode, const int dims[3], int taps, int cin, int cout, const float* x, const float* w,
                      float* out, int relu, void* hip_stream);

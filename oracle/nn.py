@@ -116,7 +116,7 @@ def adam_step(w, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 # ---------------------------------------------------------------------------
 
 # (taps, cin, cout, cin_real) of L0..L14, channel counts padded to multiples of 16
-LAYERS = [(27, 16, 16, 8), (27, 16, 16, 16), (27, 16, 32, 16), (27, 32, 32, 32), (27, 32, 48, 32),
+LAYERS = [(27, 16, 16, 14), (27, 16, 16, 16), (27, 16, 32, 16), (27, 32, 32, 32), (27, 32, 48, 32),
           (27, 48, 48, 48), (27, 48, 64, 48), (27, 64, 64, 64), (27, 112, 48, 112), (27, 48, 48, 48),
           (27, 80, 32, 80), (27, 32, 32, 32), (27, 48, 16, 48), (27, 16, 16, 16), (1, 16, 16, 16)]
 
@@ -132,8 +132,9 @@ def split_params(flat: np.ndarray) -> list:
     return out
 
 
-def pack_input(r: np.ndarray, chi: np.ndarray, bf16: bool = True):
-    """X0 (n1, n2, n3, 16): Re, Im of r_x, r_y, r_z times s, Re, Im of chi, zeros,
+def pack_input(r: np.ndarray, chi: np.ndarray, bf16: bool = True, w: np.ndarray | None = None):
+    """X0 (n1, n2, n3, 16): Re, Im of r_x, r_y, r_z times s, Re, Im of chi, then Re, Im
+    of w_x, w_y, w_z times s when a base vector w is given (zeros otherwise), zeros;
     rounded to bfloat16 (bf16 = True); s = sqrt(3N / ||r||^2)."""
     n = r.shape[1:]
     N = int(np.prod(n))
@@ -142,6 +143,9 @@ def pack_input(r: np.ndarray, chi: np.ndarray, bf16: bool = True):
     for c in range(3):
         X[..., 2 * c] = (r[c] * s).real
         X[..., 2 * c + 1] = (r[c] * s).imag
+        if w is not None:
+            X[..., 8 + 2 * c] = (w[c] * s).real
+            X[..., 9 + 2 * c] = (w[c] * s).imag
     X[..., 6] = chi.real
     X[..., 7] = chi.imag
     return (bf16_round(X) if bf16 else X), s
@@ -186,15 +190,17 @@ def unpack_output(r: np.ndarray, out: np.ndarray, s: float) -> np.ndarray:
     return z
 
 
-def unet_apply(W: list, r: np.ndarray, chi: np.ndarray, bf16: bool = True) -> np.ndarray:
-    """The preconditioner's action: the network's correction added to r."""
-    X0, s = pack_input(r, chi, bf16)
-    return unpack_output(r, unet_forward(W, X0, bf16)["out"], s)
+def unet_apply(W: list, r: np.ndarray, chi: np.ndarray, bf16: bool = True, w: np.ndarray | None = None) -> np.ndarray:
+    """The preconditioner's action: the network's correction added to the base vector
+    (w when given, else r)."""
+    X0, s = pack_input(r, chi, bf16, w)
+    return unpack_output(r if w is None else w, unet_forward(W, X0, bf16)["out"], s)
 
 
 def unet_loss_grads(W: list, samples, bf16: bool = True) -> tuple:
-    """Mean squared error of out[0:6] against (target - r) s over the six channels and
-    all voxels, averaged over the samples (r, chi, target), and its gradient with
+    """Mean squared error of out[0:6] against (target - base) s over the six channels and
+    all voxels, averaged over the samples (r, chi, target[, base]; base = r when
+    absent), and its gradient with
     respect to every layer's weights: backpropagation through the composition of
     unet_forward (chain rule layer by layer: weight gradient, input gradient masked
     by the ReLU of the layer's input, adjoints of upsampling and pooling, the skip
@@ -204,14 +210,17 @@ def unet_loss_grads(W: list, samples, bf16: bool = True) -> tuple:
     grads = [np.zeros_like(w) for w in W]
     total = 0.0
     count = len(samples)
-    for r, chi, target in samples:
-        X0, s = pack_input(r, chi, bf16)
+    for smp in samples:
+        r, chi, target = smp[:3]
+        base = smp[3] if len(smp) > 3 else None
+        X0, s = pack_input(r, chi, bf16, base)
         a = unet_forward(W, X0, bf16)
         n = r.shape[1:]
         V = int(np.prod(n))
+        ref = r if base is None else base
         want = np.zeros(n + (16,))
         for c in range(3):
-            d = (target[c] - r[c]) * s
+            d = (target[c] - ref[c]) * s
             want[..., 2 * c] = d.real
             want[..., 2 * c + 1] = d.imag
         diff = np.zeros(n + (16,))
@@ -253,11 +262,14 @@ def unet_loss_grads(W: list, samples, bf16: bool = True) -> tuple:
 def unet_loss(W: list, samples, bf16: bool = True) -> float:
     """The loss of unet_loss_grads alone (forward passes only)."""
     total = 0.0
-    for r, chi, target in samples:
-        X0, s = pack_input(r, chi, bf16)
+    for smp in samples:
+        r, chi, target = smp[:3]
+        base = smp[3] if len(smp) > 3 else None
+        X0, s = pack_input(r, chi, bf16, base)
         out = unet_forward(W, X0, bf16)["out"]
         V = int(np.prod(r.shape[1:]))
+        ref = r if base is None else base
         for c in range(3):
-            d = (target[c] - r[c]) * s
+            d = (target[c] - ref[c]) * s
             total += (np.sum((out[..., 2 * c] - d.real) ** 2) + np.sum((out[..., 2 * c + 1] - d.imag) ** 2)) / (6.0 * V)
     return total / len(samples)

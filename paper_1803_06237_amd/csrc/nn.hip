@@ -47,61 +47,129 @@ struct Vol {
 
 // ------------------------------------------------------------------ convolution
 // Y[v, o] = act(sum_t sum_i W[t][o][i] X[v + t][i]); tap t = (dz+1)*9 + (dy+1)*3 + (dx+1).
-// grid.x: 64-voxel tiles, grid.y: groups of 4 output-channel tiles of 16.
-template <int TAPS>
-__global__ __launch_bounds__(256) void k_conv(const bf16_t* __restrict__ X, int xcs, int xco, int Cin,
-                                              const bf16_t* __restrict__ Wt, int Cout, bf16_t* __restrict__ Y,
-                                              int ycs, int yco, float* __restrict__ Yf, Vol vol, int relu,
-                                              const bf16_t* __restrict__ mask, int mcs, int mco) {
+// LDS-staged implicit GEMM on v_mfma_f32_16x16x32_bf16.  A workgroup of four waves
+// computes a tile of 2 (D) x 4 (H) x 32 (W) output voxels for up to 64 output
+// channels (grid.y picks the group of four 16-channel N-tiles); wave w takes the
+// two rows (z0 + w / 2, y0 + 2 (w % 2) + {0, 1}), i.e. four 16-voxel M-tiles.  The
+// input is consumed in chunks of 16 channels: the chunk's halo tile (4 x 6 x 34
+// voxels) and its weights for all taps and the group's output channels are staged
+// in LDS once and read by every K-step.  One MFMA K-step covers two taps of the
+// chunk (K = 2 x 16): lanes 0-31 take tap t, lanes 32-63 tap t + 1 (the 28th tap is
+// zero).  Halo layout [half][voxel][8 channels] (half = channels 0-7 or 8-15), so
+// the 16 lanes of one fragment row read 256 contiguous bytes; weight layout
+// [tap pair][N-tile][lane] of 16-byte B fragments, so a wave reads 1 KiB contiguous.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+constexpr int kCtx = 32, kCty = 4, kCtz = 2;             // output tile (W, H, D)
+constexpr int kHx = kCtx + 2, kHy = kCty + 2, kHz = kCtz + 2;
+constexpr int kHvox = kHx * kHy * kHz;                   // 816 halo voxels
+constexpr int kPairs = 14;                               // tap pairs of a 3 x 3 x 3 kernel
+
+// dynamic LDS bytes of k_conv2 for nt N-tiles
+static inline size_t conv2_lds(int taps, int nt) {
+  return (size_t)2 * kHvox * 8 * 2 + (size_t)(taps == 1 ? 1 : kPairs) * nt * 64 * 16;
+}
+
+template <int TAPS, int NT>
+__global__ __launch_bounds__(256) void k_conv2(const bf16_t* __restrict__ X, int xcs, int xco, int Cin,
+                                               const bf16_t* __restrict__ Wt, int Cout, bf16_t* __restrict__ Y,
+                                               int ycs, int yco, float* __restrict__ Yf, Vol vol, int relu,
+                                               const bf16_t* __restrict__ mask, int mcs, int mco, int g0) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char conv_smem[];
+  bf16_t* tile = reinterpret_cast<bf16_t*>(conv_smem);
+  u4v* wfrag = reinterpret_cast<u4v*>(conv_smem + (size_t)2 * kHvox * 8 * 2);
+  constexpr int NPAIR = TAPS == 1 ? 1 : kPairs;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long V = vol.V();
-  const long vbase = (long)blockIdx.x * 64 + wave * 16;
-  const int m = lane & 15, kq = lane >> 4;
-  const long v = vbase + m;
-  const int nt0 = blockIdx.y * 4;
-  const int nt = min(4, Cout / 16 - nt0);
-  int z = 0, y = 0, x = 0;
-  if (v < V) {
-    x = (int)(v % vol.W);
-    y = (int)((v / vol.W) % vol.H);
-    z = (int)(v / ((long)vol.W * vol.H));
-  }
-  f4v acc[4];
+  const int ntx = (vol.W + kCtx - 1) / kCtx, nty = (vol.H + kCty - 1) / kCty;
+  int b = blockIdx.x;
+  const int tx = b % ntx;
+  b /= ntx;
+  const int ty = b % nty;
+  const int tz = b / nty;
+  const int x0 = tx * kCtx, y0 = ty * kCty, z0 = tz * kCtz;
+  const int nt0 = (g0 + blockIdx.y) * 4;       // first N-tile of this workgroup's group
+  constexpr int nt = NT;
+  const int m = lane & 15, kq = lane >> 4;     // fragment row / K-quarter
+  const int half = kq & 1, second = kq >> 1;   // channel half, which tap of the pair
+  const int wz = wave >> 1, wy = 2 * (wave & 1);
+  // this lane's halo row for tap offset 0 (the halo corner) of its first M-tile
+  const int lds_lane = (half * kHvox + (wz * kHy + wy) * kHx + m) * 8;
+  f4v acc[4][NT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
-  for (int tap = 0; tap < TAPS; ++tap) {
-    const int dz = TAPS == 1 ? 0 : tap / 9 - 1, dy = TAPS == 1 ? 0 : (tap / 3) % 3 - 1,
-              dx = TAPS == 1 ? 0 : tap % 3 - 1;
-    const int zz = z + dz, yy = y + dy, xx = x + dx;
-    const bool inb = v < V && zz >= 0 && zz < vol.D && yy >= 0 && yy < vol.H && xx >= 0 && xx < vol.W;
-    const long nv = ((long)zz * vol.H + yy) * vol.W + xx;
-    const bf16_t* xp = X + (inb ? nv : 0) * xcs + xco + 4 * kq;
-    const bf16_t* wp = Wt + ((long)tap * Cout + nt0 * 16 + m) * Cin + 4 * kq;
-    for (int c0 = 0; c0 < Cin; c0 += 16) {
-      s4v a = inb ? *reinterpret_cast<const s4v*>(xp + c0) : s4v{0, 0, 0, 0};
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t < nt) {
-          const s4v b = *reinterpret_cast<const s4v*>(wp + (long)t * 16 * Cin + c0);
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-        }
+    for (int t = 0; t < NT; ++t) acc[i][t] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int nchunk = Cin / 16;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    __syncthreads();
+    // halo tile: one 16-byte (8-channel) piece per step
+    for (int e = threadIdx.x; e < 2 * kHvox; e += 256) {
+      const int hv = e >> 1, hf = e & 1;
+      const int hx = hv % kHx, hy = (hv / kHx) % kHy, hz = hv / (kHx * kHy);
+      const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+      u4v val = u4v{0u, 0u, 0u, 0u};
+      if (xx >= 0 && xx < vol.W && yy >= 0 && yy < vol.H && zz >= 0 && zz < vol.D) {
+        const long v = ((long)zz * vol.H + yy) * vol.W + xx;
+        val = *reinterpret_cast<const u4v*>(X + v * xcs + xco + ch * 16 + hf * 8);
+      }
+      *reinterpret_cast<u4v*>(tile + ((long)hf * kHvox + hv) * 8) = val;
+    }
+    // B fragments of the chunk: entry (pair, N-tile, lane) = W[tap][co][ci .. ci + 7]
+    for (int e = threadIdx.x; e < NPAIR * NT * 64; e += 256) {
+      const int l = e & 63, t = (e >> 6) % NT, tp = (e >> 6) / NT;
+      const int lm = l & 15, lq = l >> 4;
+      const int tap = TAPS == 1 ? 0 : 2 * tp + (lq >> 1);
+      u4v val = u4v{0u, 0u, 0u, 0u};
+      if (TAPS == 1 ? (lq >> 1) == 0 : tap < 27)
+        val = *reinterpret_cast<const u4v*>(Wt + ((long)tap * Cout + (nt0 + t) * 16 + lm) * Cin + ch * 16 +
+                                            (lq & 1) * 8);
+      wfrag[e] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tp = 0; tp < NPAIR; ++tp) {
+      constexpr int kStep = kHx * kHy;
+      const int t0 = 2 * tp, t1 = 2 * tp + 1;
+      const int off0 = TAPS == 1 ? kStep + kHx + 1 : (t0 / 9) * kStep + ((t0 / 3) % 3) * kHx + t0 % 3;
+      // the 28th tap (t1 = 27) does not exist: it reads tap t0's (finite) halo values,
+      // and its B fragment is zero
+      const int off1 = (TAPS == 1 || t1 >= 27) ? off0 : (t1 / 9) * kStep + ((t1 / 3) % 3) * kHx + t1 % 3;
+      const int off = second ? off1 : off0;
+      bf8v bfr[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bfr[t] = __builtin_bit_cast(bf8v, wfrag[(tp * NT + t) * 64 + lane]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // M-tile i: row wy + (i >> 1), voxels 16 (i & 1) .. + 15
+        const int ao = lds_lane + (off + (i >> 1) * kHx + 16 * (i & 1)) * 8;
+        const bf8v a = __builtin_bit_cast(bf8v, *reinterpret_cast<const u4v*>(tile + ao));
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[t], acc[i][t], 0, 0, 0);
       }
     }
   }
-  // D[row = 4 kq + r][col = m]: voxel vbase + 4 kq + r, channel (nt0 + t) * 16 + m
+  // D[row = 4 kq + r][col = m]: voxel 16 (i & 1) + 4 kq + r of row (z0 + wz, y0 + wy + (i >> 1))
+  const int zz = z0 + wz;
+  if (zz >= vol.D) return;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (t >= nt) continue;
-    const int n = (nt0 + t) * 16 + m;
+  for (int i = 0; i < 4; ++i) {
+    const int yy = y0 + wy + (i >> 1);
+    if (yy >= vol.H) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long vo = vbase + 4 * kq + r;
-      if (vo >= V) continue;
-      float val = acc[t][r];
-      if (relu) val = fmaxf(val, 0.f);
-      if (mask) val = bf2f(mask[vo * mcs + mco + n]) > 0.f ? val : 0.f;
-      if (Y) Y[vo * ycs + yco + n] = f2bf(val);
-      if (Yf) Yf[vo * Cout + n] = val;
+    for (int t = 0; t < NT; ++t) {
+      const int n = (nt0 + t) * 16 + m;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int xx = x0 + 16 * (i & 1) + 4 * kq + r;
+        if (xx >= vol.W) continue;
+        const long vo = ((long)zz * vol.H + yy) * vol.W + xx;
+        float val = acc[i][t][r];
+        if (relu) val = fmaxf(val, 0.f);
+        if (mask) val = bf2f(mask[vo * mcs + mco + n]) > 0.f ? val : 0.f;
+        if (Y) Y[vo * ycs + yco + n] = f2bf(val);
+        if (Yf) Yf[vo * Cout + n] = val;
+      }
     }
   }
 }
@@ -223,9 +291,10 @@ __global__ void k_up_grad(const bf16_t* __restrict__ dY, int ycs, int yco, bf16_
 }
 
 // ------------------------------------------------------------------ data in / out, loss, Adam
-// X0[v][0..15] = (Re/Im r_x, r_y, r_z) * s, Re/Im chi, zeros;  s = sqrt(3N / ||r||^2)
-__global__ void k_pack(const double2* __restrict__ r, const double2* __restrict__ chi, const double2* __restrict__ sumsq,
-                       long N, bf16_t* __restrict__ X0) {
+// X0[v][0..15] = (Re/Im r_x, r_y, r_z) * s, Re/Im chi, (Re/Im w_x, w_y, w_z) * s or zeros
+// when w is null, zeros;  s = sqrt(3N / ||r||^2)
+__global__ void k_pack(const double2* __restrict__ r, const double2* __restrict__ w, const double2* __restrict__ chi,
+                       const double2* __restrict__ sumsq, long N, bf16_t* __restrict__ X0) {
   const double s = sumsq->x > 0 ? sqrt(3.0 * (double)N / sumsq->x) : 0.0;
   for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x) {
     bf16_t* o = X0 + v * 16;
@@ -239,27 +308,34 @@ __global__ void k_pack(const double2* __restrict__ r, const double2* __restrict_
     o[6] = f2bf((float)k.x);
     o[7] = f2bf((float)k.y);
 #pragma unroll
-    for (int c = 8; c < 16; ++c) o[c] = 0;
+    for (int c = 0; c < 3; ++c) {
+      const double2 a = w ? w[(long)c * N + v] : double2{0.0, 0.0};
+      o[8 + 2 * c] = f2bf((float)(a.x * s));
+      o[9 + 2 * c] = f2bf((float)(a.y * s));
+    }
+    o[14] = 0;
+    o[15] = 0;
   }
 }
 
-// z[c][v] = r[c][v] + (out[v][2c] + i out[v][2c+1]) / s: the network predicts the
-// correction A^{-1} r - r, so an untrained (small) network is the identity
+// z[c][v] = base[c][v] + (out[v][2c] + i out[v][2c+1]) / s with base = w, or r when w
+// is null: the network predicts the correction A^{-1} r - base, so an untrained
+// (small) network leaves the base preconditioner (or the identity)
 __global__ void k_unpack(const float* __restrict__ out, const double2* __restrict__ sumsq, long N,
-                         const double2* __restrict__ r, double2* __restrict__ z) {
+                         const double2* __restrict__ base, double2* __restrict__ z) {
   const double s = sumsq->x > 0 ? sqrt(3.0 * (double)N / sumsq->x) : 0.0;
   const double is = s > 0 ? 1.0 / s : 0.0;
   for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double2 rv = r[(long)c * N + v];
+      const double2 rv = base[(long)c * N + v];
       z[(long)c * N + v] = double2{rv.x + out[v * 16 + 2 * c] * is, rv.y + out[v * 16 + 2 * c + 1] * is};
     }
 }
 
-// mean squared error of out against (target - r) * s over 6 channels; dOut = d(loss)/d(out)
+// mean squared error of out against (target - base) * s over 6 channels; dOut = d(loss)/d(out)
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, const double2* __restrict__ target,
-                                              const double2* __restrict__ r, const double2* __restrict__ sumsq,
+                                              const double2* __restrict__ base, const double2* __restrict__ sumsq,
                                               long N, bf16_t* __restrict__ dOut, float gscale,
                                               double* __restrict__ partial) {
   __shared__ double red[256];
@@ -268,7 +344,7 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, con
   for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double2 t = target[(long)c * N + v], rv = r[(long)c * N + v];
+      const double2 t = target[(long)c * N + v], rv = base[(long)c * N + v];
       const float d0 = out[v * 16 + 2 * c] - (float)((t.x - rv.x) * s);
       const float d1 = out[v * 16 + 2 * c + 1] - (float)((t.y - rv.y) * s);
       acc += (double)d0 * d0 + (double)d1 * d1;
@@ -287,8 +363,6 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ out, con
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// Adam on the FP32 master weights; refresh the BF16 copies for the forward
-// ([t][o][i]) and input-gradient ([26 - t][i][o]) convolutions.
 // The constants come from the host, formed in FP64 and rounded once: k.omb1 = 1 - beta1,
 // k.omb2 = 1 - beta2 and the bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t
 // (1 - 0.999f in FP32 would carry a relative error of 1.3e-5).
@@ -348,16 +422,54 @@ static inline AdamK adam_constants(int t, float lr) {
 
 static inline int gblocks(long n) { return (int)std::min<long>(4096, (n + 255) / 256); }
 
+// k_conv2 may use more than 64 KiB of dynamic LDS (83.5 KiB with four N-tiles)
+template <int TAPS>
+static hipError_t allow_conv_lds_taps() {
+  const auto a = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 1>, a, (int)conv2_lds(TAPS, 1)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 2>, a, (int)conv2_lds(TAPS, 2)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 3>, a, (int)conv2_lds(TAPS, 3)))) return e;
+  return hipFuncSetAttribute((const void*)k_conv2<TAPS, 4>, a, (int)conv2_lds(TAPS, 4));
+}
+static hipError_t allow_conv_lds() {
+  const hipError_t e = allow_conv_lds_taps<27>();
+  return e ? e : allow_conv_lds_taps<1>();
+}
+
+template <int TAPS>
+static void conv2_launch_nt(int nt, dim3 grid, int g0, hipStream_t s, const bf16_t* X, int xcs, int xco, int Cin,
+                            const bf16_t* W, int Cout, bf16_t* Y, int ycs, int yco, float* Yf, Vol vol, int relu,
+                            const bf16_t* mask, int mcs, int mco) {
+  const size_t lds = conv2_lds(TAPS, nt);
+#define VIE_CONV2(NTV)                                                                                           \
+  if (nt == NTV)                                                                                                 \
+    hipLaunchKernelGGL((k_conv2<TAPS, NTV>), grid, dim3(256), lds, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, \
+                       vol, relu, mask, mcs, mco, g0);
+  VIE_CONV2(1)
+  VIE_CONV2(2)
+  VIE_CONV2(3)
+  VIE_CONV2(4)
+#undef VIE_CONV2
+}
+
+// Output-channel groups of four N-tiles in one launch, a smaller last group in a second.
 hipError_t conv_launch(int taps, const bf16_t* X, int xcs, int xco, int Cin, const bf16_t* W, int Cout, bf16_t* Y,
                        int ycs, int yco, float* Yf, Vol vol, int relu, const bf16_t* mask, int mcs, int mco,
                        hipStream_t s) {
-  const dim3 grid((unsigned)((vol.V() + 63) / 64), (unsigned)((Cout / 16 + 3) / 4));
-  if (taps == 27)
-    hipLaunchKernelGGL((k_conv<27>), grid, dim3(256), 0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu,
-                       mask, mcs, mco);
-  else
-    hipLaunchKernelGGL((k_conv<1>), grid, dim3(256), 0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu,
-                       mask, mcs, mco);
+  static const hipError_t lds_ok = allow_conv_lds();
+  if (lds_ok) return lds_ok;
+  const long tiles = (long)((vol.D + kCtz - 1) / kCtz) * ((vol.H + kCty - 1) / kCty) * ((vol.W + kCtx - 1) / kCtx);
+  const int ntiles = Cout / 16, full = ntiles / 4, rest = ntiles % 4;
+  auto go = [&](int nt, int groups, int g0) {
+    const dim3 grid((unsigned)tiles, (unsigned)groups);
+    if (taps == 27)
+      conv2_launch_nt<27>(nt, grid, g0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu, mask, mcs, mco);
+    else
+      conv2_launch_nt<1>(nt, grid, g0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu, mask, mcs, mco);
+  };
+  if (full) go(4, full, 0);
+  if (rest) go(rest, 1, full);
   return hipGetLastError();
 }
 
@@ -549,13 +661,13 @@ int nfail(vie_net_s* n, int code, const std::string& m) {
 
 namespace vie {
 // used by the solver (vie_api.cpp): z = ||r|| net(r / ||r||, chi)
-hipError_t net_apply(vie_net_s* N, const double2* r, const double2* chi, double2* z) {
+hipError_t net_apply(vie_net_s* N, const double2* r, const double2* w, const double2* chi, double2* z) {
   const long V = N->lv[0].V();
   hipError_t e;
   if ((e = KrylovOps<double>::nrm2sq(r, 3 * V, N->red, N->sumsq, N->stream))) return e;
-  hipLaunchKernelGGL(k_pack, dim3(gblocks(V)), dim3(256), 0, N->stream, r, chi, N->sumsq, V, N->X0);
+  hipLaunchKernelGGL(k_pack, dim3(gblocks(V)), dim3(256), 0, N->stream, r, w, chi, N->sumsq, V, N->X0);
   if ((e = net_forward(N))) return e;
-  hipLaunchKernelGGL(k_unpack, dim3(gblocks(V)), dim3(256), 0, N->stream, N->out, N->sumsq, V, r, z);
+  hipLaunchKernelGGL(k_unpack, dim3(gblocks(V)), dim3(256), 0, N->stream, N->out, N->sumsq, V, w ? w : r, z);
   return hipGetLastError();
 }
 const int* net_grid(vie_net_s* N) { return N->n; }
@@ -574,7 +686,7 @@ int vie_net_create(vie_net_t* out, const int grid[3], unsigned seed, void* hip_s
   N->stream = reinterpret_cast<hipStream_t>(hip_stream);
   for (int l = 0; l < 4; ++l) N->lv[l] = Vol{grid[0] >> l, grid[1] >> l, grid[2] >> l};
   // (taps, cin, cout, cin_real): 16/32/48/64 U-Net, input 8 real channels, output 6
-  const int spec[15][4] = {{27, 16, 16, 8},   {27, 16, 16, 16},  {27, 16, 32, 16},  {27, 32, 32, 32},
+  const int spec[15][4] = {{27, 16, 16, 14},  {27, 16, 16, 16},  {27, 16, 32, 16},  {27, 32, 32, 32},
                            {27, 32, 48, 32},  {27, 48, 48, 48},  {27, 48, 64, 48},  {27, 64, 64, 64},
                            {27, 112, 48, 112}, {27, 48, 48, 48}, {27, 80, 32, 80},  {27, 32, 32, 32},
                            {27, 48, 16, 48},  {27, 16, 16, 16},  {1, 16, 16, 16}};
@@ -679,15 +791,24 @@ int vie_net_set_params(vie_net_t N, const float* host, size_t count) {
 }
 
 int vie_net_apply(vie_net_t N, const vie_c128* r, const vie_c128* chi, vie_c128* z) {
+  return vie_net_apply_base(N, r, nullptr, chi, z);
+}
+
+int vie_net_apply_base(vie_net_t N, const vie_c128* r, const vie_c128* w, const vie_c128* chi, vie_c128* z) {
   if (!N || !r || !chi || !z) return VIE_EINVAL;
-  if (net_apply(N, reinterpret_cast<const double2*>(r), reinterpret_cast<const double2*>(chi),
-                reinterpret_cast<double2*>(z)))
+  if (net_apply(N, reinterpret_cast<const double2*>(r), reinterpret_cast<const double2*>(w),
+                reinterpret_cast<const double2*>(chi), reinterpret_cast<double2*>(z)))
     return VIE_EDEVICE;
   return VIE_OK;
 }
 
 int vie_net_train_step(vie_net_t N, int count, const vie_c128* const* r, const vie_c128* const* chi,
                        const vie_c128* const* target, float lr, double* loss) {
+  return vie_net_train_step_base(N, count, r, nullptr, chi, target, lr, loss);
+}
+
+int vie_net_train_step_base(vie_net_t N, int count, const vie_c128* const* r, const vie_c128* const* w,
+                            const vie_c128* const* chi, const vie_c128* const* target, float lr, double* loss) {
   if (!N || count < 1 || !r || !chi || !target || !(lr >= 0)) return VIE_EINVAL;
   const long V = N->lv[0].V();
   double total = 0.0;
@@ -696,12 +817,13 @@ int vie_net_train_step(vie_net_t N, int count, const vie_c128* const* r, const v
     if (!r[i] || !chi[i] || !target[i]) return VIE_EINVAL;
     const double2* ri = reinterpret_cast<const double2*>(r[i]);
     if (KrylovOps<double>::nrm2sq(ri, 3 * V, N->red, N->sumsq, N->stream)) return VIE_EDEVICE;
-    hipLaunchKernelGGL(k_pack, dim3(gblocks(V)), dim3(256), 0, N->stream, ri,
+    const double2* wi = w ? reinterpret_cast<const double2*>(w[i]) : nullptr;
+    hipLaunchKernelGGL(k_pack, dim3(gblocks(V)), dim3(256), 0, N->stream, ri, wi,
                        reinterpret_cast<const double2*>(chi[i]), N->sumsq, V, N->X0);
     if (net_forward(N)) return VIE_EDEVICE;
     const float gscale = 2.0f / (6.0f * (float)V * (float)count);
     hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, N->stream, N->out, reinterpret_cast<const double2*>(target[i]),
-                       ri, N->sumsq, V, N->gOut, gscale, N->lpart);
+                       wi ? wi : ri, N->sumsq, V, N->gOut, gscale, N->lpart);
     if (net_backward(N, i > 0 ? 1 : 0)) return VIE_EDEVICE;
     if (hipMemcpyAsync(N->lpart_h, N->lpart, sizeof(double) * nb, hipMemcpyDeviceToHost, N->stream) ||
         hipStreamSynchronize(N->stream))

@@ -24,7 +24,7 @@
 namespace vie {
 template <typename T>
 hipError_t allow_lds(size_t bytes);
-hipError_t net_apply(vie_net_s* N, const double2* r, const double2* chi, double2* z);
+hipError_t net_apply(vie_net_s* N, const double2* r, const double2* w, const double2* chi, double2* z);
 const int* net_grid(vie_net_s* N);
 void net_set_stream(vie_net_s* N, hipStream_t s);
 }
@@ -158,6 +158,7 @@ struct vie_plan_s {
   int ns = 0;
   double2* fx = nullptr;       // full FP64 operator input, zero off the support
   double2* fy = nullptr;       // full FP64 operator output
+  double2* fw = nullptr;       // full FP64 base vector (learned-circulant tier)
   float2* fx32 = nullptr;      // the same in FP32 (mixed tier)
   float2* fy32 = nullptr;
   double2* bc = nullptr;       // compressed right-hand side and solution
@@ -899,6 +900,7 @@ namespace {
 struct SolveBufs {
   double2* fx;            // full FP64 operator input, zero off the support (3N)
   double2* fy;            // full FP64 operator output (3N)
+  double2* fw;            // full FP64 base vector of the learned-circulant tier (3N; null elsewhere)
   double2* bc;            // compressed right-hand side (3N at most)
   double2* xc;            // compressed solution (3N at most)
   double2* partial_full;  // reduction partials of full-length norms
@@ -920,11 +922,13 @@ int solve_options(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, con
   if (o.inner_restart <= 0) o.inner_restart = 20;
   if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
   if (o.restart > 4096 || o.inner_restart > 4096) return fail(p, VIE_EINVAL, "restart too large");
-  if (o.precision < 0 || o.precision > 3) return fail(p, VIE_EINVAL, "unknown precision tier");
+  if (o.precision < 0 || o.precision > 4) return fail(p, VIE_EINVAL, "unknown precision tier");
   if (o.precision == 1 && !p->goct32) return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
-  if (o.precision == 2 && !p->net) return fail(p, VIE_ESTATE, "no preconditioner attached (vie_set_preconditioner)");
-  if (o.precision == 3 && !p->circ) return fail(p, VIE_ESTATE, "no circulant preconditioner (vie_circulant_build)");
-  if (o.precision == 3 && circ_info(p->circ).s != p->ns)
+  if ((o.precision == 2 || o.precision == 4) && !p->net)
+    return fail(p, VIE_ESTATE, "no preconditioner attached (vie_set_preconditioner)");
+  if ((o.precision == 3 || o.precision == 4) && !p->circ)
+    return fail(p, VIE_ESTATE, "no circulant preconditioner (vie_circulant_build)");
+  if ((o.precision == 3 || o.precision == 4) && circ_info(p->circ).s != p->ns)
     return fail(p, VIE_ESTATE, "circulant preconditioner built for another support");
   return VIE_OK;
 }
@@ -1027,29 +1031,49 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
     } pc{inner};
     status = gmres_core<double, Op64c, Pc>(p, *B.ws, A, &pc, n, B.bc, B.xc, tolc, o.restart, o.maxit,
                                            o.use_x0 != 0, true, st);
-  } else if (o.precision == 2) {
-    // learned tier: x0 = net(b), FGMRES with z = net(v) (full-grid network around
-    // the compressed vectors).  Plain GMRES takes over for the rest of the solve
-    // when a cycle reduces the true residual by less than half, when the guess
-    // net(b) is not finite (x0 = 0 then), or when a network output poisons an
-    // Arnoldi step with a non-finite value (the iterate of that cycle's start is
+  } else if (o.precision == 2 || o.precision == 4) {
+    // learned tiers.  Precision 2: z = net(v) (the network's correction of v);
+    // precision 4: z = W^{-1} v + net(v, W^{-1} v) (the network's correction of the
+    // block circulant).  x0 = the preconditioner applied to b.  The method without
+    // the network takes over for the rest of the solve -- plain GMRES (2) or the
+    // circulant FGMRES (4) -- when a restart cycle reduces the true residual by less
+    // than half, when the guess is not finite (x0 = 0 then), or when a network
+    // output makes an Arnoldi step non-finite (the iterate of that cycle's start is
     // restored: gmres_core leaves x untouched when it stops inside a cycle).
     net_set_stream(p->net, s);
     int napply = 0;
+    const bool on_circ = o.precision == 4;
+    if (on_circ) HIPTRY(p, K::zero(B.fw, nfull, s));
     struct Pc {
       vie_plan_s* p;
       Support u;
       int* count;
       double2* fx;
+      double2* fw;
       double2* fy;
+      bool on_circ;
       hipError_t operator()(const void* v, void* z, Stats&) {
         ++*count;
-        hipError_t e = scatter<double>(u, reinterpret_cast<const double2*>(v), fx, p->stream);
+        const double2* vc = reinterpret_cast<const double2*>(v);
+        double2* zc = reinterpret_cast<double2*>(z);
+        hipError_t e = scatter<double>(u, vc, fx, p->stream);
         if (e) return e;
-        if ((e = net_apply(p->net, fx, p->chi64, fy))) return e;
-        return gather<double>(u, fy, reinterpret_cast<double2*>(z), nullptr, p->stream);
+        if (on_circ) {
+          if ((e = circ_apply_rows(p->circ, vc, zc, p->stream))) return e;
+          if ((e = scatter<double>(u, zc, fw, p->stream))) return e;
+        }
+        if ((e = net_apply(p->net, fx, on_circ ? fw : nullptr, p->chi64, fy))) return e;
+        return gather<double>(u, fy, zc, nullptr, p->stream);
       }
-    } pc{p, u, &napply, B.fx, B.fy};
+    } pc{p, u, &napply, B.fx, B.fw, B.fy, on_circ};
+    struct CircPc {
+      vie_plan_s* p;
+      hipError_t operator()(const void* v, void* z, Stats& s_) {
+        ++s_.inner;
+        return circ_apply_rows(p->circ, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(z),
+                               p->stream);
+      }
+    } cpc{p};
     bool fell_back = false;
     bool have_x0 = o.use_x0 != 0;
     if (!o.use_x0) {
@@ -1065,11 +1089,18 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
     }
     double prev = INFINITY;
     status = VIE_ENOCONV;
+    int circ_applies = 0;
     while (st.iters < o.maxit) {
       const int budget = fell_back ? o.maxit : std::min(o.maxit, st.iters + o.restart);
       if (fell_back) {
-        status = gmres_core<double, Op64c, NoPrecond>(p, *B.ws, A, nullptr, n, B.bc, B.xc, tolc, o.restart,
-                                                      budget, have_x0, true, st);
+        Stats before = st;
+        if (on_circ)
+          status = gmres_core<double, Op64c, CircPc>(p, *B.ws, A, &cpc, n, B.bc, B.xc, tolc, o.restart, budget,
+                                                     have_x0, true, st);
+        else
+          status = gmres_core<double, Op64c, NoPrecond>(p, *B.ws, A, nullptr, n, B.bc, B.xc, tolc, o.restart,
+                                                        budget, have_x0, true, st);
+        circ_applies += st.inner - before.inner;
         break;
       }
       // the cycle's starting iterate, kept in the full-length scratch vector
@@ -1087,7 +1118,7 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
       if (!(st.rel_true < 0.5 * prev)) fell_back = true;
       prev = st.rel_true;
     }
-    st.inner = napply;
+    st.inner = napply + circ_applies;
     st.fallback = fell_back ? 1 : 0;
   } else {
     // FP64 FGMRES right-preconditioned by the block circulant: z = W^{-1} v
@@ -1135,7 +1166,8 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
     HIPTRY(p, dmalloc(&p->v32a, sizeof(float2) * nfull));
     HIPTRY(p, dmalloc(&p->v32b, sizeof(float2) * nfull));
   }
-  const SolveBufs B{p->fx, p->fy, p->bc, p->xc, p->partial_full, p->sumsq_full, &p->ws64};
+  if (o.precision == 4 && !p->fw) HIPTRY(p, dmalloc(&p->fw, sizeof(double2) * nfull));
+  const SolveBufs B{p->fx, p->fy, p->fw, p->bc, p->xc, p->partial_full, p->sumsq_full, &p->ws64};
   return solve_impl(p, b, x, tol, o, info, B, t0);
 }
 
@@ -1161,6 +1193,7 @@ int vie_solve_noalloc(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, 
   SolveBufs B;
   B.fx = c.take<double2>(nfull);
   B.fy = c.take<double2>(nfull);
+  B.fw = nullptr;
   B.bc = c.take<double2>(n);
   B.xc = c.take<double2>(n);
   B.partial_full = c.take<double2>(partial_blocks(nfull) + 1);
@@ -1547,7 +1580,7 @@ void vie_destroy(vie_plan_t p) {
   if (p->npin) (void)hipHostFree(p->npin);
   for (void* q : {(void*)p->goct64, (void*)p->goct32, (void*)p->chi64, (void*)p->chi32, (void*)p->U64,
                   (void*)p->U32, (void*)p->rvec, (void*)p->v32a, (void*)p->v32b, (void*)p->flag, (void*)p->colflag,
-                  (void*)p->scol, (void*)p->fx, (void*)p->fy, (void*)p->fx32, (void*)p->fy32, (void*)p->bc,
+                  (void*)p->scol, (void*)p->fx, (void*)p->fy, (void*)p->fw, (void*)p->fx32, (void*)p->fy32, (void*)p->bc,
                   (void*)p->xc, (void*)p->partial_full, (void*)p->sumsq_full, (void*)p->koct64,
                   (void*)p->koct32, (void*)p->chim64, (void*)p->chim32, (void*)p->Um64, (void*)p->Um32,
                   (void*)p->S64, (void*)p->S32, (void*)p->jm32a, (void*)p->jm32b})

@@ -626,9 +626,13 @@ if __name__ == "__main__":
     import argparse
     import json
     ap = argparse.ArgumentParser(description="experiments of the paper run on the GPU path")
-    ap.add_argument("which", choices=["strip", "bragg", "slowlight"],
+    ap.add_argument("which", choices=["strip", "bragg", "slowlight", "learned"],
                     help="strip: the reflection study of Section V-A; bragg: the grating's transmission; "
-                         "slowlight: absorbers inside the grating")
+                         "slowlight: absorbers inside the grating; learned: the network correcting the "
+                         "block circulant on rough guides (train seeds 0.., test seeds 10000..)")
+    ap.add_argument("--train", type=int, default=2000, help="learned: solver-generated training pairs")
+    ap.add_argument("--test", type=int, default=100, help="learned: test geometries")
+    ap.add_argument("--epochs", type=int, default=8, help="learned: training epochs")
     ap.add_argument("--out", default=None, help="write the JSON result here")
     ap.add_argument("--quick", action="store_true", help="every other absorber length")
     ap.add_argument("--em", action="store_true", help="electric and magnetic currents, matched absorber")
@@ -637,6 +641,23 @@ if __name__ == "__main__":
     ap.add_argument("--periods", type=int, default=100, help="bragg: grating periods")
     ap.add_argument("--circulant", action="store_true", help="bragg: block-circulant preconditioned solves")
     a = ap.parse_args()
+    if a.which == "learned":
+        from . import learned
+        st = learned.CirculantCorrectionStudy(seed=0)
+        gen = st.generate(range(a.train))
+        print("generated", gen, flush=True)
+        t0 = time.perf_counter()
+        losses = st.train(a.epochs)
+        train_s = time.perf_counter() - t0
+        print("losses", losses, "train s", round(train_s, 1), flush=True)
+        ev = st.evaluate(range(10000, 10000 + a.test))
+        res = {"generate": gen, "epochs": a.epochs, "losses": losses, "train_seconds": round(train_s, 2),
+               "test": ev["mean"], "per_seed": ev["per_seed"]}
+        print(json.dumps(ev["mean"]), flush=True)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(json.dumps(res, indent=1))
+        raise SystemExit(0)
     if a.which == "slowlight":
         res = bragg_slow_light_study(progress=lambda r: print(r, flush=True))
         res["spectrum"] = bragg_slow_light_spectrum(

@@ -89,3 +89,100 @@ def compare_tiers(plan: "vie.Plan", net: "vie.Net", b, tol: float = 1e-8, restar
         info["rel_res_fp64"] = (torch.linalg.norm(r) / torch.linalg.norm(b)).item()
         out[name] = info
     return out
+
+
+class CirculantCorrectionStudy:
+    """The learned preconditioner as a correction of the block circulant W (Section V-D):
+    z = W^{-1} v + net(v, W^{-1} v, chi), trained on pairs the method itself produces on
+    seeded rough-sidewall guides (32 x 32 x 256).
+
+    Training pair of geometry s: b = the dipole right-hand side of inputs.rough_strip(s),
+    x* = its solution by circulant-preconditioned FGMRES to 1e-8, w = W^{-1} b; the
+    network learns x* - w.  Every pair stays on the device (about 42 MB each)."""
+
+    def __init__(self, seed: int = 0, n3: int = 256):
+        import torch
+        self.torch = torch
+        wg = inputs.rough_strip(0, n3=n3)
+        self.grid = wg.n
+        self.plan = vie.Plan(self.grid, wg.h, wg.k0, wg.eps_b, fp32=True)
+        self.net = vie.Net(self.grid, seed=seed)
+        self.rng = np.random.default_rng(seed)
+        self.n3 = n3
+        self.pairs: List[tuple] = []
+        self.gen_seconds = 0.0
+
+    def _geometry(self, s: int):
+        torch = self.torch
+        wg = inputs.rough_strip(s, n3=self.n3)
+        self.plan.set_contrast(torch.from_numpy(wg.eps()).cuda())
+        self.plan.build_circulant()
+        b = self.plan.rhs(torch.from_numpy(inputs.transverse_dipole_field(wg)).cuda())
+        return wg, b
+
+    def generate(self, seeds: Sequence[int], tol: float = 1e-8) -> dict:
+        """One solver-generated pair per training geometry."""
+        torch = self.torch
+        t0 = time.perf_counter()
+        its = []
+        for s in seeds:
+            _, b = self._geometry(s)
+            x, info = self.plan.solve(b, tol=tol, restart=50, precision=3)
+            if info["status"] != vie.VIE_OK:
+                continue
+            w = self.plan.apply_circulant(b)
+            ph = complex(np.exp(1j * self.rng.uniform(0, 2 * np.pi)))
+            self.pairs.append((b * ph, w * ph, self.plan.contrast(), x * ph))
+            its.append(info["iters"])
+        torch.cuda.synchronize()
+        self.gen_seconds += time.perf_counter() - t0
+        return {"pairs": len(self.pairs), "seconds": round(time.perf_counter() - t0, 2),
+                "circulant_iters_mean": float(np.mean(its)) if its else None}
+
+    def train(self, epochs: int, lr: float = 1e-3, batch: int = 4, lr_decay: float = 0.8) -> List[float]:
+        losses = []
+        order = np.arange(len(self.pairs))
+        for _ in range(epochs):
+            self.rng.shuffle(order)
+            ep = []
+            for i in range(0, len(order), batch):
+                sel = [self.pairs[j] for j in order[i:i + batch]]
+                ep.append(self.net.train_step_base([p[0] for p in sel], [p[1] for p in sel],
+                                                   [p[2] for p in sel], [p[3] for p in sel], lr))
+            losses.append(float(np.mean(ep)))
+            lr *= lr_decay
+        return losses
+
+    def evaluate(self, seeds: Sequence[int], tol: float = 1e-8, restart: int = 50) -> dict:
+        """Iterations and wall time to tol on unseen geometries: FP64 GMRES (0), mixed
+        FGMRES (1), circulant FGMRES (3) and the network correcting the circulant (4);
+        each tier's residual recomputed with the FP64 product."""
+        torch = self.torch
+        self.plan.set_preconditioner(self.net)
+        rows = []
+        for s in seeds:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, b = self._geometry(s)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            row = {"seed": int(s), "circulant_setup_seconds": round(setup, 4)}
+            for name, prec in (("fp64", 0), ("mixed", 1), ("circulant", 3), ("learned_circulant", 4)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = self.plan.solve(b, tol=tol, restart=restart, maxit=20000, precision=prec)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                r = self.plan.residual(x, b)
+                row[name] = {"seconds": round(wall, 5), "iters": info["iters"], "applications": info["inner_iters"],
+                             "fallback": info["fallback"], "status": info["status"],
+                             "rel_res_fp64": (torch.linalg.norm(r) / torch.linalg.norm(b)).item()}
+            rows.append(row)
+        self.plan.set_preconditioner(None)
+        agg = {}
+        for name in ("fp64", "mixed", "circulant", "learned_circulant"):
+            agg[name] = {"seconds_mean": float(np.mean([r[name]["seconds"] for r in rows])),
+                         "iters_mean": float(np.mean([r[name]["iters"] for r in rows])),
+                         "max_rel_res_fp64": float(max(r[name]["rel_res_fp64"] for r in rows)),
+                         "fallbacks": int(sum(r[name]["fallback"] for r in rows))}
+        return {"per_seed": rows, "mean": agg}

@@ -101,6 +101,10 @@ def lib() -> ctypes.CDLL:
         L.vie_nn_conv_test.argtypes = [ctypes.c_int, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                        ctypes.c_int, vp]
         L.vie_net_get_grads.argtypes = [vp, vp, ctypes.c_size_t]
+        L.vie_net_apply_base.argtypes = [vp, vp, vp, vp, vp]
+        L.vie_net_train_step_base.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_float,
+                                              ctypes.POINTER(ctypes.c_double)]
         L.vie_nn_op_test.argtypes = [ctypes.c_int, ip, ctypes.c_int, vp, vp, vp, vp, vp]
         L.vie_nn_adam_test.argtypes = [ctypes.c_long, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp]
         L.vie_net_last_error.restype = ctypes.c_char_p
@@ -278,8 +282,9 @@ class Plan:
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000,
               precision: int = 0, use_x0: bool = False, inner_restart: int = 20,
               inner_tol: float = 1e-4, raise_on_noconv: bool = False):
-        """GMRES(restart) (precision 0), FP32-inner / FP64-outer FGMRES (1), learned (2) or
-        circulant-preconditioned FGMRES (3, after build_circulant).
+        """GMRES(restart) (precision 0), FP32-inner / FP64-outer FGMRES (1), learned (2),
+        circulant-preconditioned FGMRES (3, after build_circulant) or the network
+        correcting the circulant (4, after build_circulant and set_preconditioner).
 
         Returns (x, info dict).  info['status'] is VIE_OK or VIE_ENOCONV."""
         import torch
@@ -467,6 +472,33 @@ class Net:
         if code != VIE_OK:
             raise VieError(code, "vie_net_apply failed")
         return z
+
+    def apply_base(self, r, w, chi, z=None):
+        """z = w + net(r, chi, w) (vie_net_apply_base): the network's correction of w."""
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        code = lib().vie_net_apply_base(self._h, _ptr(r, torch.complex128, 3 * self.N, "r"),
+                                        _ptr(w, torch.complex128, 3 * self.N, "w"),
+                                        _ptr(chi, torch.complex128, self.N, "chi"),
+                                        _ptr(z, torch.complex128, 3 * self.N, "z"))
+        if code != VIE_OK:
+            raise VieError(code, "vie_net_apply_base failed")
+        return z
+
+    def train_step_base(self, rs, ws, chis, targets, lr: float) -> float:
+        """One Adam step on the base-vector form (vie_net_train_step_base)."""
+        import torch
+        n = len(rs)
+        R = (ctypes.c_void_p * n)(*[_ptr(r, torch.complex128, 3 * self.N, "r").value for r in rs])
+        Wb = (ctypes.c_void_p * n)(*[_ptr(w, torch.complex128, 3 * self.N, "w").value for w in ws])
+        C = (ctypes.c_void_p * n)(*[_ptr(c, torch.complex128, self.N, "chi").value for c in chis])
+        T = (ctypes.c_void_p * n)(*[_ptr(t, torch.complex128, 3 * self.N, "target").value for t in targets])
+        loss = ctypes.c_double()
+        code = lib().vie_net_train_step_base(self._h, n, R, Wb, C, T, float(lr), ctypes.byref(loss))
+        if code != VIE_OK:
+            raise VieError(code, "vie_net_train_step_base failed")
+        return loss.value
 
     def train_step(self, rs, chis, targets, lr: float) -> float:
         import torch

@@ -307,3 +307,41 @@ def test_train_step_loss_and_gradients_match_oracle():
     want = w0[big] - lr * go[big] / (np.abs(go[big]) + 1e-8)
     assert np.allclose(w1[big], want, rtol=0, atol=1e-5 * lr + 2.0 ** -24)
     assert np.array_equal(w1[go == 0], w0[go == 0])
+
+
+def test_network_with_base_vector_is_bit_exact_on_the_integer_case():
+    """vie_net_apply_base: the base vector enters input channels 8-13 and the output is
+    added to it; integer base vectors keep every sum exact."""
+    vie = _dev()
+    n = (8, 8, 16)
+    net = vie.Net(n, seed=0)
+    W, samples = _integer_network(net, 11, n, 1)
+    r, chi, _ = samples[0]
+    rng = np.random.default_rng(3)
+    w = (rng.integers(-2, 3, r.shape) + 1j * rng.integers(-2, 3, r.shape)).astype(complex)
+    want = nn.unet_apply(W, r, chi, w=w)
+    assert np.abs(want - w).max() > 0
+    got = net.apply_base(torch.from_numpy(r).cuda(), torch.from_numpy(w).cuda(),
+                         torch.from_numpy(chi).cuda()).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("broken", [False, True], ids=["untrained", "broken"])
+def test_network_correcting_the_circulant_reaches_tolerance(broken):
+    """Precision 4: FGMRES with z = W^{-1} v + net(v, W^{-1} v).  An untrained network
+    (small last layer) must still converge; a network with overflowing weights must
+    fall back to the circulant FGMRES.  Judged by the oracle's own residual."""
+    vie = _dev()
+    wg, op, plan, b = _small_system(vie)
+    plan.build_circulant()
+    net = vie.Net(wg.n, seed=2)
+    if broken:
+        net.set_params(np.full(net.num_params(), 1e30, np.float32))
+    plan.set_preconditioner(net)
+    x, info = plan.solve(torch.from_numpy(b).cuda(), tol=1e-8, restart=30, precision=4)
+    xs = x.cpu().numpy()
+    rr = np.linalg.norm(b.ravel() - op(xs.ravel())) / np.linalg.norm(b)
+    print(info, rr)
+    assert info["status"] == 0 and rr <= 1.01e-8
+    assert info["fallback"] == (1 if broken else info["fallback"])
+    assert info["inner_iters"] >= 1
