@@ -207,10 +207,77 @@ def cpu_baseline(n, seconds_budget=30.0):
         el = time.perf_counter() - t0
         if el > seconds_budget / 2 or runs >= 3:
             break
+    model, cores = host_cpu()
     return {"value": runs / el, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
             "sample": f"{runs} oracle FFT matvec(s) at {n[0]}x{n[1]}x{n[2]} (own radix-2 FFT, numpy, "
                       f"one thread) with a synthetic spectrum of the full circulant shape; table build excluded; "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s on {model}, {cores} cores available"}
+
+
+def host_cpu():
+    """Model name and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_protocol(repeats: int = 5):
+    """The CPU baselines of the measurement plan: the oracle's own-FFT FP64 matvec (one
+    thread) and the same matvec with scipy.fft on every host core, each the median of
+    `repeats` runs after one warm-up, at 8x8x32, 32x32x256 and 32x32x512 (synthetic
+    spectra of the circulant shape; table build excluded), and the oracle's GMRES(50) to
+    a relative residual of 1e-8 on the 8x8x32 guide from its dipole source (oracle table,
+    spectrum and solve).  Takes a few minutes; `bench.py --cpu-full`."""
+    import statistics
+
+    import numpy as np
+
+    from oracle import green, matvec as mv, solve
+    from paper_1803_06237_amd import inputs
+    model, cores = host_cpu()
+    out = {"cpu_model": model, "nproc": cores, "repeats": repeats, "matvec": {}}
+
+    def med(f):
+        f()
+        ts = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            f()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    for n in ((8, 8, 32), (32, 32, 256), (32, 32, 512)):
+        rng = np.random.default_rng(0)
+        M = tuple(2 * v for v in n)
+        spec = rng.standard_normal((6,) + M) + 1j * rng.standard_normal((6,) + M)
+        chi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        x = rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)
+        t_or = med(lambda: mv.matvec_fft(spec, chi, x))
+        t_sc = med(lambda: cpu_tuned_matvec(spec, chi, x, cores))
+        out["matvec"]["x".join(map(str, n))] = {"oracle_seconds": round(t_or, 5), "oracle_matvecs_per_s":
+                                                 round(1 / t_or, 4), "scipy_seconds": round(t_sc, 5),
+                                                 "scipy_matvecs_per_s": round(1 / t_sc, 3)}
+    wg = inputs.strip_small(d=2)
+    kap = mv.kappa_of(wg.h, wg.k0, wg.eps_b)
+    b = mv.rhs_from_field(wg.eps(), wg.eps_b, inputs.strip_small_dipole_rhs_field(wg), wg.h)
+    holder = {}
+
+    def gm():
+        op = mv.Operator(green.green_table(wg.n, kap), mv.contrast(wg.eps(), wg.eps_b))
+        holder["res"] = solve.gmres(op, b.ravel(), tol=1e-8, restart=50)
+    t_gm = med(gm)
+    res = holder["res"]
+    info = res[1]
+    out["gmres_8x8x32"] = {"seconds": round(t_gm, 4), "iterations": int(getattr(info, "iters", -1)),
+                           "includes": "oracle Green table, spectrum and GMRES(50) to 1e-8"}
+    return out
 
 
 def cpu_tuned_matvec(spec, chi, x, workers):
@@ -254,6 +321,53 @@ def cpu_tuned_baseline(n, seconds_budget=10.0):
                       f"(products and contrast in numpy), synthetic spectrum of the full circulant shape; {el:.1f} s"}
 
 
+# Forward FLOPs of one network application at grid n: 2 V_l 27 cin cout per 3x3x3 layer
+# (padded channel counts, as the matrix cores compute them) plus the 1x1x1 output layer.
+NN_LAYERS = [(27, 16, 16, 0), (27, 16, 16, 0), (27, 16, 32, 1), (27, 32, 32, 1), (27, 32, 48, 2), (27, 48, 48, 2),
+             (27, 48, 64, 3), (27, 64, 64, 3), (27, 112, 48, 2), (27, 48, 48, 2), (27, 80, 32, 1), (27, 32, 32, 1),
+             (27, 48, 16, 0), (27, 16, 16, 0), (1, 16, 16, 0)]
+
+
+def nn_flops(n):
+    V = n[0] * n[1] * n[2]
+    return sum(2 * (V >> (3 * lev)) * t * ci * co for t, ci, co, lev in NN_LAYERS)
+
+
+def nn_measurement(steps: int):
+    """The learned network at 32x32x256: average application time (HIP events on the
+    network's stream) and one training step, with the forward FLOP rate."""
+    import numpy as np
+    import torch
+
+    from paper_1803_06237_amd import vie
+    n = (32, 32, 256)
+    s = torch.cuda.current_stream()
+    net = vie.Net(n, seed=0)
+    rng = np.random.default_rng(0)
+    r = torch.from_numpy(rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)).cuda()
+    chi = torch.from_numpy((rng.uniform(0, 1, n) < 0.2) * (0.8 + 0.1j)).cuda()
+    w = torch.from_numpy(rng.standard_normal((3,) + n) + 1j * rng.standard_normal((3,) + n)).cuda()
+    for _ in range(3):
+        net.apply_base(r, w, chi)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        net.apply_base(r, w, chi)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    net.train_step_base([r], [w], [chi], [r], 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        net.train_step_base([r], [w], [chi], [r], 1e-4)
+    torch.cuda.synchronize()
+    tr = (time.perf_counter() - t0) / 3
+    f = nn_flops(n)
+    return {"grid": list(n), "apply_ms": round(ms, 4), "forward_gflop": round(f / 1e9, 2),
+            "forward_tflops": round(f / (ms * 1e-3) / 1e12, 1), "train_step_ms": round(tr * 1e3, 2)}
+
+
 def learned_comparison(n_train: int = 96, epochs: int = 3, n_test: int = 4):
     """The learned preconditioner as a correction of the block circulant on seeded rough
     guides (32x32x256): n_train solver-generated pairs (training seeds 0..), a few
@@ -292,6 +406,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-family", action="store_true", help="skip the 64-system absorber-family batch")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only the CPU baselines: medians of 5 runs at 8x8x32, 32x32x256, 32x32x512 and the "
+                         "oracle's GMRES on 8x8x32 (a few minutes, no GPU)")
     ap.add_argument("--profile", action="store_true",
                     help="profiler run: one device copy of a vector (counter calibration, bytes known) and the "
                          "timed FP64 products only")
@@ -299,7 +416,12 @@ def main():
                     help="profiler run: the JM-VIE products only (both grids, both precisions)")
     ap.add_argument("--profile-strip", action="store_true",
                     help="profiler run: J-VIE products on the paper's strip 30x12x1377 only (FP64, FP32)")
+    ap.add_argument("--profile-nn", action="store_true",
+                    help="profiler run: the learned network at 32x32x256 (applications and training steps)")
     args = ap.parse_args()
+    if args.cpu_full:
+        print(json.dumps({"cpu_protocol": cpu_protocol()}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver is single-GPU.",
               file=sys.stderr)
@@ -315,6 +437,9 @@ def main():
         return
     if args.profile_strip:
         print(json.dumps({"strip_matvec": strip_measurement(args.steps)}), flush=True)
+        return
+    if args.profile_nn:
+        print(json.dumps({"nn": nn_measurement(args.steps)}), flush=True)
         return
     wg = inputs.strip_long(d=2)
     n = wg.n
@@ -404,7 +529,7 @@ def main():
         e_inc = inputs.transverse_dipole_field(wg)
         b = plan.rhs(torch.from_numpy(e_inc).cuda())
         res = {}
-        for name, prec in (("fp64_gmres50", 0), ("mixed_fgmres", 1)):
+        for name, prec in (("fp64_gmres50", 0), ("mixed_fgmres", 1), ("mixed_fgmres_fp64_inner_arnoldi", 5)):
             plan.solve(b, tol=1e-8, restart=50, maxit=200, precision=prec)   # warm (allocations)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -417,6 +542,8 @@ def main():
                          "status": info["status"],
                          "unknown_iterations_per_s": round(3 * wg.N * its / dt, 1)}
         res["mixed_speedup_vs_fp64"] = round(res["fp64_gmres50"]["seconds"] / res["mixed_fgmres"]["seconds"], 3)
+        res["mixed_fp64_inner_arnoldi_speedup_vs_fp64"] = round(
+            res["fp64_gmres50"]["seconds"] / res["mixed_fgmres_fp64_inner_arnoldi"]["seconds"], 3)
         # block-circulant preconditioner (Section V-D): set-up timed apart from the solve
         plan.build_circulant()
         torch.cuda.synchronize()
@@ -448,6 +575,7 @@ def main():
         from paper_1803_06237_amd import experiments
         out["iterations_vs_length"] = experiments.iterations_vs_length()
         out["mixed_vs_fp64_observables"] = experiments.mixed_vs_fp64()
+        out["mixed_fp64_inner_arnoldi_vs_fp64_observables"] = experiments.mixed_vs_fp64(precision=5)
 
     if not args.no_family:
         from paper_1803_06237_amd import experiments

@@ -136,7 +136,9 @@ typedef struct {
                             vie_circulant_build;
                          4: FP64 FGMRES preconditioned by the attached network correcting
                             the block circulant, z = W^{-1} v + net(v, W^{-1} v), x0 from
-                            the same map of b; the circulant FGMRES is its fallback */
+                            the same map of b; the circulant FGMRES is its fallback;
+                         5: mixed as 1, but the inner GMRES keeps FP64 Krylov vectors
+                            and Arnoldi (FP32 products only) */
   int inner_restart;  /* mixed tier: inner GMRES dimension; <= 0 -> 20 */
   double inner_tol;   /* mixed tier: inner relative tolerance; <= 0 -> 1e-4 */
   int use_graph;      /* vie_solve_batch: 1 = capture one restart cycle as a HIP graph and replay it */
@@ -364,6 +366,7 @@ const char* vie_net_last_error(vie_net_t net);
  *   vie_net_get_params.  Synchronises.
  * vie_nn_op_test: one pooling or upsampling kernel on FP32 device buffers (inputs
  *   rounded to bfloat16, bfloat16 results widened to FP32), C channels per voxel
+ *   (a multiple of 8)
  *   (channels last), dims = the fine grid (even sizes): op 0 average pooling
  *   x[fine] -> out[coarse]; 1 its gradient x = dY[coarse] -> out[fine] = dY/8 at the
  *   parent, zero where mask[fine] <= 0 (mask may be NULL), added to acc[fine] (may be

@@ -31,6 +31,8 @@ namespace vie {
 
 typedef unsigned short bf16_t;
 typedef short s4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf16_t f2bf(float f) {   // round to nearest, ties to even
@@ -58,9 +60,6 @@ struct Vol {
 // zero).  Halo layout [half][voxel][8 channels] (half = channels 0-7 or 8-15), so
 // the 16 lanes of one fragment row read 256 contiguous bytes; weight layout
 // [tap pair][N-tile][lane] of 16-byte B fragments, so a wave reads 1 KiB contiguous.
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
-typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-
 constexpr int kCtx = 32, kCty = 4, kCtz = 2;             // output tile (W, H, D)
 constexpr int kHx = kCtx + 2, kHy = kCty + 2, kHz = kCtz + 2;
 constexpr int kHvox = kHx * kHy * kHz;                   // 816 halo voxels
@@ -225,21 +224,31 @@ __global__ void k_wreduce(const float* __restrict__ partial, int nchunk, long pe
 }
 
 // ------------------------------------------------------------------ pooling, upsampling
-// Y (coarse) = mean of the 8 children of X (fine)
+// Y (coarse) = mean of the 8 children of X (fine); one thread per 8 channels of a
+// coarse voxel (C, strides and offsets are multiples of 8: 16-byte accesses)
 __global__ void k_pool(const bf16_t* __restrict__ X, int xcs, int xco, bf16_t* __restrict__ Y, int ycs, int yco, int C,
                        Vol fine) {
   const Vol c{fine.D / 2, fine.H / 2, fine.W / 2};
-  const long n = c.V() * C;
+  const int C8 = C / 8;
+  const long n = c.V() * C8;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int ch = (int)(i % C);
-    const long v = i / C;
+    const int ch = (int)(i % C8) * 8;
+    const long v = i / C8;
     const int x = (int)(v % c.W), y = (int)((v / c.W) % c.H), z = (int)(v / ((long)c.W * c.H));
-    float s = 0.f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int q = 0; q < 8; ++q) {
       const long fv = (((long)(2 * z + (q >> 2)) * fine.H + 2 * y + ((q >> 1) & 1)) * fine.W + 2 * x + (q & 1));
-      s += bf2f(X[fv * xcs + xco + ch]);
+      const u4v raw = *reinterpret_cast<const u4v*>(X + fv * xcs + xco + ch);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        s[2 * k] += __uint_as_float(raw[k] << 16);
+        s[2 * k + 1] += __uint_as_float(raw[k] & 0xFFFF0000u);
+      }
     }
-    Y[v * ycs + yco + ch] = f2bf(s * 0.125f);
+    u4v o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = (unsigned)f2bf(s[2 * k] * 0.125f) | ((unsigned)f2bf(s[2 * k + 1] * 0.125f) << 16);
+    *reinterpret_cast<u4v*>(Y + v * ycs + yco + ch) = o;
   }
 }
 
@@ -259,16 +268,17 @@ __global__ void k_pool_grad(const bf16_t* __restrict__ dY, int ycs, int yco, bf1
   }
 }
 
-// Y (fine) = X[parent] (nearest neighbour)
+// Y (fine) = X[parent] (nearest neighbour); one thread per 8 channels of a fine voxel
 __global__ void k_up(const bf16_t* __restrict__ X, int xcs, int xco, bf16_t* __restrict__ Y, int ycs, int yco, int C,
                      Vol fine) {
-  const long n = fine.V() * C;
+  const int C8 = C / 8;
+  const long n = fine.V() * C8;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int ch = (int)(i % C);
-    const long v = i / C;
+    const int ch = (int)(i % C8) * 8;
+    const long v = i / C8;
     const int x = (int)(v % fine.W), y = (int)((v / fine.W) % fine.H), z = (int)(v / ((long)fine.W * fine.H));
     const long pv = ((long)(z / 2) * (fine.H / 2) + y / 2) * (fine.W / 2) + x / 2;
-    Y[v * ycs + yco + ch] = X[pv * xcs + xco + ch];
+    *reinterpret_cast<u4v*>(Y + v * ycs + yco + ch) = *reinterpret_cast<const u4v*>(X + pv * xcs + xco + ch);
   }
 }
 
@@ -910,7 +920,7 @@ int vie_net_get_grads(vie_net_t N, float* host, size_t count) {
 // 2 upsampling x[coarse] -> out[fine]; 3 its gradient x = dY[fine] -> out[coarse].
 int vie_nn_op_test(int op, const int dims[3], int C, const float* x, const float* mask, const float* acc,
                    float* out, void* hip_stream) {
-  if (!dims || !x || !out || C < 1 || op < 0 || op > 3) return VIE_EINVAL;
+  if (!dims || !x || !out || C < 8 || C % 8 || op < 0 || op > 3) return VIE_EINVAL;
   for (int d = 0; d < 3; ++d)
     if (dims[d] < 2 || dims[d] % 2) return VIE_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);

@@ -6,6 +6,9 @@
 
 #include <chrono>
 #include <cstdlib>
+#include <fcntl.h>
+#include <sys/stat.h>
+#include <unistd.h>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -188,6 +191,7 @@ struct vie_plan_s {
   std::shared_ptr<const std::vector<std::complex<double>>> table;   // host Toeplitz table
   GmresWs<double> ws64;
   GmresWs<float> ws32;
+  GmresWs<double> ws64i;       // inner FP64-Arnoldi solves of the mixed tier (precision 5)
   // created by vie_plan for vie_solve_noalloc, which may not create them itself
   hipEvent_t nev[2] = {nullptr, nullptr};
   double* npin = nullptr;      // pinned host slot, 8 doubles
@@ -280,6 +284,80 @@ hipError_t time_passes(const Geom& g, const Tune& t, int w0, int w1, const void*
   return e;
 }
 
+// Persistent tuner cache: one line "arch n1 n2 n3 value_bytes z4 zp xyv" per tuned
+// shape, in the file named by VIE_TUNE_CACHE (empty: no file), by default
+// $XDG_CACHE_HOME/vie-mi355x/tune.txt or $HOME/.cache/vie-mi355x/tune.txt.  A
+// process reads it before timing candidates and appends what it tunes; the last
+// line for a key wins.  Lines are appended with one write each.
+std::string tune_cache_path() {
+  if (const char* v = std::getenv("VIE_TUNE_CACHE")) return v;
+  std::string dir;
+  if (const char* x = std::getenv("XDG_CACHE_HOME"); x && *x) dir = x;
+  else if (const char* h = std::getenv("HOME"); h && *h) dir = std::string(h) + "/.cache";
+  else return "";
+  return dir + "/vie-mi355x/tune.txt";
+}
+
+std::string device_arch(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return (colon == std::string::npos ? a : a.substr(0, colon)) + "-cu" + std::to_string(prop.multiProcessorCount);
+}
+
+bool tune_cache_lookup(const std::string& arch, const Geom& g, int vb, Tune* t) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return false;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  char a[128];
+  int n1, n2, n3, b, z4, zp, xyv;
+  bool found = false;
+  Tune best = *t;
+  while (std::fscanf(f, "%127s %d %d %d %d %d %d %d", a, &n1, &n2, &n3, &b, &z4, &zp, &xyv) == 8) {
+    if (arch == a && n1 == g.n1 && n2 == g.n2 && n3 == g.n3 && b == vb) {
+      best.z4 = z4;
+      best.zp = zp;
+      best.xyv = xyv;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  // only shapes this build can launch
+  if (found) {
+    int opts[8];
+    const int n = vb == 16 ? z4_pencil_options<double>(g.M3, opts, 8) : z4_pencil_options<float>(g.M3, opts, 8);
+    bool ok = best.xyv >= 0 && best.xyv <= 2 && (best.z4 == 0 || best.z4 == 1) && (t->z4 || !best.z4);
+    if (best.z4) {
+      bool hit = false;
+      for (int i = 0; i < n; ++i) hit = hit || opts[i] == best.zp;
+      ok = ok && hit;
+    }
+    if (ok) *t = best;
+    return ok;
+  }
+  return false;
+}
+
+void tune_cache_store(const std::string& arch, const Geom& g, int vb, const Tune& t) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    // create the directory chain (errors ignored: the cache is optional)
+    for (size_t i = 1; i <= slash; ++i)
+      if (path[i] == '/' || i == slash) (void)::mkdir(path.substr(0, i == slash ? slash : i).c_str(), 0755);
+  }
+  char line[256];
+  const int len = std::snprintf(line, sizeof line, "%s %d %d %d %d %d %d %d\n", arch.c_str(), g.n1, g.n2, g.n3, vb,
+                                t.z4, t.zp, t.xyv);
+  const int fd = ::open(path.c_str(), O_WRONLY | O_CREAT | O_APPEND, 0644);
+  if (fd < 0) return;
+  (void)!::write(fd, line, (size_t)len);
+  ::close(fd);
+}
+
 template <typename T>
 hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goct, const void* chi,
                     const void* const tw[3], hipStream_t s) {
@@ -291,6 +369,12 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
       *t = it->second;
       return hipSuccess;
     }
+  }
+  const std::string arch = device_arch(device);
+  if (tune_cache_lookup(arch, g, (int)sizeof(cx<T>), t)) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = *t;
+    return hipSuccess;
   }
   const size_t bytes = sizeof(cx<T>) * 3 * (size_t)g.N;
   void* x = nullptr;
@@ -355,6 +439,7 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
   if (!e) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = *t;
+    tune_cache_store(arch, g, (int)sizeof(cx<T>), *t);
   }
   return e;
 }
@@ -435,6 +520,28 @@ struct Op32c {
     hipError_t e = full(xc);
     return e ? e : gather<float>(u, p->fy32, rc, bc, p->stream);
   }
+};
+
+// The FP32 product on FP64 support-compressed vectors: the inner solve of the mixed
+// tier with FP64 Arnoldi (precision 5).  x is rounded to FP32, the FP32 product runs
+// on the full grid, the gathered result is widened back to FP64.
+struct Op32in64c {
+  vie_plan_s* p;
+  Support u;
+  long n;
+  hipError_t apply(const double2* xc, double2* yc) {
+    hipError_t e = convert<double, float>(xc, p->v32a, n, p->stream);
+    if (e) return e;
+    if ((e = scatter<float>(u, p->v32a, p->fx32, p->stream))) return e;
+    const void* tw[3] = {p->tw32[0], p->tw32[1], p->tw32[2]};
+    if ((e = launch_matvec<float>(p->g, p->t32, p->fx32, p->fy32, nullptr, 0, p->U32, p->goct32, p->chi32, tw,
+                                  p->stream)))
+      return e;
+    if ((e = gather<float>(u, p->fy32, p->v32b, nullptr, p->stream))) return e;
+    return convert<float, double>(p->v32b, yc, n, p->stream);
+  }
+  // the inner solve starts from zero and never confirms a true residual
+  hipError_t residual(const double2*, const double2*, double2*) { return hipErrorNotSupported; }
 };
 
 // The JM-VIE operator on full 6N vectors (electric, then magnetic in impedance units).
@@ -922,8 +1029,9 @@ int solve_options(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, con
   if (o.inner_restart <= 0) o.inner_restart = 20;
   if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
   if (o.restart > 4096 || o.inner_restart > 4096) return fail(p, VIE_EINVAL, "restart too large");
-  if (o.precision < 0 || o.precision > 4) return fail(p, VIE_EINVAL, "unknown precision tier");
-  if (o.precision == 1 && !p->goct32) return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
+  if (o.precision < 0 || o.precision > 5) return fail(p, VIE_EINVAL, "unknown precision tier");
+  if ((o.precision == 1 || o.precision == 5) && !p->goct32)
+    return fail(p, VIE_ESTATE, "mixed tier needs a plan built with VIE_WITH_FP32");
   if ((o.precision == 2 || o.precision == 4) && !p->net)
     return fail(p, VIE_ESTATE, "no preconditioner attached (vie_set_preconditioner)");
   if ((o.precision == 3 || o.precision == 4) && !p->circ)
@@ -1024,6 +1132,25 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
       outer.inner += si.iters;
       if (rc != VIE_OK && rc != VIE_ENOCONV) return hipErrorUnknown;
       return convert<float, double>(p->v32b, reinterpret_cast<double2*>(z), n, s);
+    };
+    struct Pc {
+      decltype(inner)& f;
+      hipError_t operator()(const void* v, void* z, Stats& st_) { return f(v, z, st_); }
+    } pc{inner};
+    status = gmres_core<double, Op64c, Pc>(p, *B.ws, A, &pc, n, B.bc, B.xc, tolc, o.restart, o.maxit,
+                                           o.use_x0 != 0, true, st);
+  } else if (o.precision == 5) {
+    // mixed tier with FP64 inner Arnoldi: the inner GMRES keeps its Krylov vectors,
+    // Gram-Schmidt and Hessenberg data in FP64 and only its products run in FP32
+    Op32in64c A32{p, u, n};
+    auto inner = [&](const void* v, void* z, Stats& outer) -> hipError_t {
+      Stats si;
+      int rc = gmres_core<double, Op32in64c, NoPrecond>(p, p->ws64i, A32, nullptr, n,
+                                                         reinterpret_cast<const double2*>(v),
+                                                         reinterpret_cast<double2*>(z), o.inner_tol,
+                                                         o.inner_restart, o.inner_restart, false, false, si);
+      outer.inner += si.iters;
+      return (rc != VIE_OK && rc != VIE_ENOCONV) ? hipErrorUnknown : hipSuccess;
     };
     struct Pc {
       decltype(inner)& f;
@@ -1160,7 +1287,7 @@ int vie_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const vi
     HIPTRY(p, dmalloc(&p->partial_full, sizeof(double2) * (partial_blocks(nfull) + 1)));
     HIPTRY(p, dmalloc(&p->sumsq_full, sizeof(double2) * 2));
   }
-  if (o.precision == 1 && !p->fx32) {
+  if ((o.precision == 1 || o.precision == 5) && !p->fx32) {
     HIPTRY(p, dmalloc(&p->fx32, sizeof(float2) * nfull));
     HIPTRY(p, dmalloc(&p->fy32, sizeof(float2) * nfull));
     HIPTRY(p, dmalloc(&p->v32a, sizeof(float2) * nfull));
@@ -1575,6 +1702,7 @@ void vie_destroy(vie_plan_t p) {
   }
   p->ws64.release();
   p->ws32.release();
+  p->ws64i.release();
   for (hipEvent_t ev : p->nev)
     if (ev) (void)hipEventDestroy(ev);
   if (p->npin) (void)hipHostFree(p->npin);

@@ -159,12 +159,14 @@ def iterations_vs_length(n3s: Sequence[int] = (128, 256, 512, 1024), d: int = 2,
     return out
 
 
-def mixed_vs_fp64(degrees: Sequence[int] = DEGREES, tol: float = 1e-8, ref_tol: float = 1e-10) -> dict:
+def mixed_vs_fp64(degrees: Sequence[int] = DEGREES, tol: float = 1e-8, ref_tol: float = 1e-10,
+                  precision: int = 1) -> dict:
     """The mixed tier against FP64 on the 8 x 8 x 32 guide (h = 50 nm, 4 x 4 core, 8-voxel
     absorbers, sigma_max = 2, z-dipole where the lossless core starts), per absorber degree:
     relative L2 distance of the two solutions, and the reflection R of each against an FP64
     reference with 64-voxel absorbers (8 x 8 x 144, same cross-section, same source plane
-    relative to the lossless part), R as in Section V-A over the lossless part."""
+    relative to the lossless part), R as in Section V-A over the lossless part.
+    precision 1: inner GMRES with FP32 Krylov vectors; 5: with FP64 Krylov vectors."""
     import torch
     out = {"degrees": list(degrees), "rel_l2": [], "R_fp64": [], "R_mixed": [], "rel_dR": [],
            "rel_res_fp64": [], "rel_res_mixed": [], "inner_iters": []}
@@ -185,7 +187,8 @@ def mixed_vs_fp64(degrees: Sequence[int] = DEGREES, tol: float = 1e-8, ref_tol: 
                 fields["ref"] = axis_field(g, x.cpu().numpy())
             else:
                 x64, i64 = plan.solve(b, tol=tol, restart=50, precision=0)
-                x32, i32 = plan.solve(b, tol=tol, restart=50, precision=1, inner_restart=20, inner_tol=1e-4)
+                x32, i32 = plan.solve(b, tol=tol, restart=50, precision=precision, inner_restart=20,
+                                      inner_tol=1e-4)
                 a64, a32 = x64.cpu().numpy(), x32.cpu().numpy()
                 out["rel_l2"].append(float(np.linalg.norm(a32 - a64) / np.linalg.norm(a64)))
                 out["rel_res_fp64"].append(i64["rel_res_true"])
@@ -633,6 +636,7 @@ if __name__ == "__main__":
     ap.add_argument("--train", type=int, default=2000, help="learned: solver-generated training pairs")
     ap.add_argument("--test", type=int, default=100, help="learned: test geometries")
     ap.add_argument("--epochs", type=int, default=8, help="learned: training epochs")
+    ap.add_argument("--operator-pairs", type=int, default=2, help="learned: (A u, u) pairs per training geometry")
     ap.add_argument("--out", default=None, help="write the JSON result here")
     ap.add_argument("--quick", action="store_true", help="every other absorber length")
     ap.add_argument("--em", action="store_true", help="electric and magnetic currents, matched absorber")
@@ -644,7 +648,7 @@ if __name__ == "__main__":
     if a.which == "learned":
         from . import learned
         st = learned.CirculantCorrectionStudy(seed=0)
-        gen = st.generate(range(a.train))
+        gen = st.generate(range(a.train), n_operator=a.operator_pairs)
         print("generated", gen, flush=True)
         t0 = time.perf_counter()
         losses = st.train(a.epochs)

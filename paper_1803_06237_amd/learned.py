@@ -120,20 +120,30 @@ class CirculantCorrectionStudy:
         b = self.plan.rhs(torch.from_numpy(inputs.transverse_dipole_field(wg)).cuda())
         return wg, b
 
-    def generate(self, seeds: Sequence[int], tol: float = 1e-8) -> dict:
-        """One solver-generated pair per training geometry."""
+    def generate(self, seeds: Sequence[int], tol: float = 1e-8, n_operator: int = 0) -> dict:
+        """One solver-generated pair per training geometry, plus n_operator pairs
+        (A u, u) per geometry with u a smooth random field on the contrast's support
+        (Gaussian filter of 1 to 4 voxels), which resemble the vectors FGMRES hands the
+        preconditioner more than a dipole right-hand side does."""
         torch = self.torch
         t0 = time.perf_counter()
         its = []
         for s in seeds:
-            _, b = self._geometry(s)
+            wg, b = self._geometry(s)
             x, info = self.plan.solve(b, tol=tol, restart=50, precision=3)
             if info["status"] != vie.VIE_OK:
                 continue
+            chi = self.plan.contrast()
             w = self.plan.apply_circulant(b)
             ph = complex(np.exp(1j * self.rng.uniform(0, 2 * np.pi)))
-            self.pairs.append((b * ph, w * ph, self.plan.contrast(), x * ph))
+            self.pairs.append((b * ph, w * ph, chi, x * ph))
             its.append(info["iters"])
+            mask = wg.core_mask()
+            for _ in range(n_operator):
+                u = torch.from_numpy(smooth_field((3,) + self.grid, mask, self.rng,
+                                                  width=float(self.rng.uniform(1.0, 4.0)))).cuda()
+                v = self.plan.matvec(u)
+                self.pairs.append((v, self.plan.apply_circulant(v), chi, u))
         torch.cuda.synchronize()
         self.gen_seconds += time.perf_counter() - t0
         return {"pairs": len(self.pairs), "seconds": round(time.perf_counter() - t0, 2),

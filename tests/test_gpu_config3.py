@@ -7,11 +7,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_mixed_tier_reproduces_fp64_observables():
+@pytest.mark.parametrize("precision", [1, 5], ids=["fp32-inner-arnoldi", "fp64-inner-arnoldi"])
+def test_mixed_tier_reproduces_fp64_observables(precision):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1803_06237_amd import experiments
-    r = experiments.mixed_vs_fp64()
+    r = experiments.mixed_vs_fp64(precision=precision)
     print(r)
     for d, l2, dR, r64, r32 in zip(r["degrees"], r["rel_l2"], r["rel_dR"], r["rel_res_fp64"], r["rel_res_mixed"]):
         assert r64 <= 1e-8 and r32 <= 1e-8, d
