@@ -151,11 +151,11 @@ def strip_measurement(steps: int):
 
 
 KERNEL_SOURCES = {
-    "k_xy64<double, 0>": ["xy64.hip", "fft_device.hpp"],
-    "k_xy64<double, 1>": ["xy64.hip", "fft_device.hpp"],
-    "k_xy64<double, 2>": ["xy64.hip", "fft_device.hpp"],
-    "k_zfwd4<double, 32, 32>": ["zpass.hip", "dft_reg.hpp", "fft_device.hpp"],
-    "k_zinv4<double, 32, 32, 0>": ["zpass.hip", "dft_reg.hpp", "fft_device.hpp"],
+    "k_xy64<double, 0>": ["xy64.hip", "fft_device.hpp", "block_maps.hpp"],
+    "k_xy64<double, 1>": ["xy64.hip", "fft_device.hpp", "block_maps.hpp"],
+    "k_xy64<double, 2>": ["xy64.hip", "fft_device.hpp", "block_maps.hpp"],
+    "k_zfwd4<double, 32, 32>": ["zpass.hip", "dft_reg.hpp", "fft_device.hpp", "block_maps.hpp"],
+    "k_zinv4<double, 32, 32, 0>": ["zpass.hip", "dft_reg.hpp", "fft_device.hpp", "block_maps.hpp"],
 }
 
 

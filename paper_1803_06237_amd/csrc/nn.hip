@@ -50,53 +50,64 @@ struct Vol {
 // ------------------------------------------------------------------ convolution
 // Y[v, o] = act(sum_t sum_i W[t][o][i] X[v + t][i]); tap t = (dz+1)*9 + (dy+1)*3 + (dx+1).
 // LDS-staged implicit GEMM on v_mfma_f32_16x16x32_bf16.  A workgroup of four waves
-// computes a tile of 2 (D) x 4 (H) x 32 (W) output voxels for up to 64 output
-// channels (grid.y picks the group of four 16-channel N-tiles); wave w takes the
-// two rows (z0 + w / 2, y0 + 2 (w % 2) + {0, 1}), i.e. four 16-voxel M-tiles.  The
-// input is consumed in chunks of 16 channels: the chunk's halo tile (4 x 6 x 34
-// voxels) and its weights for all taps and the group's output channels are staged
-// in LDS once and read by every K-step.  One MFMA K-step covers two taps of the
-// chunk (K = 2 x 16): lanes 0-31 take tap t, lanes 32-63 tap t + 1 (the 28th tap is
-// zero).  Halo layout [half][voxel][8 channels] (half = channels 0-7 or 8-15), so
-// the 16 lanes of one fragment row read 256 contiguous bytes; weight layout
-// [tap pair][N-tile][lane] of 16-byte B fragments, so a wave reads 1 KiB contiguous.
-constexpr int kCtx = 32, kCty = 4, kCtz = 2;             // output tile (W, H, D)
-constexpr int kHx = kCtx + 2, kHy = kCty + 2, kHz = kCtz + 2;
-constexpr int kHvox = kHx * kHy * kHz;                   // 816 halo voxels
+// computes a tile of TZ (D) x 4 (H) x 16 MT (W) output voxels for up to 64 output
+// channels (grid.y picks the group of NT 16-channel N-tiles).  Wave w takes the
+// TZ rows (z0 + (TZ == 2 ? w / 2 : 0), y0 + ...) assigned to it, i.e. TZ * MT / ...
+// 16-voxel M-tiles: with TZ = 2, MT = 2 (the 2 x 4 x 32 tile of the large levels)
+// four M-tiles per wave; with TZ = 1, MT = 1 (the 1 x 4 x 16 tile that keeps the
+// small levels' launches wide) one.  The input is consumed in chunks of 16
+// channels: the chunk's halo tile and its weights for all taps and the group's
+// output channels are staged in LDS once and read by every K-step.  One MFMA
+// K-step covers two taps of the chunk (K = 2 x 16): lanes 0-31 take tap t, lanes
+// 32-63 tap t + 1 (the 28th tap is zero).  Halo layout [half][voxel][8 channels]
+// (half = channels 0-7 or 8-15), so the 16 lanes of one fragment row read 256
+// contiguous bytes; weight layout [tap pair][N-tile][lane] of 16-byte B fragments,
+// so a wave reads 1 KiB contiguous.
+constexpr int kCty = 4;                                  // output tile height (H)
 constexpr int kPairs = 14;                               // tap pairs of a 3 x 3 x 3 kernel
+template <int TZ, int MT> struct ConvTile {
+  static constexpr int tx = 16 * MT, ty = kCty, tz = TZ;
+  static constexpr int hx = tx + 2, hy = ty + 2, hz = tz + 2;
+  static constexpr int hvox = hx * hy * hz;
+  static constexpr int rows = TZ;                        // rows (z, y pairs) per wave: TZ
+};
 
 // dynamic LDS bytes of k_conv2 for nt N-tiles
+template <int TZ, int MT>
 static inline size_t conv2_lds(int taps, int nt) {
-  return (size_t)2 * kHvox * 8 * 2 + (size_t)(taps == 1 ? 1 : kPairs) * nt * 64 * 16;
+  return (size_t)2 * ConvTile<TZ, MT>::hvox * 8 * 2 + (size_t)(taps == 1 ? 1 : kPairs) * nt * 64 * 16;
 }
 
-template <int TAPS, int NT>
+template <int TAPS, int NT, int TZ, int MT>
 __global__ __launch_bounds__(256) void k_conv2(const bf16_t* __restrict__ X, int xcs, int xco, int Cin,
                                                const bf16_t* __restrict__ Wt, int Cout, bf16_t* __restrict__ Y,
                                                int ycs, int yco, float* __restrict__ Yf, Vol vol, int relu,
                                                const bf16_t* __restrict__ mask, int mcs, int mco, int g0) {
+  using Tl = ConvTile<TZ, MT>;
+  constexpr int kHx = Tl::hx, kHy = Tl::hy, kHvox = Tl::hvox;
+  constexpr int MI = TZ * MT;                  // M-tiles per wave
   extern __shared__ __attribute__((aligned(16))) unsigned char conv_smem[];
   bf16_t* tile = reinterpret_cast<bf16_t*>(conv_smem);
   u4v* wfrag = reinterpret_cast<u4v*>(conv_smem + (size_t)2 * kHvox * 8 * 2);
   constexpr int NPAIR = TAPS == 1 ? 1 : kPairs;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ntx = (vol.W + kCtx - 1) / kCtx, nty = (vol.H + kCty - 1) / kCty;
+  const int ntx = (vol.W + Tl::tx - 1) / Tl::tx, nty = (vol.H + Tl::ty - 1) / Tl::ty;
   int b = blockIdx.x;
   const int tx = b % ntx;
   b /= ntx;
   const int ty = b % nty;
   const int tz = b / nty;
-  const int x0 = tx * kCtx, y0 = ty * kCty, z0 = tz * kCtz;
+  const int x0 = tx * Tl::tx, y0 = ty * Tl::ty, z0 = tz * Tl::tz;
   const int nt0 = (g0 + blockIdx.y) * 4;       // first N-tile of this workgroup's group
-  constexpr int nt = NT;
   const int m = lane & 15, kq = lane >> 4;     // fragment row / K-quarter
   const int half = kq & 1, second = kq >> 1;   // channel half, which tap of the pair
-  const int wz = wave >> 1, wy = 2 * (wave & 1);
+  // wave rows: TZ = 2: (wave / 2, 2 (wave % 2) + {0, 1}); TZ = 1: (0, wave)
+  const int wz = TZ == 2 ? wave >> 1 : 0, wy = TZ == 2 ? 2 * (wave & 1) : wave;
   // this lane's halo row for tap offset 0 (the halo corner) of its first M-tile
   const int lds_lane = (half * kHvox + (wz * kHy + wy) * kHx + m) * 8;
-  f4v acc[4][NT];
+  f4v acc[MI][NT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[i][t] = f4v{0.f, 0.f, 0.f, 0.f};
   const int nchunk = Cin / 16;
@@ -139,28 +150,28 @@ __global__ __launch_bounds__(256) void k_conv2(const bf16_t* __restrict__ X, int
 #pragma unroll
       for (int t = 0; t < NT; ++t) bfr[t] = __builtin_bit_cast(bf8v, wfrag[(tp * NT + t) * 64 + lane]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        // M-tile i: row wy + (i >> 1), voxels 16 (i & 1) .. + 15
-        const int ao = lds_lane + (off + (i >> 1) * kHx + 16 * (i & 1)) * 8;
+      for (int i = 0; i < MI; ++i) {
+        // M-tile i: row (i / MT) of the wave, voxels 16 (i % MT) .. + 15
+        const int ao = lds_lane + (off + (i / MT) * kHx + 16 * (i % MT)) * 8;
         const bf8v a = __builtin_bit_cast(bf8v, *reinterpret_cast<const u4v*>(tile + ao));
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[t], acc[i][t], 0, 0, 0);
       }
     }
   }
-  // D[row = 4 kq + r][col = m]: voxel 16 (i & 1) + 4 kq + r of row (z0 + wz, y0 + wy + (i >> 1))
+  // D[row = 4 kq + r][col = m]: voxel 16 (i % MT) + 4 kq + r of wave row i / MT
   const int zz = z0 + wz;
   if (zz >= vol.D) return;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int yy = y0 + wy + (i >> 1);
+  for (int i = 0; i < MI; ++i) {
+    const int yy = y0 + wy + i / MT;
     if (yy >= vol.H) continue;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int n = (nt0 + t) * 16 + m;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int xx = x0 + 16 * (i & 1) + 4 * kq + r;
+        const int xx = x0 + 16 * (i % MT) + 4 * kq + r;
         if (xx >= vol.W) continue;
         const long vo = ((long)zz * vol.H + yy) * vol.W + xx;
         float val = acc[i][t][r];
@@ -433,29 +444,32 @@ static inline AdamK adam_constants(int t, float lr) {
 static inline int gblocks(long n) { return (int)std::min<long>(4096, (n + 255) / 256); }
 
 // k_conv2 may use more than 64 KiB of dynamic LDS (83.5 KiB with four N-tiles)
-template <int TAPS>
-static hipError_t allow_conv_lds_taps() {
+template <int TAPS, int TZ, int MT>
+static hipError_t allow_conv_lds_shape() {
   const auto a = hipFuncAttributeMaxDynamicSharedMemorySize;
   hipError_t e;
-  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 1>, a, (int)conv2_lds(TAPS, 1)))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 2>, a, (int)conv2_lds(TAPS, 2)))) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 3>, a, (int)conv2_lds(TAPS, 3)))) return e;
-  return hipFuncSetAttribute((const void*)k_conv2<TAPS, 4>, a, (int)conv2_lds(TAPS, 4));
+  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 1, TZ, MT>, a, (int)conv2_lds<TZ, MT>(TAPS, 1)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 2, TZ, MT>, a, (int)conv2_lds<TZ, MT>(TAPS, 2)))) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_conv2<TAPS, 3, TZ, MT>, a, (int)conv2_lds<TZ, MT>(TAPS, 3)))) return e;
+  return hipFuncSetAttribute((const void*)k_conv2<TAPS, 4, TZ, MT>, a, (int)conv2_lds<TZ, MT>(TAPS, 4));
 }
 static hipError_t allow_conv_lds() {
-  const hipError_t e = allow_conv_lds_taps<27>();
-  return e ? e : allow_conv_lds_taps<1>();
+  hipError_t e;
+  if ((e = allow_conv_lds_shape<27, 2, 2>())) return e;
+  if ((e = allow_conv_lds_shape<1, 2, 2>())) return e;
+  if ((e = allow_conv_lds_shape<27, 1, 1>())) return e;
+  return allow_conv_lds_shape<1, 1, 1>();
 }
 
-template <int TAPS>
+template <int TAPS, int TZ, int MT>
 static void conv2_launch_nt(int nt, dim3 grid, int g0, hipStream_t s, const bf16_t* X, int xcs, int xco, int Cin,
                             const bf16_t* W, int Cout, bf16_t* Y, int ycs, int yco, float* Yf, Vol vol, int relu,
                             const bf16_t* mask, int mcs, int mco) {
-  const size_t lds = conv2_lds(TAPS, nt);
+  const size_t lds = conv2_lds<TZ, MT>(TAPS, nt);
 #define VIE_CONV2(NTV)                                                                                           \
   if (nt == NTV)                                                                                                 \
-    hipLaunchKernelGGL((k_conv2<TAPS, NTV>), grid, dim3(256), lds, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, \
-                       vol, relu, mask, mcs, mco, g0);
+    hipLaunchKernelGGL((k_conv2<TAPS, NTV, TZ, MT>), grid, dim3(256), lds, s, X, xcs, xco, Cin, W, Cout, Y, ycs,  \
+                       yco, Yf, vol, relu, mask, mcs, mco, g0);
   VIE_CONV2(1)
   VIE_CONV2(2)
   VIE_CONV2(3)
@@ -463,20 +477,35 @@ static void conv2_launch_nt(int nt, dim3 grid, int g0, hipStream_t s, const bf16
 #undef VIE_CONV2
 }
 
-// Output-channel groups of four N-tiles in one launch, a smaller last group in a second.
+// Output-channel groups of four N-tiles in one launch, a smaller last group in a
+// second.  The 2 x 4 x 32 voxel tile where it gives at least 512 workgroups, else the
+// 1 x 4 x 16 tile (the small levels of the network).
 hipError_t conv_launch(int taps, const bf16_t* X, int xcs, int xco, int Cin, const bf16_t* W, int Cout, bf16_t* Y,
                        int ycs, int yco, float* Yf, Vol vol, int relu, const bf16_t* mask, int mcs, int mco,
                        hipStream_t s) {
   static const hipError_t lds_ok = allow_conv_lds();
   if (lds_ok) return lds_ok;
-  const long tiles = (long)((vol.D + kCtz - 1) / kCtz) * ((vol.H + kCty - 1) / kCty) * ((vol.W + kCtx - 1) / kCtx);
+  const long big = (long)((vol.D + 1) / 2) * ((vol.H + kCty - 1) / kCty) * ((vol.W + 31) / 32);
+  const long small = (long)vol.D * ((vol.H + kCty - 1) / kCty) * ((vol.W + 15) / 16);
+  const bool use_big = big >= 512;
   const int ntiles = Cout / 16, full = ntiles / 4, rest = ntiles % 4;
   auto go = [&](int nt, int groups, int g0) {
-    const dim3 grid((unsigned)tiles, (unsigned)groups);
-    if (taps == 27)
-      conv2_launch_nt<27>(nt, grid, g0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu, mask, mcs, mco);
-    else
-      conv2_launch_nt<1>(nt, grid, g0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu, mask, mcs, mco);
+    const dim3 grid((unsigned)(use_big ? big : small), (unsigned)groups);
+    if (use_big) {
+      if (taps == 27)
+        conv2_launch_nt<27, 2, 2>(nt, grid, g0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu, mask, mcs,
+                                  mco);
+      else
+        conv2_launch_nt<1, 2, 2>(nt, grid, g0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu, mask, mcs,
+                                 mco);
+    } else {
+      if (taps == 27)
+        conv2_launch_nt<27, 1, 1>(nt, grid, g0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu, mask, mcs,
+                                  mco);
+      else
+        conv2_launch_nt<1, 1, 1>(nt, grid, g0, s, X, xcs, xco, Cin, W, Cout, Y, ycs, yco, Yf, vol, relu, mask, mcs,
+                                 mco);
+    }
   };
   if (full) go(4, full, 0);
   if (rest) go(rest, 1, full);

@@ -648,13 +648,14 @@ if __name__ == "__main__":
     if a.which == "learned":
         from . import learned
         st = learned.CirculantCorrectionStudy(seed=0)
-        gen = st.generate(range(a.train), n_operator=a.operator_pairs)
+        say = lambda m: print(m, flush=True)
+        gen = st.generate(range(a.train), n_operator=a.operator_pairs, progress=say)
         print("generated", gen, flush=True)
         t0 = time.perf_counter()
-        losses = st.train(a.epochs)
+        losses = st.train(a.epochs, progress=say)
         train_s = time.perf_counter() - t0
         print("losses", losses, "train s", round(train_s, 1), flush=True)
-        ev = st.evaluate(range(10000, 10000 + a.test))
+        ev = st.evaluate(range(10000, 10000 + a.test), progress=say)
         res = {"generate": gen, "epochs": a.epochs, "losses": losses, "train_seconds": round(train_s, 2),
                "test": ev["mean"], "per_seed": ev["per_seed"]}
         print(json.dumps(ev["mean"]), flush=True)

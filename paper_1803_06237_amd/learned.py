@@ -120,7 +120,7 @@ class CirculantCorrectionStudy:
         b = self.plan.rhs(torch.from_numpy(inputs.transverse_dipole_field(wg)).cuda())
         return wg, b
 
-    def generate(self, seeds: Sequence[int], tol: float = 1e-8, n_operator: int = 0) -> dict:
+    def generate(self, seeds: Sequence[int], tol: float = 1e-8, n_operator: int = 0, progress=None) -> dict:
         """One solver-generated pair per training geometry, plus n_operator pairs
         (A u, u) per geometry with u a smooth random field on the contrast's support
         (Gaussian filter of 1 to 4 voxels), which resemble the vectors FGMRES hands the
@@ -138,6 +138,9 @@ class CirculantCorrectionStudy:
             ph = complex(np.exp(1j * self.rng.uniform(0, 2 * np.pi)))
             self.pairs.append((b * ph, w * ph, chi, x * ph))
             its.append(info["iters"])
+            if progress is not None and len(its) % 100 == 0:
+                progress(f"{len(its)} geometries, {len(self.pairs)} pairs, "
+                         f"{time.perf_counter() - t0:.1f} s")
             mask = wg.core_mask()
             for _ in range(n_operator):
                 u = torch.from_numpy(smooth_field((3,) + self.grid, mask, self.rng,
@@ -149,7 +152,7 @@ class CirculantCorrectionStudy:
         return {"pairs": len(self.pairs), "seconds": round(time.perf_counter() - t0, 2),
                 "circulant_iters_mean": float(np.mean(its)) if its else None}
 
-    def train(self, epochs: int, lr: float = 1e-3, batch: int = 4, lr_decay: float = 0.8) -> List[float]:
+    def train(self, epochs: int, lr: float = 1e-3, batch: int = 4, lr_decay: float = 0.8, progress=None) -> List[float]:
         losses = []
         order = np.arange(len(self.pairs))
         for _ in range(epochs):
@@ -160,10 +163,12 @@ class CirculantCorrectionStudy:
                 ep.append(self.net.train_step_base([p[0] for p in sel], [p[1] for p in sel],
                                                    [p[2] for p in sel], [p[3] for p in sel], lr))
             losses.append(float(np.mean(ep)))
+            if progress is not None:
+                progress(f"epoch {len(losses)} loss {losses[-1]:.4f}")
             lr *= lr_decay
         return losses
 
-    def evaluate(self, seeds: Sequence[int], tol: float = 1e-8, restart: int = 50) -> dict:
+    def evaluate(self, seeds: Sequence[int], tol: float = 1e-8, restart: int = 50, progress=None) -> dict:
         """Iterations and wall time to tol on unseen geometries: FP64 GMRES (0), mixed
         FGMRES (1), circulant FGMRES (3) and the network correcting the circulant (4);
         each tier's residual recomputed with the FP64 product."""
@@ -188,6 +193,8 @@ class CirculantCorrectionStudy:
                              "fallback": info["fallback"], "status": info["status"],
                              "rel_res_fp64": (torch.linalg.norm(r) / torch.linalg.norm(b)).item()}
             rows.append(row)
+            if progress is not None and len(rows) % 10 == 0:
+                progress(f"{len(rows)} test geometries")
         self.plan.set_preconditioner(None)
         agg = {}
         for name in ("fp64", "mixed", "circulant", "learned_circulant"):
