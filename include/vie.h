@@ -258,14 +258,18 @@ int vie_circulant_apply(vie_plan_t plan, const vie_c128* r, vie_c128* z);
 /*
  * Launch-shape tuning.  Unless VIE_NO_AUTOTUNE is given, vie_plan times the
  * candidate shapes of the product's kernels on the plan's own buffers (two
- * untimed and five timed launches each, HIP events, in three interleaved rounds
- * of which each candidate keeps its best) and keeps the fastest:
+ * untimed and five timed whole products each, HIP events, in three interleaved
+ * rounds of which each candidate keeps its best) and keeps the fastest:
  * pencils per workgroup of the four-step z passes, or the generic z passes
- * (forward and inverse timed together; circulant lengths 512 to 4096 have
- * four-step shapes) and, for 64 x 64 circulant cross-sections, the xy pass variant
- * (0: full plane in LDS; 1: x-frequency halves, two workgroups per CU; 2: full
- * plane with 512 threads and private exchange areas, one workgroup per CU).  Choices
- * are cached per (device, grid, precision) for the life of the process.
+ * (circulant lengths 512 to 4096 have four-step shapes), crossed with, for
+ * 64 x 64 circulant cross-sections, the xy pass variant (0: full plane in LDS;
+ * 1: x-frequency halves, two workgroups per CU; 2: full plane with 512 threads
+ * and private exchange areas, one workgroup per CU); the pairs are timed jointly
+ * because the z pass's writes decide what the xy pass finds in cache.  Choices
+ * are cached per (device, grid, precision) for the life of the process, and in the
+ * file named by the environment variable VIE_TUNE_CACHE (default
+ * $XDG_CACHE_HOME or $HOME/.cache, vie-mi355x/tune.txt; empty: none), keyed by
+ * the GPU architecture and CU count, the grid and the precision.
  * vie_get_tune: the current choice for precision 0 (FP64) or 1 (FP32):
  *   *xy_variant (-1 when the grid does not use the 64 x 64 kernel),
  *   *z_pencils (0 when the z passes use the generic kernels).

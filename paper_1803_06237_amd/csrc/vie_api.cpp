@@ -257,11 +257,11 @@ bool pick_tune(const Geom& g, size_t budget, size_t zbudget, Tune* t) {
 }
 
 // ---- plan-time tuning of launch shapes ----------------------------------------
-// Candidates: the four-step z passes' pencils per workgroup (with the forward and
-// the inverse pass timed together, they share the choice) and the 64 x 64 xy
-// pass variant.  Each candidate runs two untimed and five timed launches between
-// HIP events; the fastest wins.  Results are kept per (device, grid, precision)
-// for the life of the process.
+// Candidates: the four-step z passes' pencils per workgroup (the forward and the
+// inverse pass share the choice) and the 64 x 64 xy pass variant.  Each candidate
+// runs two untimed and five timed whole products (all three passes) between HIP
+// events; the fastest wins.  Results are kept per (device, grid, precision) for
+// the life of the process and in the tuner cache file.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int>, Tune> g_tune_cache;
 
@@ -386,53 +386,53 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
   // round: single rounds let launch noise decide between shapes within 1 % of
   // each other, and the choice then changed from one process to the next.
   constexpr int kRounds = 3;
-  if (!e && t->z4) {
-    int opts[8];
-    const int n = z4_pencil_options<T>(g.M3, opts, 8);
-    // candidates: the four-step pencil counts, then the generic LDS passes (the
-    // 64-value shapes of long pencils run at low occupancy in FP64)
-    float best[9];
-    for (int i = 0; i <= n; ++i) best[i] = INFINITY;
-    for (int r = 0; r < kRounds && !e; ++r) {
-      for (int i = 0; i <= n && !e; ++i) {
+  // Candidates: the four-step pencil counts and the generic LDS z passes (the
+  // 64-value shapes of long pencils run at low occupancy in FP64), crossed with
+  // the xy variants of 64 x 64 planes.  They are timed jointly, as whole
+  // back-to-back products: the z pass's write pattern decides what the xy pass
+  // finds in L2 and the Infinity Cache, so a pass timed alone, or with events
+  // between the passes, can rank the shapes differently (FP64 32x32x512: with
+  // events between the passes 8 pencils per workgroup look 7 us faster than 4;
+  // back to back, 4 stay ahead).
+  std::vector<Tune> cand;
+  {
+    std::vector<Tune> zc;
+    if (t->z4) {
+      int opts[8];
+      const int n = z4_pencil_options<T>(g.M3, opts, 8);
+      for (int i = 0; i < n; ++i) {
         Tune c = *t;
-        if (i < n) {
-          c.zp = opts[i];
-        } else {
-          c.z4 = 0;
-          c.zp = 0;
-        }
-        float ms = 0, ms2 = 0;
-        e = time_passes<T>(g, c, 0, 0, x, y, U, goct, chi, tw, s, &ms);
-        if (!e) e = time_passes<T>(g, c, 2, 2, x, y, U, goct, chi, tw, s, &ms2);
-        if (!e && ms + ms2 < best[i]) best[i] = ms + ms2;
+        c.zp = opts[i];
+        zc.push_back(c);
       }
-    }
-    int bi = 0;
-    for (int i = 1; i <= n; ++i)
-      if (best[i] < best[bi]) bi = i;
-    if (bi < n) {
-      t->zp = opts[bi];
+      Tune c = *t;
+      c.z4 = 0;
+      c.zp = 0;
+      zc.push_back(c);
     } else {
-      t->z4 = 0;
-      t->zp = 0;
+      zc.push_back(*t);
     }
+    const int nv = g.M1 == 64 && g.M2 == 64 ? 3 : 1;
+    for (const Tune& z : zc)
+      for (int v = 0; v < nv; ++v) {
+        Tune c = z;
+        if (nv > 1) c.xyv = v;
+        cand.push_back(c);
+      }
   }
-  if (!e && g.M1 == 64 && g.M2 == 64) {
-    float best[3] = {INFINITY, INFINITY, INFINITY};
+  if (cand.size() > 1) {
+    std::vector<float> best(cand.size(), INFINITY);
     for (int r = 0; r < kRounds && !e; ++r) {
-      for (int v = 0; v < 3 && !e; ++v) {
-        Tune c = *t;
-        c.xyv = v;
+      for (size_t i = 0; i < cand.size() && !e; ++i) {
         float ms = 0;
-        e = time_passes<T>(g, c, 1, 1, x, y, U, goct, chi, tw, s, &ms);
-        if (!e && ms < best[v]) best[v] = ms;
+        e = time_passes<T>(g, cand[i], 0, 2, x, y, U, goct, chi, tw, s, &ms);
+        if (!e && ms < best[i]) best[i] = ms;
       }
     }
-    int bv = 0;
-    for (int v = 1; v < 3; ++v)
-      if (best[v] < best[bv]) bv = v;
-    t->xyv = bv;
+    size_t bi = 0;
+    for (size_t i = 1; i < cand.size(); ++i)
+      if (best[i] < best[bi]) bi = i;
+    if (!e) *t = cand[bi];
   }
   if (x) (void)hipFree(x);
   if (y) (void)hipFree(y);
