@@ -206,7 +206,15 @@ int vie_solve_noalloc(vie_plan_t plan, const vie_c128* b, vie_c128* x, double to
  * synchronised.  Returns VIE_OK when every system converged, else the first
  * non-OK status (each system's status is in infos[s].status).  A plan may appear
  * several times (same operator, different right-hand sides): each system gets
- * its own intermediate buffers.
+ * its own intermediate buffers.  As in vie_solve, each system's Krylov vectors hold
+ * only its support columns (n_s = 3 |S_s| n3 values; the system solved is
+ * A_SS x_S = b_S - (A b_off)_S, and x = b off the support), and every product is
+ * a batched scatter into full-length buffers, the three passes and a batched
+ * gather.  Device memory per system is about 16 ((restart + 1 [+ restart when
+ * flexible] + 3) n_s + 2 (3 N_s) + 3 n1 n2 M3) bytes, the last term the
+ * intermediate of the passes, and the mixed tier adds half as much again for
+ * its FP32 level (inner_restart + 3 vectors of n_s).  A right-hand side with a
+ * non-finite value gives VIE_EINVAL.
  */
 int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* rhs, vie_c128* const* x, int count,
                     double tol, const vie_solve_opts* opts, vie_solve_info* infos);

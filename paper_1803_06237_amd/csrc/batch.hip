@@ -22,6 +22,7 @@
 
 #include "../../include/vie.h"
 #include "fft_device.hpp"
+#include "krylov.hpp"
 #include "vie_internal.hpp"
 
 namespace vie {
@@ -93,6 +94,18 @@ struct KDesc {
   int* iters;       // accumulated steps
   double* est;      // residual estimate |g_{k}| / ||b||
   double tol;
+};
+
+// Support compression of one system: Krylov vectors hold the 3 s n3 values of the
+// support columns, comp[(a s + p) n3 + i3] = full[a][col[p]][i3], and the product
+// runs on the full-length buffers fx (zero off the support) and fy.
+struct SDesc {
+  const int* col;   // s increasing column indices i1 n2 + i2
+  int s;
+  int n3;
+  long n12;
+  void* fx;
+  void* fy;
 };
 
 // vector selector: 0 -> V_j, 1 -> Z_j, 2 -> x, 3 -> b, 4 -> r
@@ -413,6 +426,61 @@ __global__ __launch_bounds__(kT) void k_b_copy(const KDesc* __restrict__ ds, con
   }
 }
 
+__device__ __forceinline__ long full_index(const SDesc& S, long e) {
+  const long row = e / S.n3;
+  const int t = (int)(e - row * S.n3);
+  const int a = (int)(row / S.s), p = (int)(row - (long)a * S.s);
+  return ((long)a * S.n12 + S.col[p]) * S.n3 + t;
+}
+
+// fx on the support = the compressed vector selected by (which, j); the entries
+// off the support stay as they are (zero)
+template <typename T>
+__global__ __launch_bounds__(kT) void k_b_scatter(const KDesc* __restrict__ d, const SDesc* __restrict__ sd,
+                                                  const int* __restrict__ prefix, int nsys, int total, int which,
+                                                  int j, int act_sel) {
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_item(prefix, nsys, item);
+    const KDesc& D = d[s];
+    if ((act_sel ? *D.act0 : *D.act) == 0) continue;
+    const SDesc& S = sd[s];
+    const cx<T>* src = vsel<T>(D, which, j);
+    cx<T>* fx = (cx<T>*)S.fx;
+    const long e0 = (long)(item - prefix[s]) * kC + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const long e = e0 + (long)k * kT;
+      if (e < D.n) fx[full_index(S, e)] = src[e];
+    }
+  }
+}
+
+// the compressed vector selected by (which, j) = fy on the support; sub = 1:
+// = b - fy on the support (the residual of the cycle start)
+template <typename T>
+__global__ __launch_bounds__(kT) void k_b_gather(const KDesc* __restrict__ d, const SDesc* __restrict__ sd,
+                                                 const int* __restrict__ prefix, int nsys, int total, int which,
+                                                 int j, int sub, int act_sel) {
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_item(prefix, nsys, item);
+    const KDesc& D = d[s];
+    if ((act_sel ? *D.act0 : *D.act) == 0) continue;
+    const SDesc& S = sd[s];
+    cx<T>* dst = vsel<T>(D, which, j);
+    const cx<T>* b = (const cx<T>*)D.b;
+    const cx<T>* fy = (const cx<T>*)S.fy;
+    const long e0 = (long)(item - prefix[s]) * kC + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const long e = e0 + (long)k * kT;
+      if (e < D.n) {
+        const cx<T> v = fy[full_index(S, e)];
+        dst[e] = sub ? cx<T>{b[e].x - v.x, b[e].y - v.y} : v;
+      }
+    }
+  }
+}
+
 }  // namespace vie
 
 // =============================================================================
@@ -454,8 +522,11 @@ struct BatchLevel {         // one Krylov level (outer FP64 or inner FP32) for t
   }
 };
 
-// matvec descriptors for one level: step (V_j or Z_j -> V_{j+1}) and residual (x -> r)
+// matvec descriptors for one level: step (V_j or Z_j -> V_{j+1}) and residual (x -> r),
+// both on the full-length buffers of the support descriptors
 struct PassSet {
+  std::vector<SDesc> h_sd;        // per system, filled before build_passes
+  SDesc* d_sd = nullptr;
   PassDesc* d_step = nullptr;
   PassDesc* d_res = nullptr;
   std::vector<PassDesc> h_step, h_res;
@@ -519,12 +590,16 @@ hipError_t build_level(BatchLevel<T>& L, const std::vector<long>& n, int m, bool
     D.n = n[s];
     D.nchunk = (int)((n[s] + kC - 1) / kC);
     L.cpre[s + 1] = L.cpre[s] + D.nchunk;
-    if ((e = L.alloc(&D.V, sizeof(cx<T>) * (size_t)n[s] * (m + 1)))) return e;
-    if (flex && (e = L.alloc(&D.Z, sizeof(cx<T>) * (size_t)n[s] * m))) return e;
+    // (a system without support has length 0 and no chunks; its buffers keep one
+    // element so every pointer is valid)
+    const size_t len = n[s] > 0 ? (size_t)n[s] : 1;
+    const size_t nch = D.nchunk > 0 ? (size_t)D.nchunk : 1;
+    if ((e = L.alloc(&D.V, sizeof(cx<T>) * len * (m + 1)))) return e;
+    if (flex && (e = L.alloc(&D.Z, sizeof(cx<T>) * len * m))) return e;
     D.x = x[s];
     D.b = b[s];
-    if ((e = L.alloc(&D.r, sizeof(cx<T>) * (size_t)n[s]))) return e;
-    if ((e = L.alloc((void**)&D.partial, sizeof(double2) * (size_t)(m + 1) * D.nchunk))) return e;
+    if ((e = L.alloc(&D.r, sizeof(cx<T>) * len))) return e;
+    if ((e = L.alloc((void**)&D.partial, sizeof(double2) * (size_t)(m + 1) * nch))) return e;
     double2* small = nullptr;
     const size_t per = (size_t)(m + 2) * 2 + 2 + (size_t)(m + 1) * m + 3 * (size_t)(m + 1);
     if ((e = L.alloc((void**)&small, sizeof(double2) * per))) return e;
@@ -572,21 +647,20 @@ hipError_t build_passes(vie_batch_s* B, PassSet& PS, const BatchLevel<T>& L, std
     pd.chi = dbl ? P.chi64 : P.chi32;
     pd.twz = dbl ? P.tw64[2] : P.tw32[2];
     pd.twx = dbl ? P.tw64[0] : P.tw32[0];
+    // the products read fx and write fy; the batched scatter and gather around
+    // them move the compressed Krylov vectors
     pd.active = D.act;
-    pd.xb = L.flex ? D.Z : D.V;
-    pd.xs = D.n;
-    pd.yb = D.V;
-    pd.ys = D.n;
+    pd.xb = PS.h_sd[s].fx;
+    pd.xs = 0;
+    pd.yb = PS.h_sd[s].fy;
+    pd.ys = 0;
     pd.b = nullptr;
     PS.h_step[s] = pd;
-    pd.xb = D.x;
-    pd.xs = 0;
-    pd.yb = D.r;
-    pd.ys = 0;
-    pd.b = D.b;
     pd.active = D.act0;
     PS.h_res[s] = pd;
   }
+  if ((e = alloc((void**)&PS.d_sd, sizeof(SDesc) * n))) return e;
+  if ((e = hipMemcpy(PS.d_sd, PS.h_sd.data(), sizeof(SDesc) * n, hipMemcpyHostToDevice))) return e;
   // z groups
   for (int s = 0; s < n; ++s) {
     int A, Bv, Pp;
@@ -644,15 +718,21 @@ hipError_t build_passes(vie_batch_s* B, PassSet& PS, const BatchLevel<T>& L, std
   return hipSuccess;
 }
 
-// Batched matvec: residual = false: V_{j+1} = A (V_j or Z_j), systems gated by
-// their step flags; true: r = b - A x, gated by the cycle flags.
+// Batched matvec on compressed vectors: residual = false: V_{j+1} = A (V_j or
+// Z_j), systems gated by their step flags; true: r = b - A x, gated by the cycle
+// flags.  Scatter into fx, the three passes fx -> fy, gather from fy.
 template <typename T>
 hipError_t batch_matvec(vie_batch_s* B, PassSet& PS, const BatchLevel<T>& L, bool residual, int j) {
   hipStream_t s = B->stream;
   hipError_t e;
-  const int mode = residual ? 1 : 0;
-  const int jx = residual ? 0 : j, jy = residual ? 0 : j + 1;
+  const int mode = 0;
+  const int jx = 0, jy = 0;
   const bool dbl = sizeof(T) == 8;
+  const int act_sel = residual ? 1 : 0;
+  const int gsz = L.ctotal < 4096 ? (L.ctotal > 0 ? L.ctotal : 1) : 4096;
+  hipLaunchKernelGGL((k_b_scatter<T>), dim3(gsz), dim3(kT), 0, s, L.d, PS.d_sd, L.d_cpre, L.nsys, L.ctotal,
+                     residual ? 2 : (L.flex ? 1 : 0), residual ? 0 : j, act_sel);
+  if ((e = hipGetLastError())) return e;
   for (int which = 0; which < 3; ++which) {
     if (which == 1) {
       if (PS.xytotal > 0 &&
@@ -682,7 +762,9 @@ hipError_t batch_matvec(vie_batch_s* B, PassSet& PS, const BatchLevel<T>& L, boo
         return e;
     }
   }
-  return hipSuccess;
+  hipLaunchKernelGGL((k_b_gather<T>), dim3(gsz), dim3(kT), 0, s, L.d, PS.d_sd, L.d_cpre, L.nsys, L.ctotal,
+                     residual ? 4 : 0, residual ? 0 : j + 1, residual ? 1 : 0, act_sel);
+  return hipGetLastError();
 }
 
 inline int grid_for(int total) { return total < 4096 ? (total > 0 ? total : 1) : 4096; }
@@ -737,7 +819,8 @@ hipError_t enqueue_cycle(vie_batch_s* B, BatchLevel<T>& L, PassSet& PS, int) {
       for (int i = 0; i < L.nsys; ++i) {
         if (!B->on[i]) continue;
         const KDesc& D = L.h[i];
-        if ((e = circ_apply(B->circ[i], (const double2*)D.V + (long)j * D.n, (double2*)D.Z + (long)j * D.n, s)))
+        if ((e = circ_apply_rows(B->circ[i], (const double2*)D.V + (long)j * D.n, (double2*)D.Z + (long)j * D.n,
+                                 s)))
           return e;
       }
     }
@@ -779,7 +862,8 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
   B.circ_tier = o.precision == 3;
   if (B.circ_tier) o.use_graph = 0;   // the active set is chosen on the host per cycle
   B.circ.assign(count, nullptr);
-  std::vector<long> n(count);
+  std::vector<long> n(count), nfull(count);
+  std::vector<Support> sup(count);
   for (int s = 0; s < count; ++s) {
     SysPlan& P = B.sp[s];
     hipStream_t st;
@@ -792,7 +876,12 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
     if (B.mixed && !P.goct32) return VIE_ESTATE;
     if (B.circ_tier && !(B.circ[s] = plan_circ(plans[s]))) return VIE_ESTATE;
     if (s == 0) user_stream = st;
-    n[s] = 3 * P.g.N;
+    const int* col = nullptr;
+    int ns = 0;
+    if ((rc = plan_support(plans[s], &col, &ns))) return rc;
+    sup[s] = Support{col, ns, (long)P.g.n1 * P.g.n2, P.g.n3};
+    nfull[s] = 3 * P.g.N;
+    n[s] = sup[s].size();   // Krylov vectors hold the support columns only
   }
   // the batch runs on a stream of its own (graph capture needs a non-default
   // stream), ordered after the caller's stream, and returns synchronised
@@ -801,10 +890,6 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
   hipStream_t s = B.stream;
   std::vector<const void*> bptr(count);
   std::vector<void*> xptr(count);
-  for (int i = 0; i < count; ++i) {
-    bptr[i] = rhs[i];
-    xptr[i] = x[i];
-  }
   int status = VIE_OK;
   int* act = nullptr;    // cycle flags (outer)
   int* hflags = nullptr;
@@ -842,15 +927,99 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
     }
   }
   BTRY(hipHostMalloc(&hflags, sizeof(int) * count * 4 + sizeof(double) * count * 4, hipHostMallocDefault));
+  // Support compression (as in vie_solve): off the support A is the identity, so
+  // x = b there; on it the system is A_SS x_S = b_S - (A b_off)_S with b_off = b
+  // off the support.  Per system: full-length product buffers fx (zero off the
+  // support) and fy, the compressed right-hand side bc and solution xc.
+  B.p64.h_sd.resize(count);
+  B.p32.h_sd.resize(count);
+  long nmax = 1;
+  for (int i = 0; i < count; ++i) {
+    const size_t len = n[i] > 0 ? (size_t)n[i] : 1;
+    void *fx = nullptr, *fy = nullptr, *bc = nullptr, *xc = nullptr;
+    BTRY(dmalloc(&fx, sizeof(double2) * nfull[i]));
+    extra.push_back(fx);
+    BTRY(dmalloc(&fy, sizeof(double2) * nfull[i]));
+    extra.push_back(fy);
+    BTRY(dmalloc(&bc, sizeof(double2) * len));
+    extra.push_back(bc);
+    BTRY(dmalloc(&xc, sizeof(double2) * len));
+    extra.push_back(xc);
+    B.p64.h_sd[i] = SDesc{sup[i].col, sup[i].s, sup[i].n3, sup[i].n12, fx, fy};
+    bptr[i] = bc;
+    xptr[i] = xc;
+    if (B.mixed) {
+      void *fx32 = nullptr, *fy32 = nullptr;
+      BTRY(dmalloc(&fx32, sizeof(float2) * nfull[i]));
+      extra.push_back(fx32);
+      BTRY(dmalloc(&fy32, sizeof(float2) * nfull[i]));
+      extra.push_back(fy32);
+      BTRY(hipMemsetAsync(fx32, 0, sizeof(float2) * nfull[i], s));
+      B.p32.h_sd[i] = SDesc{sup[i].col, sup[i].s, sup[i].n3, sup[i].n12, fx32, fy32};
+    }
+    nmax = std::max(nmax, nfull[i]);
+  }
+  // norms: sq[3 i] = ||b_S||^2, sq[3 i + 1] = ||b_off||^2, sq[3 i + 2] = ||b_c||^2
+  double2* dsq = nullptr;
+  double2* part = nullptr;
+  BTRY(dmalloc(&dsq, sizeof(double2) * 3 * count));
+  extra.push_back(dsq);
+  BTRY(dmalloc(&part, sizeof(double2) * partial_blocks(nmax)));
+  extra.push_back(part);
+  BTRY(hipMemsetAsync(dsq, 0, sizeof(double2) * 3 * count, s));
+  using K = KrylovOps<double>;
+  for (int i = 0; i < count; ++i) {
+    double2* fx = (double2*)B.p64.h_sd[i].fx;
+    BTRY(hipMemcpyAsync(fx, rhs[i], sizeof(double2) * nfull[i], hipMemcpyDeviceToDevice, s));
+    if (sup[i].s > 0) {
+      BTRY(gather<double>(sup[i], (const double2*)rhs[i], (double2*)bptr[i], nullptr, s));
+      BTRY(K::nrm2sq((const double2*)bptr[i], n[i], part, dsq + 3 * i, s));
+      BTRY(zero_support<double>(sup[i], fx, s));
+    }
+    BTRY(K::nrm2sq(fx, nfull[i], part, dsq + 3 * i + 1, s));
+  }
+  std::vector<double2> hsq(3 * count);
+  BTRY(hipMemcpyAsync(hsq.data(), dsq, sizeof(double2) * 3 * count, hipMemcpyDeviceToHost, s));
+  BTRY(hipStreamSynchronize(s));
+  std::vector<int> boff(count, 0);
+  for (int i = 0; i < count; ++i) {
+    if (!std::isfinite(hsq[3 * i].x) || !std::isfinite(hsq[3 * i + 1].x)) {
+      cleanup();
+      return VIE_EINVAL;   // right-hand side not finite
+    }
+    boff[i] = sup[i].s > 0 && hsq[3 * i + 1].x > 0;
+    if (!boff[i]) continue;
+    const SysPlan& P = B.sp[i];
+    const SDesc& S = B.p64.h_sd[i];
+    BTRY(launch_matvec<double>(P.g, P.t64, S.fx, S.fy, nullptr, 0, P.U64, P.goct64, P.chi64, P.tw64, s));
+    BTRY(gather<double>(sup[i], (const double2*)S.fy, (double2*)bptr[i], (const double2*)bptr[i], s));
+    BTRY(K::nrm2sq((const double2*)bptr[i], n[i], part, dsq + 3 * i + 2, s));
+  }
+  for (int i = 0; i < count; ++i) BTRY(hipMemsetAsync(B.p64.h_sd[i].fx, 0, sizeof(double2) * nfull[i], s));
+  BTRY(hipMemcpyAsync(hsq.data(), dsq, sizeof(double2) * 3 * count, hipMemcpyDeviceToHost, s));
+  BTRY(hipStreamSynchronize(s));
+  // ||r|| / ||b|| = (||r_c|| / ||b_c||) * ratio with ratio = ||b_c|| / ||b||
+  std::vector<double> ratio(count, 0.0), tolc(count, tol);
+  for (int i = 0; i < count; ++i) {
+    const double bnorm = std::sqrt(hsq[3 * i].x + hsq[3 * i + 1].x);
+    const double bcsq = boff[i] ? hsq[3 * i + 2].x : hsq[3 * i].x;
+    if (bnorm > 0 && bcsq > 0) {
+      ratio[i] = std::sqrt(bcsq) / bnorm;
+      tolc[i] = tol / ratio[i];
+    }
+  }
   BTRY(build_level<double>(B.outer, n, o.restart, B.mixed || B.circ_tier, tol, bptr, xptr, act, nullptr));
+  for (int i = 0; i < count; ++i) B.outer.h[i].tol = tolc[i];
+  BTRY(hipMemcpy(B.outer.d, B.outer.h.data(), sizeof(KDesc) * count, hipMemcpyHostToDevice));
   if (B.mixed) {
     std::vector<const void*> ib(count);
     std::vector<void*> ix(count);
     for (int i = 0; i < count; ++i) {
       void *bb = nullptr, *xx = nullptr;
-      BTRY(dmalloc(&bb, sizeof(float2) * n[i]));
+      const size_t len = n[i] > 0 ? (size_t)n[i] : 1;
+      BTRY(dmalloc(&bb, sizeof(float2) * len));
       extra.push_back(bb);
-      BTRY(dmalloc(&xx, sizeof(float2) * n[i]));
+      BTRY(dmalloc(&xx, sizeof(float2) * len));
       extra.push_back(xx);
       ib[i] = bb;
       ix[i] = xx;
@@ -867,8 +1036,10 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
   // all systems on for the set-up reductions
   std::vector<int> on(count, 1);
   BTRY(hipMemcpyAsync(act, on.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
-  BTRY(batch_norm<double>(s, O, 3, 0, 1, 1));          // ||b||^2
+  BTRY(batch_norm<double>(s, O, 3, 0, 1, 1));          // ||b_c||^2
   if (o.use_x0) {
+    for (int i = 0; i < count; ++i)
+      if (sup[i].s > 0) BTRY(gather<double>(sup[i], (const double2*)x[i], (double2*)xptr[i], nullptr, s));
     BTRY(batch_matvec<double>(&B, B.p64, O, true, 0));  // r = b - A x
   } else {
     hipLaunchKernelGGL((k_b_copy<double, double>), dim3(grid_for(O.ctotal)), dim3(kT), 0, s, O.d, O.d, O.d_cpre,
@@ -891,7 +1062,7 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
     int nact = 0;
     for (int i = 0; i < count; ++i) {
       bn[i] = std::sqrt(sq[2 * i + 1].x);
-      rel[i] = bn[i] > 0 ? std::sqrt(sq[2 * i].x) / bn[i] : 0.0;
+      rel[i] = bn[i] > 0 ? std::sqrt(sq[2 * i].x) / bn[i] * ratio[i] : 0.0;
       iters[i] = hflags[2 * count + i];
       on[i] = (std::isfinite(rel[i]) && rel[i] > tol && iters[i] < o.maxit) ? 1 : 0;
       if (!std::isfinite(rel[i])) status = VIE_ENUMERIC;
@@ -928,6 +1099,11 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
     BTRY(batch_matvec<double>(&B, B.p64, O, true, 0));
     if (cycles > 100000) break;
   }
+  // x = b off the support, xc on it
+  for (int i = 0; i < count; ++i) {
+    BTRY(hipMemcpyAsync(x[i], rhs[i], sizeof(double2) * nfull[i], hipMemcpyDeviceToDevice, s));
+    if (sup[i].s > 0) BTRY(scatter<double>(sup[i], (const double2*)xptr[i], (double2*)x[i], s));
+  }
   // report
   std::vector<int> inn(count, 0);
   BTRY(hipStreamSynchronize(s));
@@ -946,7 +1122,7 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
       infos[i].iters = iters[i];
       infos[i].inner_iters = inn[i];
       infos[i].restarts = restarts[i];
-      infos[i].matvecs = iters[i] + restarts[i] + (o.use_x0 ? 1 : 0);
+      infos[i].matvecs = iters[i] + restarts[i] + (o.use_x0 ? 1 : 0) + boff[i];
       infos[i].status = st;
       infos[i].rel_res_true = rel[i];
       infos[i].rel_res_est = rel[i];

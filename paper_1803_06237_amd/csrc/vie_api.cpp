@@ -732,6 +732,13 @@ int vie::plan_export(vie_plan_t p, Geom* g, Tune* t64, Tune* t32, void** U64, vo
 
 vie::Circ* vie::plan_circ(vie_plan_t p) { return p ? p->circ : nullptr; }
 
+int vie::plan_support(vie_plan_t p, const int** col, int* ns) {
+  if (!p || !p->has_contrast) return VIE_ESTATE;
+  *col = p->scol;
+  *ns = p->ns;
+  return VIE_OK;
+}
+
 hipError_t vie::dmalloc_bytes(void** p, size_t bytes) {
   static const bool nanfill = [] {
     const char* v = std::getenv("VIE_DEBUG_NANFILL");

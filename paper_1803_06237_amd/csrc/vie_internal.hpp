@@ -163,5 +163,8 @@ int plan_export(vie_plan_t p, Geom* g, Tune* t64, Tune* t32, void** U64, void** 
                 int* has_contrast);
 // The plan's block-circulant preconditioner, or null when none is built.
 Circ* plan_circ(vie_plan_t p);
+// The plan's support columns (device, *ns increasing indices i1 n2 + i2 where the
+// contrast is non-zero on some slice), valid while the contrast is unchanged.
+int plan_support(vie_plan_t p, const int** col, int* ns);
 
 }  // namespace vie
