@@ -82,18 +82,60 @@ def test_graph_replays_match_eager_cycles(systems):
             assert torch.equal(a, b)
 
 
-def test_batch_equals_single_solve_residual_level(systems):
-    """For b = h^{3/2} chi e (supported where the contrast is) the single solver's
-    support-compressed Krylov vectors and the batch solver's full ones hold the same
-    values, so the iterates agree to rounding."""
+@pytest.mark.parametrize("rhs", ["on_support", "everywhere"])
+def test_batch_equals_single_solve_residual_level(systems, rhs):
+    """The single and the batch solver both keep Krylov vectors compressed to the
+    support columns and solve A_SS x_S = b_S - (A b_off)_S, so for b = h^{3/2} chi e
+    (zero off the support) and for a Gaussian b (non-zero everywhere) the iterates
+    agree to rounding."""
     vie = _dev()
     wg, op, plan, _ = systems[0]
-    b = mv.rhs_from_field(wg.eps(), wg.eps_b, inputs.gaussian_rhs(wg.n, 7), wg.h)
+    if rhs == "on_support":
+        b = mv.rhs_from_field(wg.eps(), wg.eps_b, inputs.gaussian_rhs(wg.n, 7), wg.h)
+    else:
+        b = inputs.gaussian_rhs(wg.n, 7)
     x1, info1 = plan.solve(torch.from_numpy(b).cuda(), tol=1e-8, restart=30)
     xs, infos, code = vie.solve_batch([plan], [torch.from_numpy(b).cuda()], tol=1e-8, restart=30)
     assert code == vie.VIE_OK
     assert infos[0]["iters"] == info1["iters"]
+    assert abs(infos[0]["rel_res_true"] - info1["rel_res_true"]) < 1e-12
     assert torch.linalg.norm(xs[0] - x1) / torch.linalg.norm(x1) < 1e-10
+    assert _rel(op, b, xs[0].cpu().numpy()) <= 1.01e-8
+
+
+def test_batch_resumes_from_x0(systems):
+    """use_x0: a batch stopped by maxit continues from its iterates to the tolerance;
+    the oracle judges the result, and an exact start needs no step."""
+    vie = _dev()
+    plans = [s[2] for s in systems]
+    bs = [torch.from_numpy(s[3]).cuda() for s in systems]
+    xs, infos, code = vie.solve_batch(plans, bs, tol=1e-8, restart=10, maxit=10)
+    assert code == vie.VIE_ENOCONV
+    xs, infos, code = vie.solve_batch(plans, bs, xs=xs, tol=1e-8, restart=30, use_x0=True)
+    assert code == vie.VIE_OK, infos
+    for (wg, op, plan, b), x, info in zip(systems, xs, infos):
+        assert _rel(op, b, x.cpu().numpy()) <= 1.01e-8
+        assert info["matvecs"] >= info["iters"] + 1
+    again = [x.clone() for x in xs]
+    xs2, infos2, code = vie.solve_batch(plans, bs, xs=again, tol=1e-6, restart=30, use_x0=True)
+    assert code == vie.VIE_OK
+    for x, x2, info in zip(xs, xs2, infos2):
+        assert info["iters"] == 0 and info["rel_res_true"] <= 1.01e-8
+        assert torch.equal(x, x2)
+
+
+def test_batch_system_without_contrast(systems):
+    """A guide whose permittivity is the background everywhere has no support: A is
+    the identity and x = b, next to an ordinary system of the same batch."""
+    vie = _dev()
+    wg, op, plan, b = systems[2]
+    empty = vie.Plan(wg.n, wg.h, wg.k0, wg.eps_b)
+    empty.set_contrast(torch.full(wg.n, wg.eps_b, dtype=torch.complex128).cuda())
+    b2 = torch.from_numpy(inputs.gaussian_rhs(wg.n, 300)).cuda()
+    xs, infos, code = vie.solve_batch([plan, empty], [torch.from_numpy(b).cuda(), b2], tol=1e-8, restart=30)
+    assert code == vie.VIE_OK
+    assert _rel(op, b, xs[0].cpu().numpy()) <= 1.01e-8
+    assert torch.equal(xs[1], b2) and infos[1]["iters"] == 0 and infos[1]["rel_res_true"] == 0
 
 
 def test_one_plan_several_right_hand_sides(systems):
