@@ -272,16 +272,20 @@ int vie_circulant_apply(vie_plan_t plan, const vie_c128* r, vie_c128* z);
  * (circulant lengths 512 to 4096 have four-step shapes), crossed with, for
  * 64 x 64 circulant cross-sections, the xy pass variant (0: full plane in LDS;
  * 1: x-frequency halves, two workgroups per CU; 2: full plane with 512 threads
- * and private exchange areas, one workgroup per CU); the pairs are timed jointly
+ * and private exchange areas, one workgroup per CU) and, for 64 x 32 ones (the
+ * paper's strip), the xy pass (0: generic padded LDS transforms; 1: register
+ * transforms at the occupancy the LDS allows; 2: the same at half that
+ * occupancy with a larger register budget); the pairs are timed jointly
  * because the z pass's writes decide what the xy pass finds in cache.  Choices
  * are cached per (device, grid, precision) for the life of the process, and in the
  * file named by the environment variable VIE_TUNE_CACHE (default
  * $XDG_CACHE_HOME or $HOME/.cache, vie-mi355x/tune.txt; empty: none), keyed by
  * the GPU architecture and CU count, the grid and the precision.
  * vie_get_tune: the current choice for precision 0 (FP64) or 1 (FP32):
- *   *xy_variant (-1 when the grid does not use the 64 x 64 kernel),
+ *   *xy_variant (-1 when the cross-section has a single xy pass),
  *   *z_pencils (0 when the z passes use the generic kernels).
- * vie_set_tune: force a choice; z_pencils -1 = the generic z passes, 0 = the
+ * vie_set_tune: force a choice (xy_variant 0-2, ignored where the cross-section
+ *   has a single xy pass); z_pencils -1 = the generic z passes, 0 = the
  *   four-step z passes with their default pencils (generic where the grid has no
  *   four-step shape), any other value must be one of the tuner's candidates
  *   (VIE_EINVAL otherwise).  Synchronises the plan's stream first.

@@ -30,6 +30,11 @@ hipError_t launch_xy64(const Geom& g, int V, void* U, const void* goct, const vo
 template <typename T>
 hipError_t allow_lds_xy64();
 template <typename T>
+hipError_t launch_xy6432(const Geom& g, int V, void* U, const void* goct, const void* tw1, const void* tw2,
+                         hipStream_t s);
+template <typename T>
+hipError_t allow_lds_xy6432();
+template <typename T>
 hipError_t launch_z4(int which, const Geom& g, int P, const void* x, void* y, const void* b, int mode, void* U,
                      const void* chi, const void* twz, hipStream_t st);
 template <typename T>
@@ -189,6 +194,8 @@ hipError_t launch_pass(int which, const Geom& g, const Tune& t, const void* x, v
     hipLaunchKernelGGL((k_zfwd<T>), gz, dim3(t.zthreads), zl, s, (const C*)x, (C*)U, g, t.tp, (const C*)tw[2]);
   } else if (which == 1 && g.M1 == 64 && g.M2 == 64) {
     return launch_xy64<T>(g, t.xyv, U, goct, tw[0], s);
+  } else if (which == 1 && g.M1 == 64 && g.M2 == 32 && (t.xyv == 1 || t.xyv == 2)) {
+    return launch_xy6432<T>(g, t.xyv, U, goct, tw[0], tw[1], s);
   } else if (which == 1) {
     hipLaunchKernelGGL((k_xyp<T>), dim3(g.M3), dim3(t.xythreads), xy_lds_bytes<T>(g, t.cc), s, (C*)U,
                        (const C*)goct, g, t.cc, (const C*)tw[0], (const C*)tw[1]);
@@ -243,6 +250,7 @@ hipError_t allow_lds(size_t bytes) {
   if ((e = hipFuncSetAttribute((const void*)k_zinv<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)))
     return e;
   if ((e = allow_lds_xy64<T>())) return e;
+  if ((e = allow_lds_xy6432<T>())) return e;
   if ((e = allow_lds_z4<T>())) return e;
   return hipFuncSetAttribute((const void*)k_xyp<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }

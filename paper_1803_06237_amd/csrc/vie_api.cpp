@@ -370,7 +370,8 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
       return hipSuccess;
     }
   }
-  const std::string arch = device_arch(device);
+  // the suffix names the candidate set: lines written for an older set are not read
+  const std::string arch = device_arch(device) + "/xy6432";
   if (tune_cache_lookup(arch, g, (int)sizeof(cx<T>), t)) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = *t;
@@ -412,7 +413,7 @@ hipError_t autotune(const Geom& g, int device, Tune* t, void* U, const void* goc
     } else {
       zc.push_back(*t);
     }
-    const int nv = g.M1 == 64 && g.M2 == 64 ? 3 : 1;
+    const int nv = xy_variants(g);
     for (const Tune& z : zc)
       for (int v = 0; v < nv; ++v) {
         Tune c = z;
@@ -1420,7 +1421,7 @@ int vie_get_tune(vie_plan_t p, int precision, int* xy_variant, int* z_pencils) {
   int opts[8];
   const int n = precision == 0 ? z4_pencil_options<double>(p->g.M3, opts, 8)
                                : z4_pencil_options<float>(p->g.M3, opts, 8);
-  if (xy_variant) *xy_variant = (p->g.M1 == 64 && p->g.M2 == 64) ? t.xyv : -1;
+  if (xy_variant) *xy_variant = xy_variants(p->g) > 1 ? t.xyv : -1;
   if (z_pencils) *z_pencils = t.z4 && n ? (t.zp ? t.zp : opts[0]) : 0;
   return VIE_OK;
 }

@@ -29,9 +29,14 @@ struct Tune {
   int cc;        // column chunk in the xy pass
   int xythreads; // threads per workgroup in the xy pass
   int z4;        // 1: z passes use the register four-step kernels
-  int xyv;       // 64 x 64 xy pass variant: 0 full plane, 1 x-frequency halves, 2 wide
+  int xyv;       // xy pass variant; 64 x 64: 0 full plane, 1 x-frequency halves, 2 wide;
+                 // 64 x 32: 0 generic padded LDS pass, 1 and 2 register transforms
+                 // (1: at the occupancy the LDS allows, 2: at half of it)
   int zp;        // pencils per workgroup in the four-step z passes (0: the default for M3)
 };
+
+// Number of xy pass variants of a cross-section: 3 for 64 x 64 and 64 x 32, else 1.
+inline int xy_variants(const Geom& g) { return g.M1 == 64 && (g.M2 == 64 || g.M2 == 32) ? 3 : 1; }
 
 // Candidate pencil counts of the four-step z passes for M3 (empty when none exist);
 // the first is the default.

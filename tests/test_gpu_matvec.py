@@ -259,7 +259,39 @@ def test_every_xy_variant_matches_the_oracle(n):
             assert err < (1e-12 if precision == 0 else 5e-6)
 
 
+@pytest.mark.parametrize("n", [(30, 12, 20), (17, 9, 13), (32, 16, 7), (25, 14, 3), (20, 10, 1)],
+                         ids=lambda g: "x".join(map(str, g)))
+def test_every_64x32_xy_variant_matches_the_oracle(n):
+    """64 x 32 cross-sections (the paper's strip is 30 x 12): the generic padded LDS
+    pass (0) and the register-transform kernel at both register budgets (1, 2), FP64
+    and FP32, give the oracle's whole product; n3 = 3 and 1 give z circulants of 8
+    and 1 (plane map without pairing, single plane)."""
+    vie = _dev()
+    rng = np.random.default_rng(11 + sum(n))
+    kap = mv.kappa_of(H, K0, EPSB)
+    spec = mv.spectrum(green.green_table(n, kap))
+    eps = EPSB + 10 * rng.random(n) + 1j * rng.random(n)
+    eps[rng.random(n) < 0.3] = EPSB
+    chi = mv.contrast(eps, EPSB)
+    plan = vie.Plan(n, H, K0, EPSB, fp32=True)
+    plan.set_contrast(_t(eps))
+    x = _cvec(rng, (3,) + n)
+    want = mv.matvec_fft(spec, chi, x)
+    for precision in (0, 1):
+        for xyv in (0, 1, 2):
+            plan.set_tune(precision, xyv, 0)
+            assert plan.tune(precision)["xy_variant"] == xyv
+            if precision == 0:
+                y = plan.matvec(_t(x)).cpu().numpy()
+            else:
+                y = plan.matvec_c64(_t(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+            err = np.max(np.abs(y - want)) / np.max(np.abs(want))
+            print(n, precision, xyv, f"{err:.2e}")
+            assert err < (1e-12 if precision == 0 else 5e-6)
+
+
 TUNED_GRIDS = {
+    "30x12x1377_M3_4096": lambda: inputs.strip_paper(9.45, 2),
     "32x32x512_M3_1024": lambda: inputs.strip_long(d=2),
     "24x20x200_M3_512": lambda: inputs.Waveguide(n=(24, 20, 200), h=0.025, core_x=(4, 20), core_y=(6, 14),
                                                  core_z=(0, 200), n_abs=30, d=2, sigma_max=10.0),
