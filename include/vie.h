@@ -274,8 +274,9 @@ int vie_circulant_apply(vie_plan_t plan, const vie_c128* r, vie_c128* z);
  * 1: x-frequency halves, two workgroups per CU; 2: full plane with 512 threads
  * and private exchange areas, one workgroup per CU) and, for 64 x 32 ones (the
  * paper's strip), the xy pass (0: generic padded LDS transforms; 1: register
- * transforms at the occupancy the LDS allows; 2: the same at half that
- * occupancy with a larger register budget); the pairs are timed jointly
+ * transforms with an LDS exchange area per column, two FP64 workgroups per CU;
+ * 2: the same exchanging in the columns' own hand-off entries, three FP64
+ * workgroups per CU); the pairs are timed jointly
  * because the z pass's writes decide what the xy pass finds in cache.  Choices
  * are cached per (device, grid, precision) for the life of the process, and in the
  * file named by the environment variable VIE_TUNE_CACHE (default

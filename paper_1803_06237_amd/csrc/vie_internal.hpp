@@ -31,7 +31,7 @@ struct Tune {
   int z4;        // 1: z passes use the register four-step kernels
   int xyv;       // xy pass variant; 64 x 64: 0 full plane, 1 x-frequency halves, 2 wide;
                  // 64 x 32: 0 generic padded LDS pass, 1 and 2 register transforms
-                 // (1: at the occupancy the LDS allows, 2: at half of it)
+                 // (1: column exchange areas of their own, 2: exchange in the hand-off)
   int zp;        // pencils per workgroup in the four-step z passes (0: the default for M3)
 };
 

@@ -17,13 +17,17 @@
 //     DFT over a, giving Y[k1 + 8 k2] with k1 in {2 a', 2 a' + 1} on lane a';
 //     the Green product; the inverse in the mirrored order, keeping y < 16.
 //  C: the 3 n2 inverse x transforms as in A, crop to x < n1, store.
-// LDS: the hand-off (3 x 16 rows of 64 x-frequencies) and 64 column exchange
-// areas of 32 values, 80 KiB in FP64 (two workgroups per CU), 40 KiB in FP32.
+// LDS: the hand-off (3 x 16 rows of 64 x-frequencies) and, in variant 1, 64
+// column exchange areas of 32 values (80 KiB in FP64, 40 KiB in FP32); variant 2
+// exchanges in the column's own hand-off entries of components 0 and 1, free
+// once the column is in registers (48 KiB, 24 KiB).
 // The layouts were chosen by enumerating the accesses of one LDS pass (256
 // bytes: 16 lanes of 16-byte or 32 lanes of 8-byte values): hand-off element
 // (c, y, kx) at row (c, y), column kx ^ 10 (y & 3); column exchange element
-// (a, k) of group g at ((k + (g & 3)) & 7) 4 + (a ^ ((k >> 1) & 3)); row
-// exchange element (i, j) of group q at (i ^ (q & 3)) 8 + ((i + j) & 7).
+// (a, k) of group g at ((k + (g & 3)) & 7) 4 + (a ^ ((k >> 1) & 3)) of its area
+// (variant 1) or at hand-off entry (k & 1, 4 (k >> 1) + ((a + (k >> 1)) & 3), g)
+// (variant 2: the four lanes of a group always differ in y & 3); row exchange
+// element (i, j) of group q at (i ^ (q & 3)) 8 + ((i + j) & 7).
 // Planes kz and M3 - kz use the same slab of the folded Green spectrum and go to
 // workgroups b and b + 8 (same XCD).
 #include <hip/hip_runtime.h>
@@ -62,6 +66,14 @@ __device__ __forceinline__ void row64(cx<T>* v, const cx<T>* w, int a, cx<T>* X,
   dft8<T, INV>(v);
 }
 
+// The value as the compiler must materialise it here: without this, parts of the
+// Green product were carried into the inverse transforms as separate terms, which
+// raised the register need of the column stage by about half.
+template <typename T>
+__device__ __forceinline__ void pin(cx<T>& v) {
+  asm volatile("" : "+v"(v.x), "+v"(v.y));
+}
+
 // row task i of group q: (component, row)
 __device__ __forceinline__ void row_task(int q, int i, int* c, int* y) {
   if (q < 16) {
@@ -73,7 +85,7 @@ __device__ __forceinline__ void row_task(int q, int i, int* c, int* y) {
   }
 }
 
-template <typename T>
+template <typename T, bool COMPACT>
 __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
                                              const cx<T>* __restrict__ tw64, const cx<T>* __restrict__ tw32, int kz,
                                              cx<T>* R) {
@@ -115,7 +127,15 @@ __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>*
   {
     const int t = opaque_tid();
     const int a = t & 3, kx = t >> 2, r = kx & 3;
-    cx<T>* X = R + kHandVals + kx * kColX;
+    // exchange element (aa, k) of this column: its own area, or (COMPACT) a slot of
+    // the column's own hand-off entries, free once the column is in registers
+    auto xs = [&](int aa, int k) -> int {
+      if (COMPACT) {
+        const int kh = k >> 1;
+        return hand(k & 1, (kh << 2) | ((aa + kh) & 3), kx);
+      }
+      return kHandVals + kx * kColX + colx(aa, k, r);
+    };
     cx<T> v[3][8];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -133,12 +153,12 @@ __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>*
 #pragma unroll
       for (int k = 1; k < 8; ++k) v[c][k] = cmul(v[c][k], tw32[a * k]);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) X[colx(a, k, r)] = v[c][k];
+      for (int k = 0; k < 8; ++k) R[xs(a, k)] = v[c][k];
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int e = 0; e < 2; ++e)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) v[c][e * 4 + s] = X[colx(s, 2 * a + e, r)];
+        for (int s = 0; s < 4; ++s) v[c][e * 4 + s] = R[xs(s, 2 * a + e)];
       __builtin_amdgcn_wave_barrier();
       dft4<T, false>(v[c]);                                  // v[e 4 + m] = Y[2 a + e + 8 m]
       dft4<T, false>(v[c] + 4);
@@ -167,6 +187,9 @@ __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>*
         v[0][i] = cadd(cadd(cmul(gxx, ux), cmul(gxy, uy)), cmul(gxz, uz));
         v[1][i] = cadd(cadd(cmul(gxy, ux), cmul(gyy, uy)), cmul(gyz, uz));
         v[2][i] = cadd(cadd(cmul(gxz, ux), cmul(gyz, uy)), cmul(gzz, uz));
+        pin<T>(v[0][i]);
+        pin<T>(v[1][i]);
+        pin<T>(v[2][i]);
         // one point's spectrum loads in flight at a time: hoisting all eight
         // points' loads (48 values) ran the kernel out of registers
         __builtin_amdgcn_sched_barrier(0);
@@ -180,20 +203,24 @@ __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>*
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int k1v = 2 * a + e;
-          X[colx(s, k1v, r)] = s == 0 ? v[c][e * 4] : cmulc(v[c][e * 4 + s], tw32[s * k1v]);
+          R[xs(s, k1v)] = s == 0 ? v[c][e * 4] : cmulc(v[c][e * 4 + s], tw32[s * k1v]);
         }
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[c][k] = X[colx(a, k, r)];
+      for (int k = 0; k < 8; ++k) v[c][k] = R[xs(a, k)];
       __builtin_amdgcn_wave_barrier();
       dft8<T, true>(v[c]);                                   // v[b] = column value at y = a + 4 b
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // stored after all three inverse transforms: the compact exchange reuses the
+    // column's entries of components 0 and 1
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int y = a + 4 * b;
         if (y < n2) R[hand(c, y, kx)] = v[c][b];
       }
-      __builtin_amdgcn_sched_barrier(0);
-    }
   }
   __syncthreads();
 
@@ -223,16 +250,20 @@ __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>*
   }
 }
 
-// Register budget of variant V, as waves per SIMD: V = 1 at the occupancy the LDS
-// allows (two workgroups per CU in FP64, four in FP32), where the compiler spills
-// part of the column stage to scratch; V = 2 at half of it, without scratch.
-template <typename T, int V> constexpr int kWaves = (sizeof(T) == 8 ? 2 : 4) / V;
+// Variants: V = 1 gives every column group its own exchange area (80 KiB of LDS
+// in FP64: two workgroups per CU; 40 KiB in FP32: four); V = 2 exchanges in the
+// column's own hand-off entries (48 KiB in FP64: three workgroups per CU; 24 KiB
+// in FP32: five, bounded by registers).  The launch bound holds the compiler to the
+// registers of that many waves per SIMD.
+template <typename T, int V> constexpr int kWaves = sizeof(T) == 8 ? (V == 1 ? 2 : 3) : (V == 1 ? 4 : 5);
+template <int V> constexpr int kLdsOf = V == 1 ? kLdsVals : kHandVals;
 
 template <typename T, int V>
 __global__ __launch_bounds__(kThreads, (kWaves<T, V>)) void k_xy6432(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, Geom g,
                                                      const cx<T>* __restrict__ tw64, const cx<T>* __restrict__ tw32) {
   extern __shared__ unsigned char smem_raw[];
-  xy6432_plane<T>(U, goct, g, tw64, tw32, paired_plane(blockIdx.x, g.M3), reinterpret_cast<cx<T>*>(smem_raw));
+  xy6432_plane<T, V == 2>(U, goct, g, tw64, tw32, paired_plane(blockIdx.x, g.M3),
+                          reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 }  // namespace
@@ -241,22 +272,20 @@ template <typename T>
 hipError_t launch_xy6432(const Geom& g, int V, void* U, const void* goct, const void* tw1, const void* tw2,
                          hipStream_t s) {
   if (g.M1 != 64 || g.M2 != 32 || g.n1 > 32 || g.n2 > 16 || (V != 1 && V != 2)) return hipErrorInvalidValue;
-  const size_t lds = kLdsVals * sizeof(cx<T>);
   if (V == 1)
-    hipLaunchKernelGGL((k_xy6432<T, 1>), dim3(g.M3), dim3(kThreads), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
-                       (const cx<T>*)tw1, (const cx<T>*)tw2);
+    hipLaunchKernelGGL((k_xy6432<T, 1>), dim3(g.M3), dim3(kThreads), kLdsOf<1> * sizeof(cx<T>), s, (cx<T>*)U,
+                       (const cx<T>*)goct, g, (const cx<T>*)tw1, (const cx<T>*)tw2);
   else
-    hipLaunchKernelGGL((k_xy6432<T, 2>), dim3(g.M3), dim3(kThreads), lds, s, (cx<T>*)U, (const cx<T>*)goct, g,
-                       (const cx<T>*)tw1, (const cx<T>*)tw2);
+    hipLaunchKernelGGL((k_xy6432<T, 2>), dim3(g.M3), dim3(kThreads), kLdsOf<2> * sizeof(cx<T>), s, (cx<T>*)U,
+                       (const cx<T>*)goct, g, (const cx<T>*)tw1, (const cx<T>*)tw2);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t allow_lds_xy6432() {
   const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
-  const int lds = (int)(kLdsVals * sizeof(cx<T>));
-  hipError_t e = hipFuncSetAttribute((const void*)k_xy6432<T, 1>, attr, lds);
-  return e ? e : hipFuncSetAttribute((const void*)k_xy6432<T, 2>, attr, lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_xy6432<T, 1>, attr, (int)(kLdsOf<1> * sizeof(cx<T>)));
+  return e ? e : hipFuncSetAttribute((const void*)k_xy6432<T, 2>, attr, (int)(kLdsOf<2> * sizeof(cx<T>)));
 }
 
 template hipError_t launch_xy6432<double>(const Geom&, int, void*, const void*, const void*, const void*,

@@ -263,9 +263,10 @@ def test_every_xy_variant_matches_the_oracle(n):
                          ids=lambda g: "x".join(map(str, g)))
 def test_every_64x32_xy_variant_matches_the_oracle(n):
     """64 x 32 cross-sections (the paper's strip is 30 x 12): the generic padded LDS
-    pass (0) and the register-transform kernel at both register budgets (1, 2), FP64
-    and FP32, give the oracle's whole product; n3 = 3 and 1 give z circulants of 8
-    and 1 (plane map without pairing, single plane)."""
+    pass (0) and the register-transform kernel with its own column exchange areas (1)
+    and with the exchange in the hand-off entries (2), FP64 and FP32, give the
+    oracle's whole product; n3 = 3 and 1 give z circulants of 8 and 1 (plane map
+    without pairing, single plane)."""
     vie = _dev()
     rng = np.random.default_rng(11 + sum(n))
     kap = mv.kappa_of(H, K0, EPSB)
