@@ -545,9 +545,12 @@ __device__ __forceinline__ void xy64_planes(cx<T>* __restrict__ U, const cx<T>* 
   else xy64_wide<T>(U, goct, g, tw64, kz_first, nplanes, kz_second, R);
 }
 
-// threads per workgroup and occupancy hint of each variant
+// threads per workgroup and occupancy hint of each variant (waves per SIMD).  The
+// wide variant in FP32 takes 80 KiB of LDS, so two workgroups fit a CU when the
+// compiler keeps to 128 registers (it spills a few; measured 39.8 -> 37.2 us for
+// the FP32 32x32x512 xy pass, 68 -> 64.5 us per FP32 product back to back).
 template <int V> constexpr int kXyThreads = V == 2 ? 512 : 256;
-template <int V> constexpr int kXyWaves = V == 1 ? 2 : 1;
+template <typename T, int V> constexpr int kXyWaves = V == 1 ? 2 : (V == 2 && sizeof(T) == 4 ? 4 : 1);
 
 template <typename T, int V>
 __device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
@@ -561,7 +564,7 @@ __device__ __forceinline__ void xy64_body(cx<T>* __restrict__ U, const cx<T>* __
 // slab; they go to workgroups b and b + 8 (same XCD under round-robin
 // dispatch, launched one after the other) so the second read hits L2.
 template <typename T, int V>
-__global__ __launch_bounds__(kXyThreads<V>, kXyWaves<V>) void k_xy64(cx<T>* __restrict__ U,
+__global__ __launch_bounds__(kXyThreads<V>, (kXyWaves<T, V>)) void k_xy64(cx<T>* __restrict__ U,
                                                                     const cx<T>* __restrict__ goct, Geom g,
                                                                     const cx<T>* __restrict__ tw64) {
   extern __shared__ unsigned char smem_raw[];
@@ -589,7 +592,7 @@ __global__ __launch_bounds__(256, V == 1 ? 2 : 1) void k_xy64_batch(const PassDe
 }
 
 template <typename T, int V>
-__global__ __launch_bounds__(kXyThreads<V>, kXyWaves<V>) void k_xy64_batch_single(cx<T>* __restrict__ U,
+__global__ __launch_bounds__(kXyThreads<V>, (kXyWaves<T, V>)) void k_xy64_batch_single(cx<T>* __restrict__ U,
                                                                                  const cx<T>* __restrict__ goct,
                                                                                  Geom g,
                                                                                  const cx<T>* __restrict__ tw64) {
