@@ -455,9 +455,13 @@ int vie_jm_solve(vie_plan_t plan, const vie_c128* b, vie_c128* x, double tol, co
  * vie_check_block_maps -- host-only diagnostic.  Runs the product's workgroup-to-work
  * maps (z-pass pencil blocks and their XCD grouping, cross-section plane pairs) over
  * every shape the library accepts and checks that each is a bijection onto its work
- * items and that every write derived from an item lies inside its buffer.  msg (may be
- * NULL) receives "ok: ..." or the first violation, cap bytes at most.  planted = 1
- * checks a deliberately broken map instead (the checker must report it).
+ * items and that every write derived from an item lies inside its buffer; the LDS maps
+ * of the 64 x 32 cross-section pass must be bijections inside their areas and free of
+ * bank conflicts over every access of one LDS pass, in FP64 and FP32 (all but the
+ * FP32 column exchange of its variant 1).  msg (may be NULL) receives "ok: ..." or
+ * the first violation, cap bytes at most.  planted = 1 checks a deliberately broken
+ * work map, planted = 2 a hand-off swizzle with bank conflicts, instead (the checker
+ * must report them).
  * Returns VIE_OK when every map passes, VIE_EINVAL otherwise.
  */
 int vie_check_block_maps(char* msg, size_t cap, int planted);

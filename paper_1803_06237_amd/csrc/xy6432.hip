@@ -21,8 +21,11 @@
 // column exchange areas of 32 values (80 KiB in FP64, 40 KiB in FP32); variant 2
 // exchanges in the column's own hand-off entries of components 0 and 1, free
 // once the column is in registers (48 KiB, 24 KiB).
-// The layouts were chosen by enumerating the accesses of one LDS pass (256
-// bytes: 16 lanes of 16-byte or 32 lanes of 8-byte values): hand-off element
+// The layouts (xy6432_maps.hpp) were chosen by enumerating the accesses of one
+// LDS pass (256 bytes: 16 lanes of 16-byte or 32 lanes of 8-byte values), and
+// the host check in maps_check.cpp repeats that enumeration: every access is
+// free of bank conflicts except variant 1's column exchange in FP32 (two-way).
+// Hand-off element
 // (c, y, kx) at row (c, y), column kx ^ 10 (y & 3); column exchange element
 // (a, k) of group g at ((k + (g & 3)) & 7) 4 + (a ^ ((k >> 1) & 3)) of its area
 // (variant 1) or at hand-off entry (k & 1, 4 (k >> 1) + ((a + (k >> 1)) & 3), g)
@@ -35,19 +38,18 @@
 #include "block_maps.hpp"
 #include "fft_device.hpp"
 #include "vie_internal.hpp"
+#include "xy6432_maps.hpp"
 
 namespace vie {
 
 namespace {
 
-constexpr int kHandVals = 3 * 16 * 64;              // hand-off rows
-constexpr int kColX = 32;                            // exchange values per column group
+constexpr int kHandVals = kXy32HandVals;
+constexpr int kColX = kXy32ColX;
 constexpr int kLdsVals = kHandVals + 64 * kColX;
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ int hand(int c, int y, int kx) { return (c * 16 + y) * 64 + (kx ^ ((y & 3) * 10)); }
-__device__ __forceinline__ int rowx(int i, int j, int f) { return (i ^ f) * 8 + ((i + j) & 7); }
-__device__ __forceinline__ int colx(int a, int k, int r) { return ((k + r) & 7) * 4 + (a ^ ((k >> 1) & 3)); }
+__device__ __forceinline__ int hand(int c, int y, int kx) { return xy32_hand(c, y, kx); }
 
 // 64-point DFT of a group of 8 lanes (lane a holds x[a + 8 b] in, X[a + 8 m] out);
 // X is the group's 64-value exchange area.  The area belongs to one wave, whose LDS
@@ -58,10 +60,10 @@ __device__ __forceinline__ void row64(cx<T>* v, const cx<T>* w, int a, cx<T>* X,
 #pragma unroll
   for (int k = 1; k < 8; ++k) v[k] = INV ? cmulc(v[k], w[k]) : cmul(v[k], w[k]);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) X[rowx(k, a, f)] = v[k];
+  for (int k = 0; k < 8; ++k) X[xy32_rowx(k, a, f)] = v[k];
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = X[rowx(a, j, f)];
+  for (int j = 0; j < 8; ++j) v[j] = X[xy32_rowx(a, j, f)];
   __builtin_amdgcn_wave_barrier();
   dft8<T, INV>(v);
 }
@@ -74,16 +76,6 @@ __device__ __forceinline__ void pin(cx<T>& v) {
   asm volatile("" : "+v"(v.x), "+v"(v.y));
 }
 
-// row task i of group q: (component, row)
-__device__ __forceinline__ void row_task(int q, int i, int* c, int* y) {
-  if (q < 16) {
-    *c = i == 0 ? 0 : 2;
-    *y = q;
-  } else {
-    *c = 1;
-    *y = q - 16;
-  }
-}
 
 template <typename T, bool COMPACT>
 __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>* __restrict__ goct, const Geom& g,
@@ -106,7 +98,7 @@ __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>*
     for (int i = 0; i < 2; ++i) {
       if (i == 1 && q >= 16) break;
       int c, y;
-      row_task(q, i, &c, &y);
+      xy32_row_task(q, i, &c, &y);
       if (y >= n2) continue;
       cx<T> v[8];
 #pragma unroll
@@ -130,11 +122,8 @@ __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>*
     // exchange element (aa, k) of this column: its own area, or (COMPACT) a slot of
     // the column's own hand-off entries, free once the column is in registers
     auto xs = [&](int aa, int k) -> int {
-      if (COMPACT) {
-        const int kh = k >> 1;
-        return hand(k & 1, (kh << 2) | ((aa + kh) & 3), kx);
-      }
-      return kHandVals + kx * kColX + colx(aa, k, r);
+      if (COMPACT) return xy32_cslot(aa, k, kx);
+      return kHandVals + kx * kColX + xy32_colx(aa, k, r);
     };
     cx<T> v[3][8];
 #pragma unroll
@@ -235,7 +224,7 @@ __device__ __forceinline__ void xy6432_plane(cx<T>* __restrict__ U, const cx<T>*
     for (int i = 0; i < 2; ++i) {
       if (i == 1 && q >= 16) break;
       int c, y;
-      row_task(q, i, &c, &y);
+      xy32_row_task(q, i, &c, &y);
       if (y >= n2) continue;
       cx<T> v[8];
 #pragma unroll

@@ -109,3 +109,5 @@ def test_block_maps_are_bijections_with_writes_in_bounds():
     assert buf.value.startswith(b"ok:")
     assert L.vie_check_block_maps(buf, 512, 1) != 0
     assert b"not injective" in buf.value
+    assert L.vie_check_block_maps(buf, 512, 2) != 0
+    assert b"bank conflict" in buf.value
