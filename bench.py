@@ -8,9 +8,11 @@ Green product, inverse z FFT with the fused contrast.  Inputs are resident in
 HBM before the timed region.  After the timed steps the same operator is solved
 to a relative residual of 1e-8 from a dipole source with FP64 GMRES(50) and with
 the FP32-inner / FP64-outer flexible GMRES, and the oracle's FFT matvec is timed
-on the host as the CPU baseline.  Unless skipped, the 64-system absorber family is
-solved as one batch (reflection slopes reported) and the learned preconditioner
-is trained and compared on 32 x 32 x 256 rough guides.
+on the host as the CPU baseline.  The JM-VIE products and the J-VIE product on
+the paper's 30 x 12 x 1377 strip are timed beside it.  Unless skipped, the
+64-system absorber family is solved as one batch (reflection slopes reported)
+and the learned preconditioner is trained and compared on 32 x 32 x 256 rough
+guides.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
 
@@ -524,6 +526,10 @@ def main():
 
     if not args.profile:
         out["jm_matvec"] = jm_measurement(max(10, args.steps // 4))
+        # the paper's strip (Section II-A, 9.45 um absorber): 64 x 32 cross-section pass
+        sm = strip_measurement(max(10, args.steps // 4))
+        out["strip_matvec"] = {"workload": "J-VIE product, strip 30x12x1377, circulant 64x32x4096",
+                               **{k: sm[k] for k in ("fp64", "fp32")}}
 
     if not args.no_solve:
         e_inc = inputs.transverse_dipole_field(wg)
