@@ -142,6 +142,10 @@ typedef struct {
   int inner_restart;  /* mixed tier: inner GMRES dimension; <= 0 -> 20 */
   double inner_tol;   /* mixed tier: inner relative tolerance; <= 0 -> 1e-4 */
   int use_graph;      /* vie_solve_batch: 1 = capture one restart cycle as a HIP graph and replay it */
+  int stall_restarts; /* vie_solve: 0 = off; k > 0 = stop with VIE_ENOCONV (info.stalled = 1)
+                         once k restarts in a row each reduce the true residual by less than
+                         0.1 %.  The mixed tiers (1, 5) first continue from their iterate with
+                         FP64 GMRES (info.fallback = 1), which stops by the same rule. */
 } vie_solve_opts;
 
 typedef struct {
@@ -154,7 +158,9 @@ typedef struct {
   double rel_res_true;   /* ||b - A x|| / ||b|| with the FP64 matvec */
   double rel_res_est;    /* last Hessenberg estimate */
   double seconds;        /* wall time of the call */
-  int fallback;          /* learned tier: 1 when it switched to plain GMRES */
+  int fallback;          /* learned tiers: 1 when they switched to the method without the
+                            network; mixed tiers: 1 when a stall handed over to FP64 GMRES */
+  int stalled;           /* 1 when the solve stopped by the stall_restarts rule */
 } vie_solve_info;
 
 /*

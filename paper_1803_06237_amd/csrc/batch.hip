@@ -845,7 +845,7 @@ hipError_t enqueue_cycle(vie_batch_s* B, BatchLevel<T>& L, PassSet& PS, int) {
 extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* rhs, vie_c128* const* x, int count,
                                double tol, const vie_solve_opts* opts, vie_solve_info* infos) {
   if (!plans || !rhs || !x || count < 1 || !(tol > 0)) return VIE_EINVAL;
-  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4, 1};
+  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4, 1, 0};
   if (opts) o = *opts;
   hipStream_t user_stream = nullptr;
   if (o.restart <= 0) o.restart = 50;
@@ -1127,6 +1127,8 @@ extern "C" int vie_solve_batch(vie_plan_t const* plans, const vie_c128* const* r
       infos[i].rel_res_true = rel[i];
       infos[i].rel_res_est = rel[i];
       infos[i].seconds = secs;
+      infos[i].fallback = 0;
+      infos[i].stalled = 0;
     }
   }
   cleanup();

@@ -570,7 +570,12 @@ struct OpJM32 {
 struct Stats {
   int iters = 0, restarts = 0, matvecs = 0, inner = 0, fallback = 0;
   double est = 0, rel_true = INFINITY;
+  int stall_k = 0;   // in: stop after this many restarts without progress (0: never)
+  int stalled = 0;   // out: stopped by that rule
 };
+
+// least relative decrease of the true residual per restart that counts as progress
+constexpr double kStallDrop = 1e-3;
 
 struct NoPrecond {
   hipError_t operator()(const void*, void*, Stats&) { return hipSuccess; }
@@ -617,6 +622,9 @@ int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, long n, const cx<T>* 
   st.est = rel;
   int status = VIE_ENOCONV;
   const int ldh = m + 1;
+  // stagnation: the true residual of each restart against the best so far
+  double best = rel;
+  int since = 0, cycles = 0;
   while (true) {
     if (!std::isfinite(rel)) return fail(p, VIE_ENUMERIC, "non-finite residual");
     if (rel <= tol) {
@@ -624,6 +632,16 @@ int gmres_core(vie_plan_s* p, GmresWs<T>& W, OP& A, PC* M, long n, const cx<T>* 
       break;
     }
     if (st.iters >= maxit) break;
+    if (check_true && st.stall_k > 0 && cycles > 0) {
+      if (rel < best * (1.0 - kStallDrop)) {
+        best = rel;
+        since = 0;
+      } else if (++since >= st.stall_k) {
+        st.stalled = 1;
+        break;
+      }
+    }
+    ++cycles;
     HIPTRY(p, K::set_g(W.g, m, W.sumsq, s));
     HIPTRY(p, K::scale(V0, V0, n, W.sumsq, s));
     // One Arnoldi step queued on the stream, ending with a copy of its state
@@ -1030,7 +1048,7 @@ int solve_options(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, con
   if (!b || !x || (const void*)b == (const void*)x) return fail(p, VIE_EINVAL, "b, x null or aliased");
   if (!(tol > 0) || !std::isfinite(tol)) return fail(p, VIE_EINVAL, "tol must be positive");
   if (!p->has_contrast) return fail(p, VIE_ESTATE, "set_contrast first");
-  o = vie_solve_opts{50, 10000, 0, 0, 20, 1e-4, 0};
+  o = vie_solve_opts{50, 10000, 0, 0, 20, 1e-4, 0, 0};
   if (opts) o = *opts;
   if (o.restart <= 0) o.restart = 50;
   if (o.maxit <= 0) o.maxit = 10000;
@@ -1056,6 +1074,7 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
   const double2* bd = reinterpret_cast<const double2*>(b);
   double2* xd = reinterpret_cast<double2*>(x);
   Stats st;
+  st.stall_k = o.stall_restarts > 0 ? o.stall_restarts : 0;
   int status = VIE_OK;
   auto report = [&](int code) {
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1069,6 +1088,7 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
       info->rel_res_est = st.est;
       info->seconds = secs;
       info->fallback = st.fallback;
+      info->stalled = st.stalled;
     }
     if (code == VIE_ENOCONV && p->err.empty()) p->err = "tolerance not reached within maxit";
     return code;
@@ -1125,6 +1145,15 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
   const double tolc = tol / ratio;
   if (o.use_x0) HIPTRY(p, gather<double>(u, xd, B.xc, nullptr, s));
   Op64c A{p, u, B.fx, B.fy};
+  // mixed tiers: an outer FGMRES that stalled hands its iterate to FP64 GMRES for
+  // the rest of the iteration budget (same stall rule)
+  auto mixed_fallback = [&](int code) -> int {
+    if (code != VIE_ENOCONV || !st.stalled || st.iters >= o.maxit) return code;
+    st.stalled = 0;
+    st.fallback = 1;
+    return gmres_core<double, Op64c, NoPrecond>(p, *B.ws, A, nullptr, n, B.bc, B.xc, tolc, o.restart, o.maxit,
+                                                true, true, st);
+  };
   if (o.precision == 0) {
     status = gmres_core<double, Op64c, NoPrecond>(p, *B.ws, A, nullptr, n, B.bc, B.xc, tolc, o.restart, o.maxit,
                                                   o.use_x0 != 0, true, st);
@@ -1147,6 +1176,7 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
     } pc{inner};
     status = gmres_core<double, Op64c, Pc>(p, *B.ws, A, &pc, n, B.bc, B.xc, tolc, o.restart, o.maxit,
                                            o.use_x0 != 0, true, st);
+    status = mixed_fallback(status);
   } else if (o.precision == 5) {
     // mixed tier with FP64 inner Arnoldi: the inner GMRES keeps its Krylov vectors,
     // Gram-Schmidt and Hessenberg data in FP64 and only its products run in FP32
@@ -1166,6 +1196,7 @@ int solve_impl(vie_plan_s* p, const vie_c128* b, vie_c128* x, double tol, const 
     } pc{inner};
     status = gmres_core<double, Op64c, Pc>(p, *B.ws, A, &pc, n, B.bc, B.xc, tolc, o.restart, o.maxit,
                                            o.use_x0 != 0, true, st);
+    status = mixed_fallback(status);
   } else if (o.precision == 2 || o.precision == 4) {
     // learned tiers.  Precision 2: z = net(v) (the network's correction of v);
     // precision 4: z = W^{-1} v + net(v, W^{-1} v) (the network's correction of the
@@ -1643,7 +1674,7 @@ int vie_jm_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const
   if (!p->jm || !p->has_contrast) return fail(p, VIE_ESTATE, "vie_jm_enable and set_contrast first");
   if (!b || !x || (const void*)b == (const void*)x) return fail(p, VIE_EINVAL, "b, x null or aliased");
   if (!(tol > 0) || !std::isfinite(tol)) return fail(p, VIE_EINVAL, "tol must be positive");
-  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4, 0};
+  vie_solve_opts o{50, 10000, 0, 0, 20, 1e-4, 0, 0};
   if (opts) o = *opts;
   if (o.restart <= 0) o.restart = 50;
   if (o.maxit <= 0) o.maxit = 10000;
@@ -1697,6 +1728,7 @@ int vie_jm_solve(vie_plan_t p, const vie_c128* b, vie_c128* x, double tol, const
     info->rel_res_est = st.est;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->fallback = 0;
+    info->stalled = 0;
   }
   if (status == VIE_ENOCONV && p->err.empty()) p->err = "tolerance not reached within maxit";
   return status;

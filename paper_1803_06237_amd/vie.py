@@ -32,13 +32,14 @@ class VieError(RuntimeError):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("use_x0", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_restart", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("stall_restarts", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("inner_iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("matvecs", ctypes.c_int), ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double),
-                ("rel_res_est", ctypes.c_double), ("seconds", ctypes.c_double), ("fallback", ctypes.c_int)]
+                ("rel_res_est", ctypes.c_double), ("seconds", ctypes.c_double), ("fallback", ctypes.c_int),
+                ("stalled", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -281,17 +282,19 @@ class Plan:
 
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 10000,
               precision: int = 0, use_x0: bool = False, inner_restart: int = 20,
-              inner_tol: float = 1e-4, raise_on_noconv: bool = False):
+              inner_tol: float = 1e-4, raise_on_noconv: bool = False, stall_restarts: int = 0):
         """GMRES(restart) (precision 0), FP32-inner / FP64-outer FGMRES (1), learned (2),
         circulant-preconditioned FGMRES (3, after build_circulant) or the network
         correcting the circulant (4, after build_circulant and set_preconditioner).
+        stall_restarts = k > 0 stops once k restarts in a row gain less than 0.1 % of
+        the true residual (the mixed tiers hand over to FP64 GMRES first).
 
         Returns (x, info dict).  info['status'] is VIE_OK or VIE_ENOCONV."""
         import torch
         if x is None:
             x = torch.zeros_like(b)
         opts = SolveOpts(int(restart), int(maxit), int(bool(use_x0)), int(precision), int(inner_restart),
-                         float(inner_tol), 0)
+                         float(inner_tol), 0, int(stall_restarts))
         info = SolveInfo()
         code = lib().vie_solve(self._h, _ptr(b, torch.complex128, 3 * self.N, "b"),
                                _ptr(x, torch.complex128, 3 * self.N, "x"), float(tol), ctypes.byref(opts),

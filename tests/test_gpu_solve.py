@@ -124,3 +124,37 @@ def test_truncated_gmres_matches_oracle_gmres(small_strip, maxit):
     assert abs(rr - ro) <= 1e-9 * ro
     assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
     assert abs(info["rel_res_est"] - io.history[-1]) <= 1e-9 * io.history[-1]
+
+
+def test_stall_rule_stops_below_the_attainable_floor(small_strip):
+    """tol = 1e-18 lies below what FP64 GMRES can reach: with stall_restarts the solve
+    stops a few restarts after the residual stops falling (VIE_ENOCONV, stalled)
+    instead of running to maxit, and the iterate it returns is at the floor."""
+    vie = _dev()
+    wg, op, plan, b_dip, b_gau, _ = small_strip
+    b = torch.from_numpy(b_gau).cuda()
+    x, info = plan.solve(b, tol=1e-18, restart=20, maxit=100000, stall_restarts=3)
+    rr = _oracle_rel_res(op, b_gau, x.cpu().numpy())
+    print(info, "oracle rel res", rr)
+    assert info["status"] == vie.VIE_ENOCONV and info["stalled"] == 1 and info["fallback"] == 0
+    assert info["iters"] < 5000
+    assert info["rel_res_true"] < 1e-13 and rr < 1e-12
+    # the same solve to 1e-8 is unchanged by the rule: it progresses every restart
+    x1, i1 = plan.solve(b, tol=1e-8, restart=20)
+    x2, i2 = plan.solve(b, tol=1e-8, restart=20, stall_restarts=2)
+    assert i1["status"] == i2["status"] == 0 and i2["stalled"] == 0
+    assert i1["iters"] == i2["iters"] and torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("precision", [1, 5])
+def test_mixed_tier_hands_a_stall_to_fp64_gmres(small_strip, precision):
+    """A mixed-tier outer FGMRES that stalls hands its iterate to FP64 GMRES (fallback)
+    for the rest of the budget; below the floor that one stalls too."""
+    vie = _dev()
+    wg, op, plan, b_dip, b_gau, _ = small_strip
+    x, info = plan.solve(torch.from_numpy(b_gau).cuda(), tol=1e-18, restart=20, maxit=100000,
+                         precision=precision, inner_restart=10, inner_tol=1e-3, stall_restarts=2)
+    rr = _oracle_rel_res(op, b_gau, x.cpu().numpy())
+    print(precision, info, "oracle rel res", rr)
+    assert info["status"] == vie.VIE_ENOCONV and info["fallback"] == 1 and info["stalled"] == 1
+    assert info["iters"] < 5000 and rr < 1e-12
