@@ -365,6 +365,16 @@ void vie_net_destroy(vie_net_t net);
 int vie_net_num_params(vie_net_t net, size_t* count);
 int vie_net_get_params(vie_net_t net, float* host, size_t count);
 int vie_net_set_params(vie_net_t net, const float* host, size_t count);
+/*
+ * Training checkpoint (the state one vie_net_train_step continues from): the FP32
+ * master weights, the Adam moments m and v and the Adam step count.  host holds
+ * 3 count floats, [weights | m | v], each part in the layout of vie_net_get_params;
+ * count = vie_net_num_params.  vie_net_set_state refuses non-finite values, negative
+ * second moments or a negative step (VIE_EINVAL, nothing changed), rewrites the
+ * bfloat16 copies and synchronises.  Both copy through the host synchronously.
+ */
+int vie_net_get_state(vie_net_t net, float* host, size_t count, int* step);
+int vie_net_set_state(vie_net_t net, const float* host, size_t count, int step);
 int vie_net_apply(vie_net_t net, const vie_c128* r, const vie_c128* chi, vie_c128* z);
 int vie_net_train_step(vie_net_t net, int count, const vie_c128* const* r, const vie_c128* const* chi,
                        const vie_c128* const* target, float lr, double* loss);

@@ -829,6 +829,44 @@ int vie_net_set_params(vie_net_t N, const float* host, size_t count) {
   return VIE_OK;
 }
 
+int vie_net_get_state(vie_net_t N, float* host, size_t count, int* step) {
+  size_t c = 0;
+  if (!N || !host || !step || vie_net_num_params(N, &c) || c != count) return VIE_EINVAL;
+  size_t off = 0;
+  for (auto& L : N->L) {
+    const size_t b = sizeof(float) * L.n();
+    if (hipMemcpy(host + off, L.w, b, hipMemcpyDeviceToHost) ||
+        hipMemcpy(host + count + off, L.m, b, hipMemcpyDeviceToHost) ||
+        hipMemcpy(host + 2 * count + off, L.v, b, hipMemcpyDeviceToHost))
+      return VIE_EDEVICE;
+    off += L.n();
+  }
+  *step = N->step;
+  return VIE_OK;
+}
+
+int vie_net_set_state(vie_net_t N, const float* host, size_t count, int step) {
+  size_t c = 0;
+  if (!N || !host || vie_net_num_params(N, &c) || c != count) return VIE_EINVAL;
+  if (step < 0) return nfail(N, VIE_EINVAL, "negative Adam step");
+  for (size_t i = 0; i < 3 * count; ++i)
+    if (!std::isfinite(host[i])) return nfail(N, VIE_EINVAL, "state value " + std::to_string(i) + " is not finite");
+  for (size_t i = 2 * count; i < 3 * count; ++i)
+    if (host[i] < 0.f) return nfail(N, VIE_EINVAL, "negative second moment " + std::to_string(i - 2 * count));
+  size_t off = 0;
+  for (auto& L : N->L) {
+    const size_t b = sizeof(float) * L.n();
+    if (hipMemcpy(L.w, host + off, b, hipMemcpyHostToDevice) ||
+        hipMemcpy(L.m, host + count + off, b, hipMemcpyHostToDevice) ||
+        hipMemcpy(L.v, host + 2 * count + off, b, hipMemcpyHostToDevice))
+      return VIE_EDEVICE;
+    off += L.n();
+  }
+  N->step = step;
+  if (refresh_weights(N, 0, 0.f) || hipStreamSynchronize(N->stream)) return VIE_EDEVICE;
+  return VIE_OK;
+}
+
 int vie_net_apply(vie_net_t N, const vie_c128* r, const vie_c128* chi, vie_c128* z) {
   return vie_net_apply_base(N, r, nullptr, chi, z);
 }

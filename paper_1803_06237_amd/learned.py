@@ -23,6 +23,55 @@ import numpy as np
 from . import inputs, vie
 
 
+CHECKPOINT_FORMAT = "vie-unet-training-state"
+
+
+def write_checkpoint(path: str, w: np.ndarray, m: np.ndarray, v: np.ndarray, step: int, meta: Dict = None):
+    """Training checkpoint without pickling: one JSON header line (format, parameter
+    count, Adam step, caller's metadata such as grid, seeds and learning rate), then
+    the FP32 weights, Adam m and Adam v as raw little-endian float32."""
+    import json
+    n = int(np.asarray(w).size)
+    parts = [np.ascontiguousarray(a, dtype="<f4").ravel() for a in (w, m, v)]
+    if any(a.size != n for a in parts):
+        raise ValueError("weights and moments differ in size")
+    head = {"format": CHECKPOINT_FORMAT, "version": 1, "num_params": n, "step": int(step),
+            "dtype": "float32-le", "parts": ["weights", "adam_m", "adam_v"], "meta": meta or {}}
+    with open(path, "wb") as f:
+        f.write((json.dumps(head, sort_keys=True) + "\n").encode())
+        for a in parts:
+            f.write(a.tobytes())
+
+
+def read_checkpoint(path: str):
+    """(weights, m, v, step, meta) of a file written by write_checkpoint; refuses other
+    formats and files whose payload does not match the header."""
+    import json
+    with open(path, "rb") as f:
+        head = json.loads(f.readline().decode())
+        if head.get("format") != CHECKPOINT_FORMAT or head.get("version") != 1:
+            raise ValueError("not a network training checkpoint")
+        n = int(head["num_params"])
+        raw = f.read()
+    if len(raw) != 3 * 4 * n:
+        raise ValueError(f"checkpoint payload is {len(raw)} bytes, the header needs {12 * n}")
+    a = np.frombuffer(raw, dtype="<f4").astype(np.float32)
+    return a[:n].copy(), a[n:2 * n].copy(), a[2 * n:].copy(), int(head["step"]), head["meta"]
+
+
+def save_net(net: "vie.Net", path: str, meta: Dict = None):
+    """Checkpoint a network's training state (vie_net_get_state)."""
+    w, m, v, step = net.get_state()
+    write_checkpoint(path, w, m, v, step, meta)
+
+
+def load_net(net: "vie.Net", path: str) -> Dict:
+    """Restore a network's training state from a checkpoint; returns its metadata."""
+    w, m, v, step, meta = read_checkpoint(path)
+    net.set_state(w, m, v, step)
+    return meta
+
+
 def smooth_field(shape, mask: np.ndarray, rng: np.random.Generator, width: float = 3.0) -> np.ndarray:
     """Complex white noise filtered by a spatial Gaussian of `width` voxels, masked to the support."""
     from scipy.ndimage import gaussian_filter

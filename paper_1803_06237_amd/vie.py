@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.vie_net_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.vie_net_get_params.argtypes = [vp, vp, ctypes.c_size_t]
         L.vie_net_set_params.argtypes = [vp, vp, ctypes.c_size_t]
+        L.vie_net_get_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int)]
+        L.vie_net_set_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int]
         L.vie_net_apply.argtypes = [vp, vp, vp, vp]
         L.vie_net_train_step.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                          ctypes.POINTER(vp), ctypes.c_float, ctypes.POINTER(ctypes.c_double)]
@@ -457,6 +459,25 @@ class Net:
         w = np.ascontiguousarray(w, dtype=np.float32)
         if lib().vie_net_set_params(self._h, w.ctypes.data, w.size) != VIE_OK:
             raise VieError(VIE_EINVAL, "vie_net_set_params failed")
+
+    def get_state(self):
+        """Training state (vie_net_get_state): (weights, Adam m, Adam v, step)."""
+        n = self.num_params()
+        buf = np.empty(3 * n, dtype=np.float32)
+        step = ctypes.c_int()
+        if lib().vie_net_get_state(self._h, buf.ctypes.data, n, ctypes.byref(step)) != VIE_OK:
+            raise VieError(VIE_EDEVICE, "vie_net_get_state failed")
+        return buf[:n].copy(), buf[n:2 * n].copy(), buf[2 * n:].copy(), step.value
+
+    def set_state(self, w: np.ndarray, m: np.ndarray, v: np.ndarray, step: int):
+        """Restore a training state (vie_net_set_state)."""
+        n = self.num_params()
+        buf = np.concatenate([np.asarray(a, dtype=np.float32).ravel() for a in (w, m, v)])
+        if buf.size != 3 * n:
+            raise VieError(VIE_EINVAL, "state of the wrong size")
+        code = lib().vie_net_set_state(self._h, buf.ctypes.data, n, int(step))
+        if code != VIE_OK:
+            raise VieError(code, (lib().vie_net_last_error(self._h) or b"").decode())
 
     def get_grads(self) -> np.ndarray:
         """FP32 weight gradients of the last train_step (vie_net_get_grads)."""
